@@ -1,0 +1,260 @@
+"""FP64 CPU oracle for the multigrid pressure solve (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The product library never calls it, and
+it shares no code with the HIP path: the C source here is compiled by gcc into
+``oracle/_liboracle.so`` and wrapped with ctypes over numpy arrays.
+
+Every routine follows a passage of arXiv 2401.06755 (cited in the C source):
+the filter notation f(C; w) of Sec. 2.2.2 over halo-padded tensors (Sec. 2.3.3),
+the variable-coefficient identity Eq. (k-T) of Sec. 2.2.4, and the sawtooth
+multigrid (U-Net) of Sec. 2.4 / Fig. multi-grid.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = [os.path.join(_HERE, "nn4mg_oracle.c"), os.path.join(_HERE, "step_oracle.c")]
+_LIB_PATH = os.path.join(_HERE, "_liboracle.so")
+
+BC_DIRICHLET0, BC_NEUMANN0, BC_PERIODIC = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FP contraction: plain IEEE order)."""
+    srcs = [s for s in _SRC if os.path.exists(s)]
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-shared", "-fPIC",
+               "-o", _LIB_PATH + ".tmp", *srcs, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        i, d, vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        sig = {
+            "or_pad": (None, [dp, i, i, i, ip, i, dp]),
+            "or_q1_filter": (None, [d, dp]),
+            "or_filter_apply": (None, [dp, i, i, i, dp, dp]),
+            "or_apply": (None, [i, i, i, d, ip, dp, dp, dp]),
+            "or_diag": (None, [i, i, i, d, ip, dp, dp]),
+            "or_residual": (None, [i, i, i, d, ip, dp, dp, dp, dp]),
+            "or_jacobi": (None, [i, i, i, d, ip, dp, dp, dp, d, i]),
+            "or_restrict": (None, [i, i, i, dp, dp]),
+            "or_prolong": (None, [i, i, i, ip, dp, dp]),
+            "or_coarsen_k": (None, [i, i, i, dp, dp, i]),
+            "or_dense": (None, [i, i, i, d, ip, dp, dp]),
+            "or_cholesky": (i, [i, dp]),
+            "or_chol_solve": (None, [i, dp, dp, dp]),
+            "or_num_levels": (i, [i, i, i, i]),
+            "or_setup": (vp, [i, i, i, d, ip, dp, d, i, i, i]),
+            "or_free": (None, [vp]),
+            "or_levels": (i, [vp]),
+            "or_coarse_n": (i, [vp]),
+            "or_level_k": (None, [vp, i, dp]),
+            "or_vcycle": (None, [vp, dp, dp]),
+            "or_solve": (i, [vp, dp, dp, d, i, i, dp, ip]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        if hasattr(L, "or_step"):
+            _declare_step(L)
+        _lib = L
+    return _lib
+
+
+def _declare_step(L):
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.or_step.restype = ctypes.c_int
+    L.or_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_void_p]
+
+
+def _d(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _bc(bc):
+    arr = (ctypes.c_int * 6)(*[int(v) for v in bc])
+    return arr
+
+
+def _shape(a: np.ndarray):
+    """Arrays are (nz, ny, nx) in C order, i.e. x fastest."""
+    nz, ny, nx = a.shape
+    return nx, ny, nz
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def pad(u, bc, coef=False):
+    u = _f64(u)
+    nx, ny, nz = _shape(u)
+    out = np.empty((nz + 2, ny + 2, nx + 2))
+    lib().or_pad(_d(u), nx, ny, nz, _bc(bc), int(coef), _d(out))
+    return out
+
+
+def q1_filter(h):
+    w = np.empty(27)
+    lib().or_q1_filter(float(h), _d(w))
+    return w.reshape(3, 3, 3)  # [c][b][a] = (z, y, x)
+
+
+def filter_apply(up, w):
+    up = _f64(up)
+    w = _f64(w).reshape(27)
+    nz, ny, nx = up.shape[0] - 2, up.shape[1] - 2, up.shape[2] - 2
+    out = np.empty((nz, ny, nx))
+    lib().or_filter_apply(_d(up), nx, ny, nz, _d(w), _d(out))
+    return out
+
+
+def apply(x, h, bc, k=None):
+    x = _f64(x)
+    nx, ny, nz = _shape(x)
+    y = np.empty_like(x)
+    kk = _f64(k) if k is not None else None
+    lib().or_apply(nx, ny, nz, float(h), _bc(bc), _d(kk) if kk is not None else None, _d(x), _d(y))
+    return y
+
+
+def diag(shape_xyz, h, bc, k=None):
+    nx, ny, nz = shape_xyz
+    d = np.empty((nz, ny, nx))
+    kk = _f64(k) if k is not None else None
+    lib().or_diag(nx, ny, nz, float(h), _bc(bc), _d(kk) if kk is not None else None, _d(d))
+    return d
+
+
+def residual(b, x, h, bc, k=None):
+    b, x = _f64(b), _f64(x)
+    nx, ny, nz = _shape(x)
+    r = np.empty_like(x)
+    kk = _f64(k) if k is not None else None
+    lib().or_residual(nx, ny, nz, float(h), _bc(bc), _d(kk) if kk is not None else None, _d(b), _d(x), _d(r))
+    return r
+
+
+def jacobi(b, y, h, bc, k=None, omega=2.0 / 3.0, nsweeps=1):
+    b = _f64(b)
+    y = _f64(y).copy()
+    nx, ny, nz = _shape(y)
+    kk = _f64(k) if k is not None else None
+    lib().or_jacobi(nx, ny, nz, float(h), _bc(bc), _d(kk) if kk is not None else None, _d(b), _d(y), float(omega),
+                    int(nsweeps))
+    return y
+
+
+def restrict(r):
+    r = _f64(r)
+    nx, ny, nz = _shape(r)
+    rc = np.empty((nz // 2, ny // 2, nx // 2))
+    lib().or_restrict(nx, ny, nz, _d(r), _d(rc))
+    return rc
+
+
+def prolong(ec, bc):
+    ec = _f64(ec)
+    cx, cy, cz = _shape(ec)
+    ef = np.empty((2 * cz, 2 * cy, 2 * cx))
+    lib().or_prolong(cx, cy, cz, _bc(bc), _d(ec), _d(ef))
+    return ef
+
+
+def coarsen_k(k, harmonic=False):
+    k = _f64(k)
+    nx, ny, nz = _shape(k)
+    kc = np.empty((nz // 2, ny // 2, nx // 2))
+    lib().or_coarsen_k(nx, ny, nz, _d(k), _d(kc), int(harmonic))
+    return kc
+
+
+def dense(shape_xyz, h, bc, k=None):
+    nx, ny, nz = shape_xyz
+    n = nx * ny * nz
+    A = np.empty((n, n))
+    kk = _f64(k) if k is not None else None
+    lib().or_dense(nx, ny, nz, float(h), _bc(bc), _d(kk) if kk is not None else None, _d(A))
+    return A
+
+
+def cholesky(A):
+    L = _f64(A).copy()
+    rc = lib().or_cholesky(L.shape[0], _d(L))
+    if rc != 0:
+        raise np.linalg.LinAlgError("not positive definite")
+    return L
+
+
+def chol_solve(L, b):
+    L, b = _f64(L), _f64(b)
+    x = np.empty_like(b)
+    lib().or_chol_solve(L.shape[0], _d(L), _d(b), _d(x))
+    return x
+
+
+def num_levels(nx, ny, nz, min_coarse=4):
+    return lib().or_num_levels(nx, ny, nz, min_coarse)
+
+
+class Hierarchy:
+    """Level chain + coarsest Cholesky factor; mirrors nn4mg_setup's meaning."""
+
+    def __init__(self, shape_xyz, h, bc, k=None, omega=2.0 / 3.0, nu_post=2, min_coarse=4, harmonic=False):
+        nx, ny, nz = shape_xyz
+        self.shape = (nz, ny, nx)
+        self._k = _f64(k) if k is not None else None  # kept alive: level 0 is referenced
+        self._ptr = lib().or_setup(nx, ny, nz, float(h), _bc(bc),
+                                   _d(self._k) if self._k is not None else None, float(omega), int(nu_post),
+                                   int(min_coarse), int(harmonic))
+        if not self._ptr:
+            raise ValueError("oracle setup rejected the configuration")
+        self.levels = lib().or_levels(self._ptr)
+        self.coarse_n = lib().or_coarse_n(self._ptr)
+
+    def level_k(self, l):
+        nz, ny, nx = self.shape
+        out = np.empty((nz >> l, ny >> l, nx >> l))
+        lib().or_level_k(self._ptr, l, _d(out))
+        return out
+
+    def vcycle(self, x, b):
+        x = _f64(x).copy()
+        lib().or_vcycle(self._ptr, _d(x), _d(_f64(b)))
+        return x
+
+    def solve(self, b, x0=None, rtol=1e-8, max_cycles=100, fixed=False):
+        b = _f64(b)
+        x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+        hist = np.zeros(max_cycles + 1)
+        cyc = ctypes.c_int(0)
+        st = lib().or_solve(self._ptr, _d(b), _d(x), float(rtol), int(max_cycles), int(fixed), _d(hist),
+                            ctypes.byref(cyc))
+        return x, hist[: cyc.value + 1].copy(), st
+
+    def __del__(self):
+        p = getattr(self, "_ptr", None)
+        if p:
+            lib().or_free(p)
+            self._ptr = None
