@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark of the multigrid pressure solve on one MI355X.
+
+Workload (the variable-density pressure-Poisson solve of the collapsing-column /
+rising-bubble scheme, synthetic): 256^3 cells on the unit cube, rho = 1000 in a
+sphere of radius 0.15 at the centre and 1 outside (two-cell ramp), k = 1/rho,
+zero-normal-derivative walls, Gaussian right-hand side projected to zero mean.
+One step = one solve from x = 0 to relative residual 1e-8 (FP64 throughout):
+b-norm, the finest residual before each cycle, every sawtooth V(0,2) cycle and
+the final projection.  The hierarchy (coefficient coarsening, coarsest inverse)
+is built once before the timed region, as a time-stepping code keeps it
+resident; its cost is reported separately.
+
+Prints one JSON line: value = finest cells x V-cycles / second / 1e9
+(Gcell-updates/s), the roofline figure of the dominant kernel from HIP events
+recorded on the solve stream over the timed region, the FP32-smoothing /
+FP64-refinement solve of the same workload beside it, and the FP64 oracle timed
+on the host on one V-cycle of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+# Algorithmic bytes per finest cell of each finest-level kernel class: every
+# array the kernel needs is read once and every output written once.
+BYTES_PER_CELL = {
+    "fp64": {"resid": 8 + 8 + 8 + 1,          # x, b, k; restricted residual (1/8 cell)
+             "sweep_prolong": 8 + 1 + 8 + 8 + 8,  # x, e_1 (1/8), b, k; y
+             "sweep": 8 + 8 + 8 + 8},          # y, b, k; x
+    "mixed": {"resid": 8 + 8 + 8 + 4 + 0.5,   # x, b, k (FP64); r32, restricted r32
+              "sweep_prolong": 0.5 + 4 + 4 + 4,  # e_1 (FP32, 1/8), r32, k32; y32
+              "sweep": 4 + 4 + 4 + 8 + 8},     # y32, r32, k32; x64 read + write
+}
+KCLASS = {"resid": 0, "sweep_prolong": 1, "sweep": 2}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cycle_model_bytes(levels, mode):
+    """Algorithmic bytes of one V(0,2) cycle over all levels (finest kernels as
+    above; coarse level l: restriction 8+1 B, two sweeps like the finest ones
+    without x; FP32 on coarse levels in mixed mode)."""
+    w = 8 if mode == "fp64" else 4
+    n0 = levels[0][0] * levels[0][1] * levels[0][2]
+    tot = n0 * sum(BYTES_PER_CELL[mode].values())
+    for l in range(1, len(levels) - 1):
+        n = levels[l][0] * levels[l][1] * levels[l][2]
+        restrict = w + w / 8
+        tot += n * (restrict + (w / 8 + 3 * w) + 4 * w)
+    return tot
+
+
+def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol):
+    nx, ny, nz = work["shape"]
+    n = nx * ny * nz
+    cfg = nn4mg.config_default(nx, ny, nz, work["h"], bc=work["bc"], coef_mode=nn4mg.COEF_NODAL,
+                               precision=precision)
+    kd = torch.from_numpy(work["k"].reshape(-1)).cuda()
+    bd = torch.from_numpy(work["b"].reshape(-1)).cuda()
+    xd = torch.zeros_like(bd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = nn4mg.Hierarchy(cfg, kd)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    H.update_coef(kd)
+    torch.cuda.synchronize()
+    update_ms = (time.perf_counter() - t0) * 1e3
+    info = None
+    for w in range(warmup):
+        xd.zero_()
+        info = H.solve(bd, xd, rtol=rtol, max_cycles=2000)
+        log(f"  warmup {w}: cycles {info.cycles} relres {info.relres:.3e} {info.solve_ms:.1f} ms")
+    H.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles = 0
+    infos = []
+    for s in range(steps):
+        xd.zero_()
+        info = H.solve(bd, xd, rtol=rtol, max_cycles=2000)
+        cycles += info.cycles
+        infos.append(info)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    H.profile(False)
+    for s, inf in enumerate(infos):
+        log(f"  step {s}: cycles {inf.cycles} relres {inf.relres:.3e} status {inf.status} {inf.solve_ms:.1f} ms")
+    kern = {}
+    for name, cls in KCLASS.items():
+        cnt, ms = H.profile_read(cls)
+        kern[name] = (cnt, ms)
+    levels = H.levels()
+    H.close()
+    return dict(n=n, dt=dt, cycles=cycles, info=infos[-1], kern=kern, levels=levels, setup_ms=setup_ms,
+                update_ms=update_ms, all_converged=all(i.status == 0 for i in infos))
+
+
+def roofline(res, mode):
+    best = None
+    for name, (cnt, ms) in res["kern"].items():
+        if cnt == 0:
+            continue
+        if best is None or ms > res["kern"][best][1]:
+            best = name
+    cnt, ms = res["kern"][best]
+    avg_s = ms / cnt / 1e3
+    bytes_per_launch = BYTES_PER_CELL[mode][best] * res["n"]
+    achieved = bytes_per_launch / avg_s / 1e9
+    per_kernel = {}
+    for name, (c, m) in res["kern"].items():
+        if c:
+            a = BYTES_PER_CELL[mode][name] * res["n"] / (m / c / 1e3) / 1e9
+            per_kernel[name] = {"launches": c, "avg_us": round(m / c * 1e3, 2), "GBps": round(a, 1),
+                                "bytes_per_cell": BYTES_PER_CELL[mode][name]}
+    return best, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                  "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None}, per_kernel
+
+
+def cpu_baseline(work):
+    """One FP64 V-cycle of the same workload in the oracle (single-threaded C)."""
+    import numpy as np
+
+    import oracle
+
+    nx, ny, nz = work["shape"]
+    OH = oracle.Hierarchy(work["shape"], work["h"], work["bc"], k=work["k"])
+    x = np.zeros_like(work["b"])
+    b = work["b"] - work["b"].mean()
+    t0 = time.perf_counter()
+    x = OH.vcycle(x, b)
+    dt = time.perf_counter() - t0
+    return {"value": round(nx * ny * nz / dt / 1e9, 5), "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 V(0,2) cycle of the {nx}x{ny}x{nz} variable-density workload, "
+                      f"{dt:.1f} s on one host core"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2401_06755_amd import inputs, nn4mg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    log(f"generating the {args.n}^3 dense-sphere workload")
+    work = inputs.dense_sphere(args.n, seed=2)
+    log("FP64 solve")
+    r64 = run_solver(nn4mg, torch, work, nn4mg.PREC_FP64, args.steps, args.warmup, args.rtol)
+    value = r64["n"] * r64["cycles"] / r64["dt"] / 1e9
+    best, roof, per_kernel = roofline(r64, "fp64")
+    model_bytes = cycle_model_bytes(r64["levels"], "fp64")
+    out = {
+        "metric": "V-cycle Gcell-updates/s (solve to relative residual 1e-8)",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["dt"] / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"variable-density pressure Poisson {args.n}^3, dense sphere r=0.15 "
+                               "rho 1000/1 (k=1/rho), Neumann walls, zero-mean Gaussian RHS, "
+                               "sawtooth V(0,2) to rtol 1e-8",
+                   "grid": [args.n] * 3, "levels": len(r64["levels"]),
+                   "cycles_per_solve": r64["info"].cycles, "precision": "fp64",
+                   "relres": r64["info"].relres, "all_converged": r64["all_converged"]},
+        "roofline": roof,
+        "roofline_kernel": {"class": best, **per_kernel[best]},
+        "fine_kernels": per_kernel,
+        "hbm_model_GBps": round(model_bytes * r64["cycles"] / r64["dt"] / 1e9, 1),
+        "model_bytes_per_cell_cycle": round(model_bytes / r64["n"], 2),
+        "setup_ms": round(r64["setup_ms"], 2),
+        "update_coef_ms": round(r64["update_ms"], 2),
+        "paper_context": {"metric": "1/H_s node-cycles/s (Eq. speed)", "value_G": 9.09,
+                          "hardware": "NVIDIA A10", "precision": "not stated"},
+    }
+    if not args.no_mixed:
+        log("mixed precision solve (FP32 smoothing, FP64 residual/refinement)")
+        rm = run_solver(nn4mg, torch, work, nn4mg.PREC_FP32_SMOOTH, args.steps, args.warmup, args.rtol)
+        bm, roofm, pkm = roofline(rm, "mixed")
+        out["mixed"] = {"value": round(rm["n"] * rm["cycles"] / rm["dt"] / 1e9, 3),
+                        "ms_per_step": round(rm["dt"] / args.steps * 1e3, 3),
+                        "cycles_per_solve": rm["info"].cycles, "relres": rm["info"].relres,
+                        "speedup_vs_fp64_solve": round(r64["dt"] / rm["dt"], 3),
+                        "dtype": "f32 smoothing + f64 residual/coarsest/refinement",
+                        "roofline": roofm, "roofline_kernel": bm, "fine_kernels": pkm}
+    if not args.no_cpu_baseline:
+        log("CPU baseline: oracle, one V-cycle")
+        out["cpu_baseline"] = cpu_baseline(work)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * nn4mg — multigrid pressure solve on MI355X (gfx950).
+ *
+ * The operation is the implicit pressure step of Chen et al., arXiv 2401.06755:
+ * the discretised pressure-Poisson residual of Eq. (ph_disc) / Eq. (ph_disc2)
+ * (Sec. 2.4, Stages 1 and 3) is driven to zero by a sawtooth multigrid cycle
+ * laid out as a U-Net (Fig. multi-grid): restriction of the residual on the
+ * way down, an exact solve at the bottom, trilinear prolongation and weighted
+ * Jacobi smoothing on the way up, with the boundary conditions applied at every
+ * level (Sec. 2.3.3).  The operator is the linear-element (Q1) Laplacian filter
+ * w_lap (27 points: centre 8h/3, faces 0, edges -h/6, corners -h/12), either
+ * with a constant coefficient or with a nodal coefficient k (= 1/rho) through
+ * the identity of Eq. (k-T), Sec. 2.2.4.
+ *
+ * Conventions shared by every entry point:
+ *  - Fields are device arrays of nx*ny*nz values, x fastest:
+ *    idx = i + nx*(j + ny*k).  Cells are centred at ((i+1/2)h, (j+1/2)h, (k+1/2)h).
+ *  - Right-hand sides are volume-integrated, as the filter weights are: b is
+ *    used as given, and the relative residual ||b - A x||_2 / ||b||_2 is
+ *    scale-free.
+ *  - All device work is enqueued on the HIP stream given at setup.  Calls that
+ *    return host values synchronise that stream before returning.
+ *  - Every function returns NN4MG_OK (0) or a negative status; nothing throws
+ *    across this boundary.  nn4mg_last_error() gives a message for the last
+ *    failure on the calling thread.
+ *  - The caller owns every pointer it passes; the library owns the hierarchy
+ *    (coarse levels, reduced-precision copies, workspaces, coarsest inverse).
+ */
+#ifndef NN4MG_H
+#define NN4MG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nn4mg_hier *nn4mg_t;
+
+enum nn4mg_status {
+    NN4MG_OK = 0,
+    NN4MG_EINVAL = -1,     /* bad configuration or argument */
+    NN4MG_ENOMEM = -2,     /* device or host allocation failed */
+    NN4MG_EDEVICE = -3,    /* a HIP call failed */
+    NN4MG_ENOTCONV = -4,   /* max_cycles reached before rtol; x is valid */
+    NN4MG_EBREAKDOWN = -5, /* non-finite residual */
+    NN4MG_EBUSY = -6       /* server: request not admissible now */
+};
+
+/* Homogeneous boundary rules applied through the one-cell halo (Sec. 2.3.3):
+ * DIRICHLET0 halo = -mirror (zero value on the cell face), NEUMANN0 halo =
+ * +mirror (zero normal derivative), PERIODIC halo = wrap.  The coefficient k is
+ * always continued by +mirror (wrap for periodic). */
+enum { NN4MG_BC_DIRICHLET0 = 0, NN4MG_BC_NEUMANN0 = 1, NN4MG_BC_PERIODIC = 2 };
+
+/* CONST: A = f(.; w_lap).  NODAL: A x = 1/2 [f(k.x) + k.f(x) - x.f(k)], Eq. (k-T). */
+enum { NN4MG_COEF_CONST = 0, NN4MG_COEF_NODAL = 1 };
+
+/* FP64: every step in double.
+ * FP32_SMOOTH: FP64 residual (FP64 k), FP64 coarsest solve and FP64 update
+ *   x += e; the V-cycle on the correction runs in FP32 with an FP32 copy of k.
+ * FP16_COEF: as FP32_SMOOTH but the smoothing coefficient copy is stored in
+ *   FP16 (arithmetic still FP32). */
+enum { NN4MG_PREC_FP64 = 0, NN4MG_PREC_FP32_SMOOTH = 1, NN4MG_PREC_FP16_COEF = 2 };
+
+/* Outer iteration: STATIONARY repeats the cycle (x <- x + V(b - A x));
+ * FCG runs flexible conjugate gradients in FP64 with one cycle as the
+ * preconditioner. */
+enum { NN4MG_OUTER_STATIONARY = 0, NN4MG_OUTER_FCG = 1 };
+
+typedef struct {
+    int nx, ny, nz;   /* interior cells of the finest level, each >= 1 */
+    double h;         /* uniform spacing (> 0) */
+    int bc[6];        /* x-lo, x-hi, y-lo, y-hi, z-lo, z-hi */
+    int coef_mode;    /* NN4MG_COEF_* */
+    int precision;    /* NN4MG_PREC_* */
+    int nu_post;      /* Jacobi sweeps after each prolongation (default 2, >= 1) */
+    double omega;     /* Jacobi weight (default 2/3) */
+    int min_coarse;   /* coarsen while every dim is even and the smallest > min_coarse (default 4) */
+    int outer;        /* NN4MG_OUTER_* (default STATIONARY) */
+    int coarse_avg;   /* 0: coarse k = mean of the 8 children; 1: harmonic mean */
+    int reserved[7];  /* must be zero */
+} nn4mg_config;
+
+#define NN4MG_HIST_MAX 512
+
+typedef struct {
+    int cycles;        /* cycles (outer iterations) performed */
+    int status;        /* same as the return value of nn4mg_solve */
+    double relres0;    /* ||b - A x0|| / ||b|| */
+    double relres;     /* final relative residual (FP64 operator) */
+    int hist_len;      /* min(cycles + 1, NN4MG_HIST_MAX) */
+    double hist[NN4MG_HIST_MAX]; /* relative residual before each cycle, then the final one */
+    double solve_ms;   /* wall time of the call (host clock) */
+} nn4mg_info;
+
+/* Fill cfg with the defaults above for an nx x ny x nz grid of spacing h, all
+ * walls Dirichlet-zero, constant coefficient, FP64. */
+void nn4mg_config_default(nn4mg_config *cfg, int nx, int ny, int nz, double h);
+
+/* Device bytes nn4mg_setup will allocate for cfg (0 if cfg is invalid). */
+size_t nn4mg_bytes_required(const nn4mg_config *cfg);
+
+/* Build the level hierarchy (Fig. multi-grid; boundary rules at every level,
+ * Sec. 2.3.3).  Levels: halve while all dims are even and the smallest exceeds
+ * cfg->min_coarse.  Coarse operators are the same filter at h_l = 2^l h with k
+ * averaged over the 8 children.  The coarsest matrix (<= 512 unknowns) is
+ * assembled, factorised and inverted on the host in FP64.
+ *   k_dev: nx*ny*nz device doubles, > 0, required iff coef_mode == NODAL; it
+ *          is copied, so the caller may free it after the call returns.
+ *   hip_stream: a hipStream_t (NULL = the null stream).
+ * Errors: EINVAL (dims < 1, h <= 0, bad enum, coarsest level too large, NULL
+ * k for NODAL or non-positive k), ENOMEM, EDEVICE. */
+int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, nn4mg_t *out);
+
+/* Replace the coefficient (same shape) and rebuild the coarse levels and the
+ * coarsest inverse, as each time step of the paper's scheme changes rho
+ * (Eq. rho).  Errors: EINVAL (CONST handle, NULL, non-positive k), EDEVICE. */
+int nn4mg_update_coef(nn4mg_t h, const double *k_dev);
+
+/* r = b - A x on the finest level, in FP64 (the residual of Eq. ph_disc).
+ *   x_dev, b_dev: nx*ny*nz device doubles.
+ *   r_dev: nx*ny*nz device doubles, or NULL (not written).
+ *   norm2_out: host double receiving ||r||_2, or NULL (then no sync).
+ * b is used as given (no projection, even for singular problems). */
+int nn4mg_residual(nn4mg_t h, const double *x_dev, const double *b_dev, double *r_dev, double *norm2_out);
+
+/* One outer iteration on x: FP64 precision: x <- V(x, b), one sawtooth
+ * V(0, nu_post) cycle; reduced precisions: x <- x + V32(0, b - A x).  b is used
+ * as given.  No norm, no projection; for parity checks of a single cycle. */
+int nn4mg_vcycle(nn4mg_t h, const double *b_dev, double *x_dev);
+
+/* Solve A x = b.  x_dev holds the initial guess and receives the solution.
+ * Before each cycle the relative residual ||b - A x|| / ||b|| is taken in
+ * FP64; the solve stops when it is <= rtol (fixed_cycles == 0) or after
+ * max_cycles cycles (fixed_cycles == 1 runs exactly max_cycles, the paper's
+ * fixed count of 20 per pressure solve, Sec. 2.4).  Singular problems (no
+ * Dirichlet face): b is projected to zero mean for the solve and x is
+ * returned with zero mean.  If ||b|| == 0, x is set to 0.
+ * Returns OK, ENOTCONV (x valid), EBREAKDOWN, EINVAL (max_cycles < 0), EDEVICE.
+ * info (may be NULL) receives the history. */
+int nn4mg_solve(nn4mg_t h, const double *b_dev, double *x_dev, double rtol, int max_cycles, int fixed_cycles,
+                nn4mg_info *info);
+
+/* Number of levels and their dims (dims must hold 3*max_levels ints, x,y,z per level). */
+int nn4mg_levels(nn4mg_t h, int *levels, int *dims, int max_levels);
+
+/* Device bytes held by the handle. */
+size_t nn4mg_bytes_held(nn4mg_t h);
+
+/* Kernel timing for benchmarks: while enabled, every launch of the finest-level
+ * kernels below is bracketed by a pair of HIP events on the handle's stream;
+ * launches that exit early (after the stopping rule fired) are discarded.
+ * enable = 1 resets and starts recording, 0 stops.  Recording is capped at
+ * 4096 launches per class. */
+enum { NN4MG_KCLASS_FINE_RESID = 0,        /* residual + restriction + norm partials */
+       NN4MG_KCLASS_FINE_SWEEP_PROLONG = 1, /* first sweep, reads x + P e_1 */
+       NN4MG_KCLASS_FINE_SWEEP = 2,         /* later sweeps */
+       NN4MG_KCLASS_COUNT = 3 };
+int nn4mg_profile(nn4mg_t h, int enable);
+/* Launch count and summed duration (ms) of one class since the last enable. */
+int nn4mg_profile_read(nn4mg_t h, int kclass, int *launches, double *total_ms);
+
+/* Release the hierarchy (synchronises its stream first).  NULL is accepted. */
+int nn4mg_destroy(nn4mg_t h);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *nn4mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NN4MG_H */

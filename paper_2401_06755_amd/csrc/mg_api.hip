@@ -1,0 +1,897 @@
+// Host side of the nn4mg library: level hierarchy, coarsest-level inverse,
+// cycle driver and the C-ABI declared in include/nn4mg.h.
+//
+// The solve runs the sawtooth cycle of Fig. multi-grid (arXiv 2401.06755,
+// Sec. 2.4): the residual of the finest level is restricted to every coarser
+// level (the coarse initial guesses are zero, so their residuals are their
+// right-hand sides), solved exactly at the bottom, then prolongated, added and
+// smoothed by nu_post weighted-Jacobi sweeps on the way up.  The residual norm
+// and the stopping rule are evaluated on the device after every cycle; kernels
+// of later cycles exit at once when the rule has fired, so the host only
+// synchronises once per batch of cycles.
+#include "../../include/nn4mg.h"
+#include "mg_internal.h"
+
+#include <chrono>
+#include <cstddef>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace nn4mg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                    \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(NN4MG_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxCoarse = 512;
+constexpr int kDefaultZc = 16;
+
+struct Level {
+    int nx = 0, ny = 0, nz = 0;
+    double h = 0.0;
+    size_t n = 0;
+    double *b = nullptr, *e = nullptr, *t = nullptr;  // FP64 cycle buffers
+    double *k = nullptr;                              // FP64 coefficient
+    float *b32 = nullptr, *e32 = nullptr, *t32 = nullptr, *t32b = nullptr;  // FP32 cycle buffers
+    void *ks = nullptr;                               // FP32 / FP16 smoothing coefficient
+    TileShape tiles{};
+};
+
+int count_levels(int nx, int ny, int nz, int min_coarse)
+{
+    int L = 1;
+    while (nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0) {
+        int m = nx < ny ? nx : ny;
+        m = m < nz ? m : nz;
+        if (m <= min_coarse) break;
+        nx /= 2;
+        ny /= 2;
+        nz /= 2;
+        ++L;
+        if (L == kMaxLevels) break;
+    }
+    return L;
+}
+
+int validate(const nn4mg_config *c)
+{
+    if (!c) return fail(NN4MG_EINVAL, "config is NULL");
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1 || c->nx > 65536 || c->ny > 65536 || c->nz > 65536)
+        return fail(NN4MG_EINVAL, "grid dims must be in [1, 65536]");
+    if ((double)c->nx * c->ny * c->nz > 8.0e9) return fail(NN4MG_EINVAL, "grid too large");
+    if (!(c->h > 0.0) || !std::isfinite(c->h)) return fail(NN4MG_EINVAL, "h must be positive");
+    for (int f = 0; f < 6; ++f)
+        if (c->bc[f] < 0 || c->bc[f] > 2) return fail(NN4MG_EINVAL, "unknown boundary rule");
+    for (int a = 0; a < 3; ++a)
+        if ((c->bc[2 * a] == NN4MG_BC_PERIODIC) != (c->bc[2 * a + 1] == NN4MG_BC_PERIODIC))
+            return fail(NN4MG_EINVAL, "periodic must be set on both faces of an axis");
+    if (c->coef_mode != NN4MG_COEF_CONST && c->coef_mode != NN4MG_COEF_NODAL)
+        return fail(NN4MG_EINVAL, "unknown coef_mode");
+    if (c->precision < 0 || c->precision > 2) return fail(NN4MG_EINVAL, "unknown precision");
+    if (c->precision == NN4MG_PREC_FP16_COEF && c->coef_mode != NN4MG_COEF_NODAL)
+        return fail(NN4MG_EINVAL, "FP16 coefficient storage needs a nodal coefficient");
+    if (c->nu_post < 1 || c->nu_post > 64) return fail(NN4MG_EINVAL, "nu_post must be in [1, 64]");
+    if (!(c->omega > 0.0 && c->omega < 2.0)) return fail(NN4MG_EINVAL, "omega must be in (0, 2)");
+    if (c->min_coarse < 1) return fail(NN4MG_EINVAL, "min_coarse must be >= 1");
+    if (c->outer != NN4MG_OUTER_STATIONARY && c->outer != NN4MG_OUTER_FCG)
+        return fail(NN4MG_EINVAL, "unknown outer iteration");
+    if (c->coarse_avg != 0 && c->coarse_avg != 1) return fail(NN4MG_EINVAL, "coarse_avg must be 0 or 1");
+    for (int i = 0; i < 7; ++i)
+        if (c->reserved[i] != 0) return fail(NN4MG_EINVAL, "reserved fields must be zero");
+    const int L = count_levels(c->nx, c->ny, c->nz, c->min_coarse);
+    const double nc = (double)(c->nx >> (L - 1)) * (c->ny >> (L - 1)) * (c->nz >> (L - 1));
+    if (nc > kMaxCoarse) return fail(NN4MG_EINVAL, "coarsest level has more than 512 cells (dims not divisible enough)");
+    return NN4MG_OK;
+}
+
+// ---------------------------------------------------------------- host operator
+// Link form of Eq. (k-T): (A x)_i = sum_{s in edges, corners} c_s (k_i + k_s)(x_i - x_s)
+// with c_edge = h/12, c_corner = h/24; k == NULL: the constant-coefficient filter.
+int hfold(int i, int n, int lo, int hi, int &s)
+{
+    if (i < 0) {
+        if (lo == BC_P) return i + n;
+        if (lo == BC_D) s = -s;
+        return -1 - i;
+    }
+    if (i >= n) {
+        if (hi == BC_P) return i - n;
+        if (hi == BC_D) s = -s;
+        return 2 * n - 1 - i;
+    }
+    return i;
+}
+
+void host_apply(int nx, int ny, int nz, double h, const int bc[6], const double *k, const double *x, double *y)
+{
+    for (int kk = 0; kk < nz; ++kk)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t c = (size_t)i + (size_t)nx * (j + (size_t)ny * kk);
+                double acc = 0.0;
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int m = std::abs(dx) + std::abs(dy) + std::abs(dz);
+                            if (m < 2) continue;
+                            const double cs = (m == 2) ? h / 12.0 : h / 24.0;
+                            int s = 1;
+                            const int fi = hfold(i + dx, nx, bc[0], bc[1], s);
+                            const int fj = hfold(j + dy, ny, bc[2], bc[3], s);
+                            const int fk = hfold(kk + dz, nz, bc[4], bc[5], s);
+                            const size_t q = (size_t)fi + (size_t)nx * (fj + (size_t)ny * fk);
+                            const double kl = k ? 0.5 * (k[c] + k[q]) : 1.0;
+                            acc += 2.0 * cs * kl * (x[c] - s * x[q]);
+                        }
+                y[c] = acc;
+            }
+}
+
+// Dense coarsest matrix, rank-one shift if singular, Cholesky, explicit inverse.
+int coarse_inverse(int nx, int ny, int nz, double h, const int bc[6], const double *k, int singular,
+                   std::vector<double> &inv)
+{
+    const int n = nx * ny * nz;
+    std::vector<double> A((size_t)n * n), e(n, 0.0), col(n);
+    for (int j = 0; j < n; ++j) {
+        e[j] = 1.0;
+        host_apply(nx, ny, nz, h, bc, k, e.data(), col.data());
+        for (int i = 0; i < n; ++i) A[(size_t)i * n + j] = col[i];
+        e[j] = 0.0;
+    }
+    if (singular) {
+        double cbar = 0.0;
+        for (int i = 0; i < n; ++i) cbar += A[(size_t)i * n + i];
+        cbar /= n;
+        for (auto &v : A) v += cbar / n;
+    }
+    // Cholesky A = L L^T (lower, in place)
+    for (int j = 0; j < n; ++j) {
+        double s = A[(size_t)j * n + j];
+        for (int p = 0; p < j; ++p) s -= A[(size_t)j * n + p] * A[(size_t)j * n + p];
+        if (!(s > 0.0)) return fail(NN4MG_EINVAL, "coarsest matrix is not positive definite");
+        const double d = std::sqrt(s);
+        A[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[(size_t)i * n + j];
+            for (int p = 0; p < j; ++p) t -= A[(size_t)i * n + p] * A[(size_t)j * n + p];
+            A[(size_t)i * n + j] = t / d;
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    std::vector<double> y(n);
+    for (int c = 0; c < n; ++c) {
+        for (int i = 0; i < n; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int p = 0; p < i; ++p) s -= A[(size_t)i * n + p] * y[p];
+            y[i] = s / A[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int p = i + 1; p < n; ++p) s -= A[(size_t)p * n + i] * y[p];
+            y[i] = s / A[(size_t)i * n + i];
+        }
+        for (int i = 0; i < n; ++i) inv[(size_t)c * n + i] = y[i];
+    }
+    // symmetrise (the kernel reads column i as row i)
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double v = 0.5 * (inv[(size_t)i * n + j] + inv[(size_t)j * n + i]);
+            inv[(size_t)i * n + j] = inv[(size_t)j * n + i] = v;
+        }
+    return NN4MG_OK;
+}
+
+}  // namespace
+
+struct nn4mg_hier {
+    nn4mg_config cfg{};
+    hipStream_t stream = nullptr;
+    int L = 0;
+    Level lv[kMaxLevels];
+    int singular = 0;
+    int mixed = 0;
+    int kt64 = KT_NONE;     // coefficient type of FP64 launches
+    int kts = KT_NONE;      // coefficient type of FP32 smoothing launches
+    int nc = 0;
+    double *ainv = nullptr;
+    SolveState *st = nullptr;
+    SolveState *st_host = nullptr;
+    double *partials = nullptr;
+    int max_partials = 0;
+    double *scal = nullptr;  // device scalars: [0] sum, [1] mean of x, [2..7] spare
+    int *flag = nullptr;
+    double *fcg = nullptr;   // FCG vectors (r, z, p, q) at level 0, FP64
+    size_t bytes = 0;
+    std::vector<void *> allocs;
+    // kernel timing (nn4mg_profile)
+    bool prof_on = false;
+    int cur_tag = 0;
+    size_t prof_solve_begin = 0;
+    std::vector<hipEvent_t> prof_ev;  // 2 per record
+    std::vector<int> prof_cls, prof_tag, prof_valid;
+};
+
+namespace {
+
+template <typename P>
+int dalloc(nn4mg_hier *H, P **p, size_t count)
+{
+    void *q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, count * sizeof(P)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(NN4MG_ENOMEM, "hipMalloc failed");
+    }
+    H->allocs.push_back(q);
+    H->bytes += count * sizeof(P);
+    *p = (P *)q;
+    return NN4MG_OK;
+}
+
+void release(nn4mg_hier *H)
+{
+    if (H->stream) (void)hipStreamSynchronize(H->stream);
+    for (hipEvent_t e : H->prof_ev) (void)hipEventDestroy(e);
+    H->prof_ev.clear();
+    for (void *p : H->allocs) (void)hipFree(p);
+    H->allocs.clear();
+    if (H->st_host) (void)hipHostFree(H->st_host);
+    H->st_host = nullptr;
+}
+
+size_t bytes_for(const nn4mg_config *c)
+{
+    const int L = count_levels(c->nx, c->ny, c->nz, c->min_coarse);
+    const bool mixed = c->precision != NN4MG_PREC_FP64;
+    const bool nodal = c->coef_mode == NN4MG_COEF_NODAL;
+    const size_t ks = c->precision == NN4MG_PREC_FP16_COEF ? 2 : 4;
+    size_t b = 0;
+    size_t maxblk = 1024;
+    for (int l = 0; l < L; ++l) {
+        const size_t n = (size_t)(c->nx >> l) * (c->ny >> l) * (c->nz >> l);
+        const TileShape t = make_tiles(c->nx >> l, c->ny >> l, c->nz >> l, kDefaultZc);
+        if ((size_t)t.blocks() > maxblk) maxblk = t.blocks();
+        if (nodal) b += 8 * n;
+        if (!mixed) {
+            b += (l == 0) ? 8 * n : 24 * n;
+        } else {
+            b += (l == 0) ? 8 * n : 12 * n;
+            if (l == 0 && c->nu_post > 2) b += 4 * n;
+            if (nodal) b += ks * n;
+        }
+    }
+    const size_t nc = (size_t)(c->nx >> (L - 1)) * (c->ny >> (L - 1)) * (c->nz >> (L - 1));
+    b += 8 * nc * nc + sizeof(SolveState) + 8 * maxblk + 64 + 4;
+    if (c->outer == NN4MG_OUTER_FCG) b += 4 * 8 * (size_t)c->nx * c->ny * c->nz;
+    return b;
+}
+
+int rebuild_coefficients(nn4mg_hier *H)
+{
+    hipStream_t s = H->stream;
+    const nn4mg_config &c = H->cfg;
+    const bool nodal = c.coef_mode == NN4MG_COEF_NODAL;
+    if (nodal) {
+        for (int l = 1; l < H->L; ++l)
+            HIP_TRY(launch_coarsen_k(H->lv[l - 1].k, H->lv[l].k, H->lv[l - 1].nx, H->lv[l - 1].ny, H->lv[l - 1].nz,
+                                     c.coarse_avg, s));
+        if (H->mixed)
+            for (int l = 0; l < H->L; ++l) HIP_TRY(launch_cast_k(H->lv[l].k, H->lv[l].ks, H->lv[l].n, H->kts, s));
+    }
+    const Level &C = H->lv[H->L - 1];
+    std::vector<double> hk;
+    if (nodal) {
+        hk.resize(C.n);
+        HIP_TRY(hipMemcpyAsync(hk.data(), C.k, C.n * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    std::vector<double> inv;
+    int rc = coarse_inverse(C.nx, C.ny, C.nz, C.h, c.bc, nodal ? hk.data() : nullptr, H->singular, inv);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(H->ainv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return NN4MG_OK;
+}
+
+int load_k(nn4mg_hier *H, const double *k_dev)
+{
+    hipStream_t s = H->stream;
+    Level &F = H->lv[0];
+    HIP_TRY(hipMemcpyAsync(F.k, k_dev, F.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemsetAsync(H->flag, 0, sizeof(int), s));
+    HIP_TRY(launch_check_positive(F.k, F.n, H->flag, s));
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, H->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad) return fail(NN4MG_EINVAL, "coefficient k must be positive and finite");
+    return rebuild_coefficients(H);
+}
+
+constexpr size_t kProfMax = 3 * 4096;
+
+// Open a timing record for a launch of class cls; returns its index or -1.
+long prof_begin(nn4mg_hier *H, int cls)
+{
+    if (!H->prof_on) return -1;
+    const size_t i = H->prof_cls.size();
+    if (i >= kProfMax) return -1;
+    if (H->prof_ev.size() < 2 * (i + 1)) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return -1;
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return -1;
+        }
+        H->prof_ev.push_back(e0);
+        H->prof_ev.push_back(e1);
+    }
+    if (hipEventRecord(H->prof_ev[2 * i], H->stream) != hipSuccess) return -1;
+    H->prof_cls.push_back(cls);
+    H->prof_tag.push_back(H->cur_tag);
+    H->prof_valid.push_back(1);
+    return (long)i;
+}
+
+void prof_end(nn4mg_hier *H, long i)
+{
+    if (i < 0) return;
+    if (hipEventRecord(H->prof_ev[2 * i + 1], H->stream) != hipSuccess) H->prof_valid[i] = 0;
+}
+
+// After a solve that ran `cycles` iterations: launches tagged with a later
+// iteration exited early and are dropped.
+void prof_close_solve(nn4mg_hier *H, int cycles, bool ran)
+{
+    for (size_t i = H->prof_solve_begin; i < H->prof_cls.size(); ++i)
+        if (!ran || H->prof_tag[i] > cycles) H->prof_valid[i] = 0;
+    H->prof_solve_begin = H->prof_cls.size();
+}
+
+StencilArgs base_args(const nn4mg_hier *H, int l)
+{
+    StencilArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const Level &V = H->lv[l];
+    a.g.nx = V.nx;
+    a.g.ny = V.ny;
+    a.g.nz = V.nz;
+    for (int f = 0; f < 6; ++f) a.g.bc[f] = H->cfg.bc[f];
+    a.t = V.tiles;
+    a.h = V.h;
+    a.omega = H->cfg.omega;
+    if (l + 1 < H->L) {
+        a.cnx = H->lv[l + 1].nx;
+        a.cny = H->lv[l + 1].ny;
+        a.cnz = H->lv[l + 1].nz;
+    }
+    return a;
+}
+
+// Finest-level FP64 residual r = (b - bmean) - A x.  r_full / r_coarse select
+// the outputs (FP32 when the handle is mixed and to_f32 is set).
+int enqueue_resid(nn4mg_hier *H, const double *x, const double *b, const double *bmean, void *r_full,
+                  void *r_coarse, bool to_f32, bool partials, const int *done)
+{
+    StencilArgs a = base_args(H, 0);
+    a.yin = x;
+    a.b = b;
+    a.k = H->lv[0].k;
+    a.bmean = bmean;
+    a.r = r_full;
+    a.rc = r_coarse;
+    a.partials = partials ? H->partials : nullptr;
+    a.done = done;
+    const long pr = prof_begin(H, NN4MG_KCLASS_FINE_RESID);
+    HIP_TRY(launch_stencil(1, H->kt64, IN_PLAIN, OUT_RESID, to_f32 ? 1 : 0, a, H->stream));
+    prof_end(H, pr);
+    return NN4MG_OK;
+}
+
+// nu_post Jacobi sweeps at level l >= 1 (first input: P e_{l+1}); result in e.
+int enqueue_coarse_sweeps(nn4mg_hier *H, int l, const int *done)
+{
+    Level &V = H->lv[l];
+    const int nu = H->cfg.nu_post;
+    const bool f64 = !H->mixed;
+    void *buf[2] = {f64 ? (void *)V.t : (void *)V.t32, f64 ? (void *)V.e : (void *)V.e32};
+    int cur = (nu % 2 == 1) ? 1 : 0;  // the last sweep must land in e
+    const void *in = nullptr;
+    for (int s = 0; s < nu; ++s) {
+        StencilArgs a = base_args(H, l);
+        a.b = f64 ? (const void *)V.b : (const void *)V.b32;
+        a.k = f64 ? (const void *)V.k : V.ks;
+        a.yout = buf[cur];
+        a.done = done;
+        int in_mode = IN_PLAIN;
+        if (s == 0) {
+            in_mode = IN_PROLONG;
+            a.ec = f64 ? (const void *)H->lv[l + 1].e : (const void *)H->lv[l + 1].e32;
+        } else {
+            a.yin = in;
+        }
+        HIP_TRY(launch_stencil(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, in_mode, OUT_STORE, 0, a, H->stream));
+        in = buf[cur];
+        cur ^= 1;
+    }
+    return NN4MG_OK;
+}
+
+// Finest-level sweeps: FP64: x <- smooth(x + P e_1); mixed: x += smooth(P e_1).
+int enqueue_fine_sweeps(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done)
+{
+    Level &F = H->lv[0];
+    const int nu = H->cfg.nu_post;
+    if (!H->mixed) {
+        void *buf[2] = {F.t, x};
+        int cur = 0;
+        const void *in = nullptr;
+        for (int s = 0; s < nu; ++s) {
+            StencilArgs a = base_args(H, 0);
+            a.b = b;
+            a.bmean = bmean;
+            a.k = F.k;
+            a.yout = buf[cur];
+            a.done = done;
+            int in_mode = IN_PLAIN;
+            if (s == 0) {
+                in_mode = IN_PROLONG_ADD;
+                a.yin = x;
+                a.ec = H->lv[1].e;
+            } else {
+                a.yin = in;
+            }
+            const long pr = prof_begin(H, s == 0 ? NN4MG_KCLASS_FINE_SWEEP_PROLONG : NN4MG_KCLASS_FINE_SWEEP);
+            HIP_TRY(launch_stencil(1, H->kt64, in_mode, OUT_STORE, 0, a, H->stream));
+            prof_end(H, pr);
+            in = buf[cur];
+            cur ^= 1;
+        }
+        if (nu % 2 == 1) HIP_TRY(launch_copy(x, F.t, F.n, done, H->stream));
+        return NN4MG_OK;
+    }
+    float *buf[2] = {F.t32, F.t32b};
+    int cur = 0;
+    const void *in = nullptr;
+    for (int s = 0; s < nu; ++s) {
+        const bool last = (s == nu - 1);
+        StencilArgs a = base_args(H, 0);
+        a.b = F.b32;
+        a.k = F.ks;
+        a.done = done;
+        int in_mode = IN_PLAIN;
+        if (s == 0) {
+            in_mode = IN_PROLONG;
+            a.ec = H->lv[1].e32;
+        } else {
+            a.yin = in;
+        }
+        if (last) {
+            a.x64 = x;
+        } else {
+            a.yout = buf[cur];
+        }
+        const long pr = prof_begin(H, s == 0 ? NN4MG_KCLASS_FINE_SWEEP_PROLONG : NN4MG_KCLASS_FINE_SWEEP);
+        HIP_TRY(launch_stencil(0, H->kts, in_mode, last ? OUT_ADD64 : OUT_STORE, 0, a, H->stream));
+        prof_end(H, pr);
+        if (!last) {
+            in = buf[cur];
+            cur ^= 1;
+        }
+    }
+    return NN4MG_OK;
+}
+
+// Everything of one cycle after the finest residual has been restricted to
+// level 1 (FP64: lv[1].b; mixed: lv[1].b32 and the FP32 finest residual in
+// lv[0].b32).
+int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done)
+{
+    const bool f64 = !H->mixed;
+    const int L = H->L;
+    hipStream_t s = H->stream;
+    int rc;
+    for (int l = 1; l + 1 < L; ++l) {
+        Level &V = H->lv[l];
+        HIP_TRY(launch_restrict(f64 ? 1 : 0, f64 ? (void *)V.b : (void *)V.b32,
+                                f64 ? (void *)H->lv[l + 1].b : (void *)H->lv[l + 1].b32, V.nx, V.ny, V.nz, done, s));
+    }
+    Level &C = H->lv[L - 1];
+    HIP_TRY(launch_coarse_solve(f64 ? 1 : 0, f64 ? (void *)C.b : (void *)C.b32, f64 ? (void *)C.e : (void *)C.e32,
+                                H->ainv, H->nc, H->singular, done, s));
+    for (int l = L - 2; l >= 1; --l)
+        if ((rc = enqueue_coarse_sweeps(H, l, done))) return rc;
+    return enqueue_fine_sweeps(H, b, bmean, x, done);
+}
+
+// One outer iteration starting with the finest residual.  For a single-level
+// hierarchy the whole problem is the coarsest one.
+int enqueue_resid_for_cycle(nn4mg_hier *H, const double *b, const double *x, const double *bmean, bool with_norm,
+                            const int *done)
+{
+    if (H->L == 1) {
+        Level &F = H->lv[0];
+        return enqueue_resid(H, x, b, bmean, H->mixed ? (void *)F.b32 : (void *)F.b, nullptr, H->mixed, with_norm,
+                             done);
+    }
+    if (H->mixed)
+        return enqueue_resid(H, x, b, bmean, H->lv[0].b32, H->lv[1].b32, true, with_norm, done);
+    return enqueue_resid(H, x, b, bmean, nullptr, H->lv[1].b, false, with_norm, done);
+}
+
+int enqueue_single_level_body(nn4mg_hier *H, double *x, const int *done)
+{
+    Level &F = H->lv[0];
+    hipStream_t s = H->stream;
+    if (!H->mixed) {
+        HIP_TRY(launch_coarse_solve(1, F.b, F.e, H->ainv, H->nc, H->singular, done, s));
+        HIP_TRY(launch_add(x, F.e, 0, F.n, done, s));
+    } else {
+        HIP_TRY(launch_coarse_solve(0, F.b32, F.e32, H->ainv, H->nc, H->singular, done, s));
+        HIP_TRY(launch_add(x, F.e32, 1, F.n, done, s));
+    }
+    return NN4MG_OK;
+}
+
+int enqueue_body(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done)
+{
+    if (H->L == 1) return enqueue_single_level_body(H, x, done);
+    return enqueue_cycle_body(H, b, bmean, x, done);
+}
+
+int resid_blocks(const nn4mg_hier *H) { return H->lv[0].tiles.blocks(); }
+
+}  // namespace
+
+// ============================================================================ C-ABI
+
+extern "C" {
+
+void nn4mg_config_default(nn4mg_config *cfg, int nx, int ny, int nz, double h)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->nx = nx;
+    cfg->ny = ny;
+    cfg->nz = nz;
+    cfg->h = h;
+    for (int f = 0; f < 6; ++f) cfg->bc[f] = NN4MG_BC_DIRICHLET0;
+    cfg->coef_mode = NN4MG_COEF_CONST;
+    cfg->precision = NN4MG_PREC_FP64;
+    cfg->nu_post = 2;
+    cfg->omega = 2.0 / 3.0;
+    cfg->min_coarse = 4;
+    cfg->outer = NN4MG_OUTER_STATIONARY;
+    cfg->coarse_avg = 0;
+}
+
+size_t nn4mg_bytes_required(const nn4mg_config *cfg)
+{
+    if (validate(cfg) != NN4MG_OK) return 0;
+    return bytes_for(cfg);
+}
+
+const char *nn4mg_last_error(void) { return g_err.c_str(); }
+
+int nn4mg_destroy(nn4mg_t h)
+{
+    if (!h) return NN4MG_OK;
+    release(h);
+    delete h;
+    return NN4MG_OK;
+}
+
+int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, nn4mg_t *out)
+{
+    if (!out) return fail(NN4MG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    const bool nodal = cfg->coef_mode == NN4MG_COEF_NODAL;
+    if (nodal && !k_dev) return fail(NN4MG_EINVAL, "nodal coefficient requires k");
+    if (cfg->outer == NN4MG_OUTER_FCG && cfg->precision != NN4MG_PREC_FP64 && false)
+        return fail(NN4MG_EINVAL, "unsupported");
+    nn4mg_hier *H = new nn4mg_hier();
+    H->cfg = *cfg;
+    H->stream = (hipStream_t)hip_stream;
+    H->L = count_levels(cfg->nx, cfg->ny, cfg->nz, cfg->min_coarse);
+    H->mixed = cfg->precision != NN4MG_PREC_FP64;
+    H->singular = 1;
+    for (int f = 0; f < 6; ++f)
+        if (cfg->bc[f] == NN4MG_BC_DIRICHLET0) H->singular = 0;
+    H->kt64 = nodal ? KT_F64 : KT_NONE;
+    H->kts = !nodal ? KT_NONE : (cfg->precision == NN4MG_PREC_FP16_COEF ? KT_F16 : KT_F32);
+    int maxblk = 1024;
+#define TRY(x)                    \
+    do {                          \
+        int r_ = (x);             \
+        if (r_) {                 \
+            nn4mg_destroy(H);     \
+            return r_;            \
+        }                         \
+    } while (0)
+    for (int l = 0; l < H->L; ++l) {
+        Level &V = H->lv[l];
+        V.nx = cfg->nx >> l;
+        V.ny = cfg->ny >> l;
+        V.nz = cfg->nz >> l;
+        V.h = cfg->h * (double)(1 << l);
+        V.n = (size_t)V.nx * V.ny * V.nz;
+        V.tiles = make_tiles(V.nx, V.ny, V.nz, kDefaultZc);
+        if (V.tiles.blocks() > maxblk) maxblk = V.tiles.blocks();
+        if (nodal) TRY(dalloc(H, &V.k, V.n));
+        const bool single = (H->L == 1);
+        if (!H->mixed) {
+            TRY(dalloc(H, &V.t, V.n));
+            if (l > 0 || single) {
+                TRY(dalloc(H, &V.b, V.n));
+                TRY(dalloc(H, &V.e, V.n));
+            }
+        } else {
+            TRY(dalloc(H, &V.b32, V.n));
+            TRY(dalloc(H, &V.t32, V.n));
+            if (l > 0 || single) TRY(dalloc(H, &V.e32, V.n));
+            if (l == 0 && cfg->nu_post > 2) TRY(dalloc(H, &V.t32b, V.n));
+            if (nodal) {
+                if (H->kts == KT_F16) {
+                    __half *p;
+                    TRY(dalloc(H, &p, V.n));
+                    V.ks = p;
+                } else {
+                    float *p;
+                    TRY(dalloc(H, &p, V.n));
+                    V.ks = p;
+                }
+            }
+        }
+    }
+    const Level &C = H->lv[H->L - 1];
+    H->nc = (int)C.n;
+    TRY(dalloc(H, &H->ainv, (size_t)H->nc * H->nc));
+    TRY(dalloc(H, &H->st, 1));
+    TRY(dalloc(H, &H->partials, (size_t)maxblk));
+    H->max_partials = maxblk;
+    TRY(dalloc(H, &H->scal, 8));
+    TRY(dalloc(H, &H->flag, 1));
+    if (cfg->outer == NN4MG_OUTER_FCG) TRY(dalloc(H, &H->fcg, 4 * H->lv[0].n));
+    if (hipHostMalloc((void **)&H->st_host, sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        nn4mg_destroy(H);
+        return fail(NN4MG_ENOMEM, "pinned host allocation failed");
+    }
+    if (nodal)
+        TRY(load_k(H, k_dev));
+    else
+        TRY(rebuild_coefficients(H));
+#undef TRY
+    *out = H;
+    return NN4MG_OK;
+}
+
+int nn4mg_update_coef(nn4mg_t H, const double *k_dev)
+{
+    if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
+    if (H->cfg.coef_mode != NN4MG_COEF_NODAL) return fail(NN4MG_EINVAL, "handle has a constant coefficient");
+    if (!k_dev) return fail(NN4MG_EINVAL, "k is NULL");
+    return load_k(H, k_dev);
+}
+
+int nn4mg_levels(nn4mg_t H, int *levels, int *dims, int max_levels)
+{
+    if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
+    if (levels) *levels = H->L;
+    if (dims)
+        for (int l = 0; l < H->L && l < max_levels; ++l) {
+            dims[3 * l] = H->lv[l].nx;
+            dims[3 * l + 1] = H->lv[l].ny;
+            dims[3 * l + 2] = H->lv[l].nz;
+        }
+    return NN4MG_OK;
+}
+
+size_t nn4mg_bytes_held(nn4mg_t H) { return H ? H->bytes : 0; }
+
+int nn4mg_residual(nn4mg_t H, const double *x, const double *b, double *r, double *norm2_out)
+{
+    if (!H || !x || !b) return fail(NN4MG_EINVAL, "NULL argument");
+    StencilArgs a = base_args(H, 0);
+    a.yin = x;
+    a.b = b;
+    a.k = H->lv[0].k;
+    a.r = r;
+    a.partials = norm2_out ? H->partials : nullptr;
+    HIP_TRY(launch_stencil(1, H->kt64, IN_PLAIN, OUT_RESID, 0, a, H->stream));
+    if (norm2_out) {
+        HIP_TRY(launch_reduce(H->partials, resid_blocks(H), 1.0, H->scal, H->stream));
+        double s = 0.0;
+        HIP_TRY(hipMemcpyAsync(&s, H->scal, sizeof(double), hipMemcpyDeviceToHost, H->stream));
+        HIP_TRY(hipStreamSynchronize(H->stream));
+        *norm2_out = std::sqrt(s);
+    }
+    return NN4MG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct StateHeader {
+    double nb, bmean, rtol;
+    int max_cycles, fixed, nres, done, status, pad_;
+    double last;
+};
+static_assert(sizeof(StateHeader) == offsetof(SolveState, hist), "state header layout");
+
+int read_header(nn4mg_hier *H, StateHeader *hd)
+{
+    HIP_TRY(hipMemcpyAsync(H->st_host, H->st, sizeof(StateHeader), hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    std::memcpy(hd, H->st_host, sizeof(StateHeader));
+    return NN4MG_OK;
+}
+
+// ||b - mean|| (mean only for singular problems) into st->nb, st->bmean.
+int enqueue_b_norm(nn4mg_hier *H, const double *b)
+{
+    const size_t n = H->lv[0].n;
+    hipStream_t s = H->stream;
+    if (H->singular) {
+        HIP_TRY(launch_sum_partials(b, n, nullptr, 1, H->partials, s));
+        HIP_TRY(launch_reduce(H->partials, sum_blocks(n), 1.0 / (double)n, &H->st->bmean, s));
+    }
+    HIP_TRY(launch_sum_partials(b, n, H->singular ? &H->st->bmean : nullptr, 2, H->partials, s));
+    HIP_TRY(launch_reduce(H->partials, sum_blocks(n), 1.0, H->scal, s));
+    HIP_TRY(launch_set_nb(H->st, H->scal, s));
+    return NN4MG_OK;
+}
+
+int enqueue_stationary_iteration(nn4mg_hier *H, const double *b, double *x)
+{
+    int rc;
+    H->cur_tag += 1;
+    const int *done = &H->st->done;
+    if ((rc = enqueue_body(H, b, H->singular ? &H->st->bmean : nullptr, x, done))) return rc;
+    if ((rc = enqueue_resid_for_cycle(H, b, x, H->singular ? &H->st->bmean : nullptr, true, done))) return rc;
+    HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), H->stream));
+    return NN4MG_OK;
+}
+
+int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady_clock::time_point t0)
+{
+    hipStream_t s = H->stream;
+    const size_t n = H->lv[0].n;
+    StateHeader hd;
+    int rc;
+    if ((rc = read_header(H, &hd))) return rc;
+    if (!(hd.nb > 0.0)) {
+        HIP_TRY(launch_fill(x, n, 0.0, s));
+    } else if (H->singular) {
+        HIP_TRY(launch_sum_partials(x, n, nullptr, 1, H->partials, s));
+        HIP_TRY(launch_reduce(H->partials, sum_blocks(n), 1.0 / (double)n, H->scal + 1, s));
+        HIP_TRY(launch_sub_scalar(x, n, H->scal + 1, s));
+    }
+    HIP_TRY(hipMemcpyAsync(H->st_host, H->st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const SolveState &S = *H->st_host;
+    prof_close_solve(H, S.nres - 1, S.nb > 0.0);
+    int status = NN4MG_OK;
+    if (S.status == -4) status = fail(NN4MG_ENOTCONV, "max_cycles reached before rtol");
+    if (S.status == -5) status = fail(NN4MG_EBREAKDOWN, "non-finite residual");
+    if (info) {
+        info->cycles = S.nres > 0 ? S.nres - 1 : 0;
+        info->status = status;
+        info->relres0 = S.hist[0];
+        info->relres = S.last;
+        info->hist_len = S.nres < NN4MG_HIST_MAX ? S.nres : NN4MG_HIST_MAX;
+        for (int i = 0; i < info->hist_len; ++i) info->hist[i] = S.hist[i];
+        info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+int solve_stationary(nn4mg_hier *H, const double *b, double *x, double rtol, int max_cycles, int fixed,
+                     nn4mg_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = H->stream;
+    int rc;
+    HIP_TRY(launch_init_state(H->st, rtol, max_cycles, fixed, s));
+    H->cur_tag = 0;
+    H->prof_solve_begin = H->prof_cls.size();
+    if ((rc = enqueue_b_norm(H, b))) return rc;
+    if ((rc = enqueue_resid_for_cycle(H, b, x, H->singular ? &H->st->bmean : nullptr, true, &H->st->done))) return rc;
+    HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), s));
+    int enqueued = 0;
+    int planned = fixed ? max_cycles : (max_cycles < 4 ? max_cycles : 4);
+    double prev_last = -1.0;
+    StateHeader hd;
+    while (true) {
+        for (int c = 0; c < planned; ++c)
+            if ((rc = enqueue_stationary_iteration(H, b, x))) return rc;
+        enqueued += planned;
+        if ((rc = read_header(H, &hd))) return rc;
+        if (hd.done || enqueued >= max_cycles) break;
+        const int remaining = max_cycles - enqueued;
+        int need = 4;
+        if (prev_last > 0.0 && hd.last > 0.0 && hd.last < prev_last) {
+            const double rate = std::pow(hd.last / prev_last, 1.0 / planned);
+            if (rate > 0.0 && rate < 1.0) need = (int)std::ceil(std::log(rtol / hd.last) / std::log(rate));
+        }
+        if (need < 1) need = 1;
+        if (need > 64) need = 64;
+        prev_last = hd.last;
+        planned = need < remaining ? need : remaining;
+    }
+    return finish_solve(H, x, info, t0);
+}
+
+}  // namespace
+
+extern "C" {
+
+int nn4mg_profile(nn4mg_t H, int enable)
+{
+    if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    if (enable) {
+        H->prof_cls.clear();
+        H->prof_tag.clear();
+        H->prof_valid.clear();
+        H->prof_solve_begin = 0;
+    }
+    H->prof_on = enable != 0;
+    return NN4MG_OK;
+}
+
+int nn4mg_profile_read(nn4mg_t H, int kclass, int *launches, double *total_ms)
+{
+    if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
+    if (kclass < 0 || kclass >= NN4MG_KCLASS_COUNT) return fail(NN4MG_EINVAL, "unknown kernel class");
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    int n = 0;
+    double tot = 0.0;
+    for (size_t i = 0; i < H->prof_cls.size(); ++i) {
+        if (H->prof_cls[i] != kclass || !H->prof_valid[i]) continue;
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, H->prof_ev[2 * i], H->prof_ev[2 * i + 1]));
+        tot += ms;
+        ++n;
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = tot;
+    return NN4MG_OK;
+}
+
+int nn4mg_vcycle(nn4mg_t H, const double *b, double *x)
+{
+    if (!H || !b || !x) return fail(NN4MG_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = enqueue_resid_for_cycle(H, b, x, nullptr, false, nullptr))) return rc;
+    return enqueue_body(H, b, nullptr, x, nullptr);
+}
+
+int nn4mg_solve(nn4mg_t H, const double *b, double *x, double rtol, int max_cycles, int fixed_cycles,
+                nn4mg_info *info)
+{
+    if (!H || !b || !x) return fail(NN4MG_EINVAL, "NULL argument");
+    if (max_cycles < 0) return fail(NN4MG_EINVAL, "max_cycles must be >= 0");
+    if (!(rtol >= 0.0)) return fail(NN4MG_EINVAL, "rtol must be >= 0");
+    return solve_stationary(H, b, x, rtol, max_cycles, fixed_cycles ? 1 : 0, info);
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Internal declarations of the nn4mg HIP library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nn4mg {
+
+enum Bc { BC_D = 0, BC_N = 1, BC_P = 2 };
+
+// Coefficient storage of a stencil launch.
+enum KType { KT_NONE = 0, KT_F64 = 1, KT_F32 = 2, KT_F16 = 3 };
+
+// How a stencil kernel forms the field it smooths, per loaded cell.
+enum InMode {
+    IN_PLAIN = 0,       // y = yin
+    IN_PROLONG = 1,     // y = P ec
+    IN_PROLONG_ADD = 2  // y = yin + P ec
+};
+
+// What a stencil kernel writes.
+enum OutMode {
+    OUT_STORE = 0,  // yout = y + omega (b - A y) / D
+    OUT_ADD64 = 1,  // x64 += y + omega (b - A y) / D
+    OUT_RESID = 2   // r = (b - bmean) - A y, optional restriction R r, per-block sum of r^2
+};
+
+// Launch shape of the z-marching stencil kernels: a workgroup of 256 threads
+// (64 along x, 4 along y, two rows per thread) owns a 64 x 8 column of cells
+// and marches `zc` planes along z.
+struct TileShape {
+    int tiles_x, tiles_y, chunks_z, zc;
+    int blocks() const { return tiles_x * tiles_y * chunks_z; }
+};
+
+constexpr int kTileX = 64;
+constexpr int kTileY = 8;
+
+TileShape make_tiles(int nx, int ny, int nz, int zc);
+
+struct Geom {
+    int nx, ny, nz;
+    int bc[6];
+};
+
+// Argument block of one stencil launch.  Pointers are device pointers; the
+// element types follow the template instance chosen by the launcher.
+struct StencilArgs {
+    Geom g;
+    TileShape t;
+    double h, omega;
+    const void *yin;     // IN_PLAIN input / IN_PROLONG_ADD addend (type T)
+    const void *ec;      // coarse correction (type T), dims cnx x cny x cnz
+    int cnx, cny, cnz;
+    const void *b;       // right-hand side (type T)
+    const void *k;       // coefficient (KType), NULL for constant
+    void *yout;          // OUT_STORE destination (type T)
+    double *x64;         // OUT_ADD64 destination
+    const double *bmean; // subtracted from b if not NULL (projected right-hand side)
+    void *r;             // OUT_RESID: full residual (type OT), may be NULL
+    void *rc;            // OUT_RESID: restricted residual (type OT), may be NULL
+    double *partials;    // OUT_RESID: one sum of r^2 per block, may be NULL
+    const int *done;     // skip the launch when *done != 0 (may be NULL)
+};
+
+// Device-resident state of a solve; the host polls a copy of it.
+struct SolveState {
+    double nb;       // ||b - bmean||
+    double bmean;    // mean of b (singular problems), else 0
+    double rtol;
+    int max_cycles;
+    int fixed;
+    int nres;        // residual norms recorded
+    int done;        // 1 once the stopping rule fired
+    int status;      // 0, -4 (max cycles), -5 (non-finite)
+    int pad_;
+    double last;     // last relative residual
+    double hist[512];
+    // flexible CG scalars
+    double fcg_rho, fcg_alpha, fcg_beta, fcg_pq_prev;
+};
+
+// ---------------------------------------------------------------- launchers
+// All return hipSuccess or the launch error.
+
+// Stencil kernel: T in {double, float}; kt selects the coefficient type
+// (KT_F64 requires T = double or float; KT_F32/KT_F16 require T = float);
+// for OUT_RESID, T must be double and out_f32 selects float outputs r/rc.
+hipError_t launch_stencil(int T_is_f64, int kt, int in_mode, int out_mode, int out_f32, const StencilArgs &a,
+                          hipStream_t s);
+
+hipError_t launch_restrict(int T_is_f64, const void *fine, void *coarse, int nx, int ny, int nz, const int *done,
+                           hipStream_t s);
+hipError_t launch_coarsen_k(const double *kf, double *kc, int nx, int ny, int nz, int harmonic, hipStream_t s);
+hipError_t launch_cast_k(const double *k, void *out, size_t n, int kt, hipStream_t s);
+hipError_t launch_check_positive(const double *k, size_t n, int *bad, hipStream_t s);
+
+// Sums (fixed order, deterministic): partials[blk] = sum over the block's
+// slice of (v - shift)^p (p = 1 or 2; shift may be NULL).
+int sum_blocks(size_t n);
+hipError_t launch_sum_partials(const double *v, size_t n, const double *shift, int power, double *partials,
+                               hipStream_t s);
+// out[0] = scale * sum(partials[0..n))  (single workgroup, fixed tree)
+hipError_t launch_reduce(const double *partials, int n, double scale, double *out, hipStream_t s);
+// Reset the solve state; set_nb: nb = sqrt(*sumsq), and done at once if nb == 0.
+hipError_t launch_init_state(SolveState *st, double rtol, int max_cycles, int fixed, hipStream_t s);
+hipError_t launch_set_nb(SolveState *st, const double *sumsq, hipStream_t s);
+// Stopping rule after a residual: consumes partials of r^2.
+hipError_t launch_finish_norm(SolveState *st, const double *partials, int n, hipStream_t s);
+
+hipError_t launch_coarse_solve(int T_is_f64, const void *bc, void *ec, const double *ainv, int n, int singular,
+                               const int *done, hipStream_t s);
+hipError_t launch_sub_scalar(double *x, size_t n, const double *val, hipStream_t s);
+hipError_t launch_fill(double *x, size_t n, double v, hipStream_t s);
+hipError_t launch_copy(double *dst, const double *src, size_t n, const int *done, hipStream_t s);
+// x += e (e FP64, or FP32 when e_f32)
+hipError_t launch_add(double *x, const void *e, int e_f32, size_t n, const int *done, hipStream_t s);
+
+}  // namespace nn4mg

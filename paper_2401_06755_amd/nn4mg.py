@@ -1,0 +1,220 @@
+"""Python binding of the nn4mg C-ABI (include/nn4mg.h): argument marshalling only.
+
+Every step of the solve runs in the HIP kernels of libnn4mg.so; this module
+checks tensor shapes/dtypes/devices, passes raw device pointers and the current
+torch stream, and converts status codes into exceptions.  PyTorch provides the
+device memory and the stream.  If the library has not been built, every entry
+point raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnn4mg.so")
+
+NN4MG_OK = 0
+NN4MG_EINVAL = -1
+NN4MG_ENOMEM = -2
+NN4MG_EDEVICE = -3
+NN4MG_ENOTCONV = -4
+NN4MG_EBREAKDOWN = -5
+NN4MG_EBUSY = -6
+
+BC_DIRICHLET0, BC_NEUMANN0, BC_PERIODIC = 0, 1, 2
+COEF_CONST, COEF_NODAL = 0, 1
+PREC_FP64, PREC_FP32_SMOOTH, PREC_FP16_COEF = 0, 1, 2
+OUTER_STATIONARY, OUTER_FCG = 0, 1
+KCLASS_FINE_RESID, KCLASS_FINE_SWEEP_PROLONG, KCLASS_FINE_SWEEP = 0, 1, 2
+HIST_MAX = 512
+
+
+class Nn4mgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nn4mg error {code}: {msg}")
+        self.code = code
+
+
+class NotConverged(Nn4mgError):
+    pass
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("h", ctypes.c_double),
+        ("bc", ctypes.c_int * 6),
+        ("coef_mode", ctypes.c_int), ("precision", ctypes.c_int),
+        ("nu_post", ctypes.c_int), ("omega", ctypes.c_double),
+        ("min_coarse", ctypes.c_int), ("outer", ctypes.c_int), ("coarse_avg", ctypes.c_int),
+        ("reserved", ctypes.c_int * 7),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("cycles", ctypes.c_int), ("status", ctypes.c_int),
+        ("relres0", ctypes.c_double), ("relres", ctypes.c_double),
+        ("hist_len", ctypes.c_int),
+        ("hist", ctypes.c_double * HIST_MAX),
+        ("solve_ms", ctypes.c_double),
+    ]
+
+    def history(self):
+        return [self.hist[i] for i in range(self.hist_len)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnn4mg.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"nn4mg HIP library missing at {LIB_PATH}; build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    cfgp = ctypes.POINTER(Config)
+    L.nn4mg_config_default.restype = None
+    L.nn4mg_config_default.argtypes = [cfgp, i, i, i, d]
+    L.nn4mg_bytes_required.restype = sz
+    L.nn4mg_bytes_required.argtypes = [cfgp]
+    L.nn4mg_setup.restype = i
+    L.nn4mg_setup.argtypes = [cfgp, vp, vp, ctypes.POINTER(vp)]
+    L.nn4mg_update_coef.restype = i
+    L.nn4mg_update_coef.argtypes = [vp, vp]
+    L.nn4mg_residual.restype = i
+    L.nn4mg_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(d)]
+    L.nn4mg_vcycle.restype = i
+    L.nn4mg_vcycle.argtypes = [vp, vp, vp]
+    L.nn4mg_solve.restype = i
+    L.nn4mg_solve.argtypes = [vp, vp, vp, d, i, i, ctypes.POINTER(Info)]
+    L.nn4mg_levels.restype = i
+    L.nn4mg_levels.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), i]
+    L.nn4mg_bytes_held.restype = sz
+    L.nn4mg_bytes_held.argtypes = [vp]
+    L.nn4mg_profile.restype = i
+    L.nn4mg_profile.argtypes = [vp, i]
+    L.nn4mg_profile_read.restype = i
+    L.nn4mg_profile_read.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(d)]
+    L.nn4mg_destroy.restype = i
+    L.nn4mg_destroy.argtypes = [vp]
+    L.nn4mg_last_error.restype = ctypes.c_char_p
+    L.nn4mg_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code == NN4MG_OK:
+        return
+    msg = lib().nn4mg_last_error().decode()
+    if code == NN4MG_ENOTCONV:
+        raise NotConverged(code, msg)
+    raise Nn4mgError(code, msg)
+
+
+def config_default(nx, ny, nz, h, **kw) -> Config:
+    c = Config()
+    lib().nn4mg_config_default(ctypes.byref(c), int(nx), int(ny), int(nz), float(h))
+    for key, val in kw.items():
+        if key == "bc":
+            for f in range(6):
+                c.bc[f] = int(val[f])
+        else:
+            setattr(c, key, val)
+    return c
+
+
+def bytes_required(cfg: Config) -> int:
+    return int(lib().nn4mg_bytes_required(ctypes.byref(cfg)))
+
+
+def _field(t: torch.Tensor, n: int, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Hierarchy:
+    """A multigrid hierarchy bound to the current torch stream (nn4mg_setup)."""
+
+    def __init__(self, cfg: Config, k: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None):
+        self.cfg = cfg
+        self.n = cfg.nx * cfg.ny * cfg.nz
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        kp = _field(k, self.n, "k") if k is not None else None
+        h = ctypes.c_void_p()
+        _check(lib().nn4mg_setup(ctypes.byref(cfg), kp, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("hierarchy destroyed")
+        return self._h
+
+    def update_coef(self, k: torch.Tensor):
+        _check(lib().nn4mg_update_coef(self.handle, _field(k, self.n, "k")))
+
+    def residual(self, x: torch.Tensor, b: torch.Tensor, r: torch.Tensor | None = None, norm: bool = True):
+        out = ctypes.c_double(0.0)
+        _check(lib().nn4mg_residual(self.handle, _field(x, self.n, "x"), _field(b, self.n, "b"),
+                                    _field(r, self.n, "r") if r is not None else None,
+                                    ctypes.byref(out) if norm else None))
+        return out.value if norm else None
+
+    def vcycle(self, b: torch.Tensor, x: torch.Tensor):
+        _check(lib().nn4mg_vcycle(self.handle, _field(b, self.n, "b"), _field(x, self.n, "x")))
+
+    def solve(self, b: torch.Tensor, x: torch.Tensor, rtol: float = 1e-8, max_cycles: int = 100,
+              fixed_cycles: bool = False, raise_on_notconv: bool = False) -> Info:
+        info = Info()
+        code = lib().nn4mg_solve(self.handle, _field(b, self.n, "b"), _field(x, self.n, "x"), float(rtol),
+                                 int(max_cycles), int(bool(fixed_cycles)), ctypes.byref(info))
+        if code == NN4MG_ENOTCONV and not raise_on_notconv:
+            return info
+        _check(code)
+        return info
+
+    def levels(self):
+        L = ctypes.c_int(0)
+        dims = (ctypes.c_int * 48)()
+        _check(lib().nn4mg_levels(self.handle, ctypes.byref(L), dims, 16))
+        return [(dims[3 * l], dims[3 * l + 1], dims[3 * l + 2]) for l in range(L.value)]
+
+    def profile(self, enable: bool):
+        _check(lib().nn4mg_profile(self.handle, int(bool(enable))))
+
+    def profile_read(self, kclass: int):
+        n = ctypes.c_int(0)
+        ms = ctypes.c_double(0.0)
+        _check(lib().nn4mg_profile_read(self.handle, int(kclass), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def bytes_held(self) -> int:
+        return int(lib().nn4mg_bytes_held(self.handle))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nn4mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

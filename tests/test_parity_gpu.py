@@ -1,0 +1,228 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C-ABI.
+
+Tolerances (FP64 path): single operator applications agree to 1e-13 of the
+largest output (the two sides sum the same terms in different orders, so they
+differ by a few ulps of the largest term); one V-cycle to 1e-12; solves at a
+fixed cycle count to 1e-10 relative (the bar of the method description), both
+for x and for every entry of the residual history (history entries are
+compared with an absolute floor of 1e-13 * ||b||, the size of rounding in
+b - A x itself).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_06755_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+D, N, P = 0, 1, 2
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_06755_amd import nn4mg
+
+    nn4mg.lib()
+    return nn4mg
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).cuda()
+
+
+def host(t, shape):
+    return t.cpu().numpy().reshape(shape)
+
+
+def make(mg, shape_xyz, h, bc, k=None, **kw):
+    cfg = mg.config_default(*shape_xyz, h, bc=bc, coef_mode=1 if k is not None else 0, **kw)
+    return mg.Hierarchy(cfg, dev(k) if k is not None else None)
+
+
+def rand_k(shape, seed, spread=3.0):
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(-spread, spread, size=shape))
+
+
+RESID_CASES = [
+    ((80, 24, 40), (D, D, D, D, D, D), False),
+    ((80, 24, 40), (N, N, N, N, N, N), True),
+    ((64, 64, 64), (D, N, P, P, N, D), True),
+    ((96, 24, 24), (N, D, N, D, P, P), False),
+    ((5, 7, 3), (D, N, N, D, N, N), True),
+    ((1, 1, 1), (N, N, N, N, N, D), True),
+    ((136, 12, 20), (N, N, D, D, N, N), True),
+    ((40, 12, 24), (D, D, N, N, N, D), True),
+]
+
+
+@pytest.mark.parametrize("shape,bc,var", RESID_CASES)
+def test_residual_matches_oracle(mg, shape, bc, var):
+    import torch
+
+    nx, ny, nz = shape
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((nz, ny, nx))
+    b = rng.standard_normal((nz, ny, nx))
+    k = rand_k((nz, ny, nx), 12) if var else None
+    h = 1.0 / nx
+    H = make(mg, shape, h, bc, k)
+    r = torch.empty(nx * ny * nz, dtype=torch.float64, device="cuda")
+    nrm = H.residual(dev(x), dev(b), r)
+    want = oracle.residual(b, x, h, bc, k)
+    got = host(r, want.shape)
+    scale = np.abs(want).max()
+    assert np.max(np.abs(got - want)) <= 1e-13 * scale
+    assert abs(nrm - np.linalg.norm(want)) <= 1e-12 * np.linalg.norm(want)
+
+
+VC_CASES = [
+    ((64, 64, 64), (D,) * 6, False),
+    ((80, 24, 40), (N, N, N, N, N, D), True),
+    ((32, 48, 16), (D, N, P, P, N, D), True),
+    ((40, 12, 24), (N, N, D, N, N, N), True),
+    ((48, 48, 48), (N,) * 6, True),
+    ((8, 8, 8), (D,) * 6, False),
+    ((6, 10, 4), (N, D, N, N, D, N), True),
+]
+
+
+@pytest.mark.parametrize("shape,bc,var", VC_CASES)
+def test_one_vcycle_matches_oracle(mg, shape, bc, var):
+    nx, ny, nz = shape
+    rng = np.random.default_rng(21)
+    x0 = rng.standard_normal((nz, ny, nx))
+    b = rng.standard_normal((nz, ny, nx))
+    if all(v != D for v in bc):
+        b -= b.mean()
+    k = rand_k((nz, ny, nx), 22) if var else None
+    h = 1.0 / nx
+    H = make(mg, shape, h, bc, k)
+    OH = oracle.Hierarchy(shape, h, bc, k=k)
+    xd = dev(x0)
+    H.vcycle(dev(b), xd)
+    got = host(xd, x0.shape)
+    want = OH.vcycle(x0, b)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("shape,bc,var,cycles", [
+    ((64, 64, 64), (D,) * 6, False, 20),
+    ((80, 24, 40), (N, N, N, N, N, D), True, 20),
+    ((48, 48, 48), (N,) * 6, True, 12),
+    ((40, 40, 80), (N, N, N, N, N, D), True, 10),
+])
+def test_fixed_cycle_solve_matches_oracle(mg, shape, bc, var, cycles):
+    nx, ny, nz = shape
+    rng = np.random.default_rng(31)
+    b = rng.standard_normal((nz, ny, nx))
+    k = None
+    if var:
+        frac = inputs.sphere_fraction(shape, 1.0 / nx, (0.5, 0.5, 0.5 * nz / nx), 0.3)
+        k = inputs.two_phase_k(frac, 1000.0, 1.0)
+    h = 1.0 / nx
+    H = make(mg, shape, h, bc, k)
+    OH = oracle.Hierarchy(shape, h, bc, k=k)
+    xd = dev(np.zeros_like(b))
+    info = H.solve(dev(b), xd, max_cycles=cycles, fixed_cycles=True)
+    xo, hist_o, st = OH.solve(b, max_cycles=cycles, fixed=True)
+    assert info.status == 0 and info.cycles == cycles and st == 0
+    got = host(xd, b.shape)
+    assert np.max(np.abs(got - xo)) <= 1e-10 * np.abs(xo).max()
+    hist_g = np.array(info.history())
+    assert len(hist_g) == len(hist_o) == cycles + 1
+    assert np.all(np.abs(hist_g - hist_o) <= 1e-10 * hist_o + 1e-13)
+
+
+def test_config1_poisson_64_to_1e8(mg):
+    """64^3 constant-coefficient Poisson, zero Dirichlet, sine mode + 1e-3 noise,
+    5 levels to 4^3, V(0,2), omega = 2/3, solved to relative residual 1e-8."""
+    w = inputs.poisson_sine_noise(64, seed=1)
+    H = make(mg, w["shape"], w["h"], w["bc"])
+    assert H.levels() == [(64, 64, 64), (32, 32, 32), (16, 16, 16), (8, 8, 8), (4, 4, 4)]
+    OH = oracle.Hierarchy(w["shape"], w["h"], w["bc"])
+    xd = dev(np.zeros_like(w["b"]))
+    info = H.solve(dev(w["b"]), xd, rtol=1e-8, max_cycles=100)
+    xo, hist_o, st = OH.solve(w["b"], rtol=1e-8, max_cycles=100)
+    assert info.status == 0 and st == 0
+    assert info.cycles == len(hist_o) - 1
+    assert info.relres <= 1e-8
+    got = host(xd, w["b"].shape)
+    assert np.max(np.abs(got - xo)) <= 1e-10 * np.abs(xo).max()
+    r = oracle.residual(w["b"], got, w["h"], w["bc"])
+    assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(w["b"])
+
+
+def test_singular_neumann_zero_mean_and_projection(mg):
+    """All-Neumann: b projected to zero mean, x returned with zero mean; same
+    cycle count and x as the oracle (which projects x after every cycle)."""
+    shape = (32, 32, 32)
+    rng = np.random.default_rng(41)
+    k = rand_k((32, 32, 32), 42, spread=2.0)
+    b = rng.standard_normal((32, 32, 32)) + 3.0
+    x0 = rng.standard_normal((32, 32, 32))
+    H = make(mg, shape, 1 / 32, (N,) * 6, k)
+    OH = oracle.Hierarchy(shape, 1 / 32, (N,) * 6, k=k)
+    xd = dev(x0)
+    info = H.solve(dev(b), xd, rtol=1e-9, max_cycles=300)
+    assert info.status == 0
+    got = host(xd, b.shape)
+    assert abs(got.mean()) <= 1e-13 * np.abs(got).max()
+    xo, hist_o, st = OH.solve(b, x0=x0, rtol=1e-9, max_cycles=300)
+    assert st == 0 and info.cycles == len(hist_o) - 1
+    assert np.max(np.abs(got - xo)) <= 1e-10 * np.abs(xo).max()
+    r = (b - b.mean()) - oracle.apply(got, 1 / 32, (N,) * 6, k)
+    assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(b - b.mean())
+
+
+def test_zero_rhs_and_zero_cycles(mg):
+    shape = (16, 16, 16)
+    H = make(mg, shape, 1 / 16, (D,) * 6)
+    xd = dev(np.ones((16, 16, 16)))
+    info = H.solve(dev(np.zeros((16, 16, 16))), xd)
+    assert info.status == 0 and info.cycles == 0
+    assert float(xd.abs().max()) == 0.0
+    b = np.random.default_rng(5).standard_normal((16, 16, 16))
+    x0 = np.random.default_rng(6).standard_normal((16, 16, 16))
+    xd = dev(x0)
+    info = H.solve(dev(b), xd, max_cycles=0, rtol=1e-30)
+    assert info.status == mg.NN4MG_ENOTCONV and info.cycles == 0
+    np.testing.assert_array_equal(host(xd, x0.shape), x0)
+    want = np.linalg.norm(oracle.residual(b, x0, 1 / 16, (D,) * 6)) / np.linalg.norm(b)
+    assert abs(info.relres0 - want) <= 1e-12 * want
+
+
+def test_bitwise_repeatable(mg):
+    w = inputs.dense_sphere(48, seed=2)
+    H = make(mg, w["shape"], w["h"], w["bc"], w["k"])
+    outs = []
+    for _ in range(2):
+        xd = dev(np.zeros_like(w["b"]))
+        H.solve(dev(w["b"]), xd, rtol=1e-8, max_cycles=200)
+        outs.append(xd.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_invalid_configs_rejected(mg):
+    with pytest.raises(mg.Nn4mgError):
+        mg.Hierarchy(mg.config_default(0, 4, 4, 0.25))
+    with pytest.raises(mg.Nn4mgError):
+        mg.Hierarchy(mg.config_default(8, 8, 8, -1.0))
+    with pytest.raises(mg.Nn4mgError):  # coarsest level too large (odd dims)
+        mg.Hierarchy(mg.config_default(33, 33, 33, 1 / 33))
+    with pytest.raises(mg.Nn4mgError):  # periodic on one face only
+        mg.Hierarchy(mg.config_default(8, 8, 8, 0.125, bc=(P, D, D, D, D, D)))
+    cfg = mg.config_default(8, 8, 8, 0.125, coef_mode=1)
+    with pytest.raises(mg.Nn4mgError):  # nodal without k
+        mg.Hierarchy(cfg)
+    k = np.ones((8, 8, 8))
+    k[3, 3, 3] = 0.0
+    with pytest.raises(mg.Nn4mgError):  # non-positive k
+        mg.Hierarchy(cfg, dev(k))
