@@ -52,6 +52,26 @@ struct Level {
     TileShape tiles{};
 };
 
+// Default launch shape of a level: the tile width that pads the x-y plane
+// least (ties: the wider tile, for longer coalesced rows), and the longest
+// z-chunk that still gives >= 1024 workgroups.
+TileShape default_tiles(int nx, int ny, int nz)
+{
+    int best_tx = 64;
+    double best_area = 1e300;
+    for (int tx : {64, 32, 16}) {
+        const int ty = 512 / tx;
+        const double area = (double)((nx + tx - 1) / tx * tx) * (double)((ny + ty - 1) / ty * ty);
+        if (area < best_area) {
+            best_area = area;
+            best_tx = tx;
+        }
+    }
+    int zc = kDefaultZc;
+    while (zc > 2 && (double)nx * ny * nz / (512.0 * zc) < 1024.0) zc /= 2;
+    return make_tiles(nx, ny, nz, zc, best_tx);
+}
+
 int count_levels(int nx, int ny, int nz, int min_coarse)
 {
     int L = 1;
@@ -224,7 +244,7 @@ struct nn4mg_hier {
     int cur_tag = 0;
     size_t prof_solve_begin = 0;
     std::vector<hipEvent_t> prof_ev;  // 2 per record
-    std::vector<int> prof_cls, prof_tag, prof_valid;
+    std::vector<int> prof_cls, prof_tag, prof_valid, prof_lvl;
 };
 
 namespace {
@@ -265,8 +285,10 @@ size_t bytes_for(const nn4mg_config *c)
     size_t maxblk = 1024;
     for (int l = 0; l < L; ++l) {
         const size_t n = (size_t)(c->nx >> l) * (c->ny >> l) * (c->nz >> l);
-        const TileShape t = make_tiles(c->nx >> l, c->ny >> l, c->nz >> l, kDefaultZc);
-        if ((size_t)t.blocks() > maxblk) maxblk = t.blocks();
+        for (int tx : {64, 32, 16}) {
+            const TileShape t = make_tiles(c->nx >> l, c->ny >> l, c->nz >> l, 2, tx);
+            if ((size_t)t.blocks() > maxblk) maxblk = t.blocks();
+        }
         if (nodal) b += 8 * n;
         if (!mixed) {
             b += (l == 0) ? 8 * n : 24 * n;
@@ -326,7 +348,7 @@ int load_k(nn4mg_hier *H, const double *k_dev)
 constexpr size_t kProfMax = 3 * 4096;
 
 // Open a timing record for a launch of class cls; returns its index or -1.
-long prof_begin(nn4mg_hier *H, int cls)
+long prof_begin(nn4mg_hier *H, int cls, int level = 0)
 {
     if (!H->prof_on) return -1;
     const size_t i = H->prof_cls.size();
@@ -343,6 +365,7 @@ long prof_begin(nn4mg_hier *H, int cls)
     }
     if (hipEventRecord(H->prof_ev[2 * i], H->stream) != hipSuccess) return -1;
     H->prof_cls.push_back(cls);
+    H->prof_lvl.push_back(level);
     H->prof_tag.push_back(H->cur_tag);
     H->prof_valid.push_back(1);
     return (long)i;
@@ -425,7 +448,9 @@ int enqueue_coarse_sweeps(nn4mg_hier *H, int l, const int *done)
         } else {
             a.yin = in;
         }
+        const long pr = prof_begin(H, s == 0 ? NN4MG_KCLASS_FINE_SWEEP_PROLONG : NN4MG_KCLASS_FINE_SWEEP, l);
         HIP_TRY(launch_stencil(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, in_mode, OUT_STORE, 0, a, H->stream));
+        prof_end(H, pr);
         in = buf[cur];
         cur ^= 1;
     }
@@ -632,7 +657,7 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
         V.nz = cfg->nz >> l;
         V.h = cfg->h * (double)(1 << l);
         V.n = (size_t)V.nx * V.ny * V.nz;
-        V.tiles = make_tiles(V.nx, V.ny, V.nz, kDefaultZc);
+        V.tiles = default_tiles(V.nx, V.ny, V.nz);
         if (V.tiles.blocks() > maxblk) maxblk = V.tiles.blocks();
         if (nodal) TRY(dalloc(H, &V.k, V.n));
         const bool single = (H->L == 1);
@@ -660,6 +685,11 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
             }
         }
     }
+    for (int l = 0; l < H->L; ++l)
+        for (int tx : {64, 32, 16}) {
+            const int nb = make_tiles(H->lv[l].nx, H->lv[l].ny, H->lv[l].nz, 2, tx, 2).blocks();
+            if (nb > maxblk) maxblk = nb;
+        }
     const Level &C = H->lv[H->L - 1];
     H->nc = (int)C.n;
     TRY(dalloc(H, &H->ainv, (size_t)H->nc * H->nc));
@@ -850,6 +880,7 @@ int nn4mg_profile(nn4mg_t H, int enable)
     HIP_TRY(hipStreamSynchronize(H->stream));
     if (enable) {
         H->prof_cls.clear();
+        H->prof_lvl.clear();
         H->prof_tag.clear();
         H->prof_valid.clear();
         H->prof_solve_begin = 0;
@@ -858,15 +889,16 @@ int nn4mg_profile(nn4mg_t H, int enable)
     return NN4MG_OK;
 }
 
-int nn4mg_profile_read(nn4mg_t H, int kclass, int *launches, double *total_ms)
+int nn4mg_profile_read_level(nn4mg_t H, int level, int kclass, int *launches, double *total_ms)
 {
     if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
     if (kclass < 0 || kclass >= NN4MG_KCLASS_COUNT) return fail(NN4MG_EINVAL, "unknown kernel class");
+    if (level < 0 || level >= H->L) return fail(NN4MG_EINVAL, "bad level");
     HIP_TRY(hipStreamSynchronize(H->stream));
     int n = 0;
     double tot = 0.0;
     for (size_t i = 0; i < H->prof_cls.size(); ++i) {
-        if (H->prof_cls[i] != kclass || !H->prof_valid[i]) continue;
+        if (H->prof_cls[i] != kclass || H->prof_lvl[i] != level || !H->prof_valid[i]) continue;
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, H->prof_ev[2 * i], H->prof_ev[2 * i + 1]));
         tot += ms;
@@ -874,6 +906,109 @@ int nn4mg_profile_read(nn4mg_t H, int kclass, int *launches, double *total_ms)
     }
     if (launches) *launches = n;
     if (total_ms) *total_ms = tot;
+    return NN4MG_OK;
+}
+
+int nn4mg_profile_read(nn4mg_t H, int kclass, int *launches, double *total_ms)
+{
+    return nn4mg_profile_read_level(H, 0, kclass, launches, total_ms);
+}
+
+int nn4mg_set_tiles(nn4mg_t H, int level, int tx, int ry, int zc)
+{
+    if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
+    if (level < 0 || level >= H->L) return fail(NN4MG_EINVAL, "bad level");
+    if ((tx != 64 && tx != 32 && tx != 16) || (ry != 2 && ry != 4) || (tx == 16 && ry != 2) || zc < 2 || (zc & 1))
+        return fail(NN4MG_EINVAL, "bad tile shape");
+    Level &V = H->lv[level];
+    const TileShape t = make_tiles(V.nx, V.ny, V.nz, zc, tx, ry);
+    if (t.blocks() > H->max_partials) return fail(NN4MG_EINVAL, "tile shape needs too many workgroups");
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    V.tiles = t;
+    return NN4MG_OK;
+}
+
+int nn4mg_get_tiles(nn4mg_t H, int level, int *tx, int *ry, int *zc)
+{
+    if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
+    if (level < 0 || level >= H->L) return fail(NN4MG_EINVAL, "bad level");
+    if (tx) *tx = H->lv[level].tiles.tx;
+    if (ry) *ry = H->lv[level].tiles.ry;
+    if (zc) *zc = H->lv[level].tiles.zc;
+    return NN4MG_OK;
+}
+
+int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int max_levels)
+{
+    if (!H || !b || !x) return fail(NN4MG_EINVAL, "NULL argument");
+    const int L = H->L;
+    const int txs[5] = {64, 64, 32, 32, 16};
+    const int rys[5] = {2, 4, 2, 4, 2};
+    const int zcs[5] = {2, 4, 8, 16, 32};
+    const int reps = 3;
+    std::vector<double> best(L, 1e300);
+    std::vector<TileShape> best_t(L);
+    for (int l = 0; l < L; ++l) best_t[l] = H->lv[l].tiles;
+    const bool saved_on = H->prof_on;
+    int rc;
+    for (int ti = 0; ti < 5; ++ti)
+        for (int zi = 0; zi < 5; ++zi) {
+            std::vector<bool> used(L, false);
+            for (int l = 0; l < L; ++l) {
+                Level &V = H->lv[l];
+                if (zcs[zi] > V.nz + (V.nz & 1)) continue;
+                const TileShape t = make_tiles(V.nx, V.ny, V.nz, zcs[zi], txs[ti], rys[ti]);
+                if (t.blocks() > H->max_partials) continue;
+                V.tiles = t;
+                used[l] = true;
+            }
+            HIP_TRY(hipStreamSynchronize(H->stream));
+            H->prof_on = true;
+            H->prof_cls.clear();
+            H->prof_lvl.clear();
+            H->prof_tag.clear();
+            H->prof_valid.clear();
+            H->cur_tag = 0;
+            for (int r = 0; r < reps + 1; ++r) {
+                if (r == 1) {  // the first cycle warms caches and code; drop it
+                    HIP_TRY(hipStreamSynchronize(H->stream));
+                    H->prof_cls.clear();
+                    H->prof_lvl.clear();
+                    H->prof_tag.clear();
+                    H->prof_valid.clear();
+                }
+                if ((rc = enqueue_resid_for_cycle(H, b, x, nullptr, false, nullptr))) return rc;
+                if ((rc = enqueue_body(H, b, nullptr, x, nullptr))) return rc;
+            }
+            H->prof_on = false;
+            for (int l = 0; l < L; ++l) {
+                if (!used[l]) continue;
+                double tot = 0.0;
+                for (int cls = 0; cls < NN4MG_KCLASS_COUNT; ++cls) {
+                    double ms = 0.0;
+                    int n = 0;
+                    if ((rc = nn4mg_profile_read_level(H, l, cls, &n, &ms))) return rc;
+                    tot += ms;
+                }
+                if (tot > 0.0 && tot < best[l]) {
+                    best[l] = tot;
+                    best_t[l] = H->lv[l].tiles;
+                }
+            }
+        }
+    for (int l = 0; l < L; ++l) H->lv[l].tiles = best_t[l];
+    H->prof_on = saved_on;
+    H->prof_cls.clear();
+    H->prof_lvl.clear();
+    H->prof_tag.clear();
+    H->prof_valid.clear();
+    H->prof_solve_begin = 0;
+    if (tiles_out)
+        for (int l = 0; l < L && l < max_levels; ++l) {
+            tiles_out[3 * l] = best_t[l].tx;
+            tiles_out[3 * l + 1] = best_t[l].ry;
+            tiles_out[3 * l + 2] = best_t[l].zc;
+        }
     return NN4MG_OK;
 }
 

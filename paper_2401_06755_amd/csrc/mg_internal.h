@@ -28,17 +28,16 @@ enum OutMode {
 };
 
 // Launch shape of the z-marching stencil kernels: a workgroup of 256 threads
-// (64 along x, 4 along y, two rows per thread) owns a 64 x 8 column of cells
-// and marches `zc` planes along z.
+// (tx along x, 256/tx along y, ry rows per thread) owns a tx x (ry*256/tx)
+// column of cells and marches `zc` planes along z.
 struct TileShape {
+    int tx;  // cells per tile along x: 64, 32 or 16
+    int ry;  // cell rows per thread: 2 or 4 (tile is tx x ry*256/tx)
     int tiles_x, tiles_y, chunks_z, zc;
     int blocks() const { return tiles_x * tiles_y * chunks_z; }
 };
 
-constexpr int kTileX = 64;
-constexpr int kTileY = 8;
-
-TileShape make_tiles(int nx, int ny, int nz, int zc);
+TileShape make_tiles(int nx, int ny, int nz, int zc, int tx, int ry = 2);
 
 struct Geom {
     int nx, ny, nz;

@@ -102,6 +102,14 @@ def lib():
     L.nn4mg_profile.argtypes = [vp, i]
     L.nn4mg_profile_read.restype = i
     L.nn4mg_profile_read.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(d)]
+    L.nn4mg_profile_read_level.restype = i
+    L.nn4mg_profile_read_level.argtypes = [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(d)]
+    L.nn4mg_set_tiles.restype = i
+    L.nn4mg_set_tiles.argtypes = [vp, i, i, i, i]
+    L.nn4mg_get_tiles.restype = i
+    L.nn4mg_get_tiles.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+    L.nn4mg_autotune.restype = i
+    L.nn4mg_autotune.argtypes = [vp, vp, vp, ctypes.POINTER(i), i]
     L.nn4mg_destroy.restype = i
     L.nn4mg_destroy.argtypes = [vp]
     L.nn4mg_last_error.restype = ctypes.c_char_p
@@ -204,6 +212,26 @@ class Hierarchy:
         ms = ctypes.c_double(0.0)
         _check(lib().nn4mg_profile_read(self.handle, int(kclass), ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    def profile_read_level(self, level: int, kclass: int):
+        n = ctypes.c_int(0)
+        ms = ctypes.c_double(0.0)
+        _check(lib().nn4mg_profile_read_level(self.handle, int(level), int(kclass), ctypes.byref(n),
+                                              ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def set_tiles(self, level: int, tx: int, ry: int, zc: int):
+        _check(lib().nn4mg_set_tiles(self.handle, int(level), int(tx), int(ry), int(zc)))
+
+    def get_tiles(self, level: int):
+        tx, ry, zc = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check(lib().nn4mg_get_tiles(self.handle, int(level), ctypes.byref(tx), ctypes.byref(ry), ctypes.byref(zc)))
+        return tx.value, ry.value, zc.value
+
+    def autotune(self, b: torch.Tensor, x: torch.Tensor):
+        out = (ctypes.c_int * 48)()
+        _check(lib().nn4mg_autotune(self.handle, _field(b, self.n, "b"), _field(x, self.n, "x"), out, 16))
+        return [(out[3 * l], out[3 * l + 1], out[3 * l + 2]) for l in range(len(self.levels()))]
 
     def bytes_held(self) -> int:
         return int(lib().nn4mg_bytes_held(self.handle))
