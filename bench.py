@@ -62,7 +62,7 @@ def cycle_model_bytes(levels, mode):
     return tot
 
 
-def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol):
+def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol, autotune=True):
     nx, ny, nz = work["shape"]
     n = nx * ny * nz
     cfg = nn4mg.config_default(nx, ny, nz, work["h"], bc=work["bc"], coef_mode=nn4mg.COEF_NODAL,
@@ -79,12 +79,18 @@ def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol):
     H.update_coef(kd)
     torch.cuda.synchronize()
     update_ms = (time.perf_counter() - t0) * 1e3
+    tiles, tune_ms = None, 0.0
+    if autotune:
+        t0 = time.perf_counter()
+        tiles = H.autotune(bd, xd)
+        tune_ms = (time.perf_counter() - t0) * 1e3
+        log(f"  autotuned tiles per level (resid, first sweep, sweep): {tiles}")
     info = None
     for w in range(warmup):
         xd.zero_()
         info = H.solve(bd, xd, rtol=rtol, max_cycles=2000)
         log(f"  warmup {w}: cycles {info.cycles} relres {info.relres:.3e} {info.solve_ms:.1f} ms")
-    H.profile(True)
+    # timed region: K solves, no instrumentation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cycles = 0
@@ -96,17 +102,30 @@ def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol):
         infos.append(info)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    H.profile(False)
     for s, inf in enumerate(infos):
         log(f"  step {s}: cycles {inf.cycles} relres {inf.relres:.3e} status {inf.status} {inf.solve_ms:.1f} ms")
+    # the same K solves again with every finest-level launch bracketed by HIP
+    # events on the solve stream (event records add a little host overhead,
+    # so they are kept out of the timed region above)
+    H.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in range(steps):
+        xd.zero_()
+        H.solve(bd, xd, rtol=rtol, max_cycles=2000)
+    torch.cuda.synchronize()
+    dt_prof = time.perf_counter() - t1
+    H.profile(False)
     kern = {}
     for name, cls in KCLASS.items():
         cnt, ms = H.profile_read(cls)
         kern[name] = (cnt, ms)
     levels = H.levels()
     H.close()
-    return dict(n=n, dt=dt, cycles=cycles, info=infos[-1], kern=kern, levels=levels, setup_ms=setup_ms,
-                update_ms=update_ms, all_converged=all(i.status == 0 for i in infos))
+    return dict(n=n, dt=dt, dt_prof=dt_prof, cycles=cycles, info=infos[-1], kern=kern, levels=levels,
+                setup_ms=setup_ms,
+                update_ms=update_ms, tiles=tiles, tune_ms=tune_ms,
+                all_converged=all(i.status == 0 for i in infos))
 
 
 def roofline(res, mode):
@@ -157,6 +176,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 256 MiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -171,10 +193,17 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"generating the {args.n}^3 dense-sphere workload")
     work = inputs.dense_sphere(args.n, seed=2)
     log("FP64 solve")
-    r64 = run_solver(nn4mg, torch, work, nn4mg.PREC_FP64, args.steps, args.warmup, args.rtol)
+    r64 = run_solver(nn4mg, torch, work, nn4mg.PREC_FP64, args.steps, args.warmup, args.rtol,
+                     autotune=not args.no_autotune)
     value = r64["n"] * r64["cycles"] / r64["dt"] / 1e9
     best, roof, per_kernel = roofline(r64, "fp64")
     model_bytes = cycle_model_bytes(r64["levels"], "fp64")
@@ -198,18 +227,23 @@ def main():
                    "cycles_per_solve": r64["info"].cycles, "precision": "fp64",
                    "relres": r64["info"].relres, "all_converged": r64["all_converged"]},
         "roofline": roof,
-        "roofline_kernel": {"class": best, **per_kernel[best]},
+        "roofline_kernel": {"class": best, **per_kernel[best],
+                            "timing": "HIP events on the solve stream over a second run of the same K steps"},
+        "ms_per_step_profiled": round(r64["dt_prof"] / args.steps * 1e3, 3),
         "fine_kernels": per_kernel,
         "hbm_model_GBps": round(model_bytes * r64["cycles"] / r64["dt"] / 1e9, 1),
         "model_bytes_per_cell_cycle": round(model_bytes / r64["n"], 2),
         "setup_ms": round(r64["setup_ms"], 2),
+        "autotune_ms": round(r64["tune_ms"], 1),
+        "tiles_per_level": r64["tiles"],
         "update_coef_ms": round(r64["update_ms"], 2),
         "paper_context": {"metric": "1/H_s node-cycles/s (Eq. speed)", "value_G": 9.09,
                           "hardware": "NVIDIA A10", "precision": "not stated"},
     }
     if not args.no_mixed:
         log("mixed precision solve (FP32 smoothing, FP64 residual/refinement)")
-        rm = run_solver(nn4mg, torch, work, nn4mg.PREC_FP32_SMOOTH, args.steps, args.warmup, args.rtol)
+        rm = run_solver(nn4mg, torch, work, nn4mg.PREC_FP32_SMOOTH, args.steps, args.warmup, args.rtol,
+                        autotune=not args.no_autotune)
         bm, roofm, pkm = roofline(rm, "mixed")
         out["mixed"] = {"value": round(rm["n"] * rm["cycles"] / rm["dt"] / 1e9, 3),
                         "ms_per_step": round(rm["dt"] / args.steps * 1e3, 3),

@@ -165,18 +165,20 @@ int nn4mg_profile_read(nn4mg_t h, int kclass, int *launches, double *total_ms);
  * classes only. */
 int nn4mg_profile_read_level(nn4mg_t h, int level, int kclass, int *launches, double *total_ms);
 
-/* Launch shape of the stencil kernels of one level: tile width tx (64, 32 or
- * 16 cells along x), ry cell rows per thread (2 or 4; 2 when tx == 16; the
- * tile is tx x ry*256/tx cells in x-y) and the number of z-planes zc (even,
- * >= 2) each workgroup marches.  Any shape gives the same results; only the
- * speed differs.  EINVAL for a bad level or shape. */
-int nn4mg_set_tiles(nn4mg_t h, int level, int tx, int ry, int zc);
-int nn4mg_get_tiles(nn4mg_t h, int level, int *tx, int *ry, int *zc);
+/* Launch shape of one stencil kernel class (NN4MG_KCLASS_*; -1 = all classes
+ * for set) of one level: tile width tx (64, 32 or 16 cells along x), ry cell
+ * rows per thread (2 or 4; 2 when tx == 16; the tile is tx x ry*256/tx cells
+ * in x-y) and the number of z-planes zc (even, >= 2) each workgroup marches.
+ * Any shape gives the same results; only the speed differs.  EINVAL for a bad
+ * level, class or shape. */
+int nn4mg_set_tiles(nn4mg_t h, int level, int kclass, int tx, int ry, int zc);
+int nn4mg_get_tiles(nn4mg_t h, int level, int kclass, int *tx, int *ry, int *zc);
 
-/* Autotuner: for every level, time the candidate launch shapes (tile width,
- * rows per thread, z-chunk) on a few cycles with b_dev and x_dev as input
- * (x_dev is overwritten), keep the fastest shape per level, and return it in
- * tiles_out (3 ints per level: tx, ry, zc; may be NULL).  Synchronous. */
+/* Autotuner: time the candidate launch shapes (tile width, rows per thread,
+ * z-chunk) on a few cycles with b_dev and x_dev as input (x_dev is
+ * overwritten), keep the fastest shape per level and kernel class, and return
+ * them in tiles_out (9 ints per level: tx, ry, zc for each of the 3 classes;
+ * may be NULL).  Synchronous. */
 int nn4mg_autotune(nn4mg_t h, const double *b_dev, double *x_dev, int *tiles_out, int max_levels);
 
 /* Release the hierarchy (synchronises its stream first).  NULL is accepted. */

@@ -49,7 +49,7 @@ struct Level {
     double *k = nullptr;                              // FP64 coefficient
     float *b32 = nullptr, *e32 = nullptr, *t32 = nullptr, *t32b = nullptr;  // FP32 cycle buffers
     void *ks = nullptr;                               // FP32 / FP16 smoothing coefficient
-    TileShape tiles{};
+    TileShape tiles[3]{};  // launch shape per kernel class (NN4MG_KCLASS_*)
 };
 
 // Default launch shape of a level: the tile width that pads the x-y plane
@@ -386,7 +386,7 @@ void prof_close_solve(nn4mg_hier *H, int cycles, bool ran)
     H->prof_solve_begin = H->prof_cls.size();
 }
 
-StencilArgs base_args(const nn4mg_hier *H, int l)
+StencilArgs base_args(const nn4mg_hier *H, int l, int kclass)
 {
     StencilArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -395,7 +395,7 @@ StencilArgs base_args(const nn4mg_hier *H, int l)
     a.g.ny = V.ny;
     a.g.nz = V.nz;
     for (int f = 0; f < 6; ++f) a.g.bc[f] = H->cfg.bc[f];
-    a.t = V.tiles;
+    a.t = V.tiles[kclass];
     a.h = V.h;
     a.omega = H->cfg.omega;
     if (l + 1 < H->L) {
@@ -411,7 +411,7 @@ StencilArgs base_args(const nn4mg_hier *H, int l)
 int enqueue_resid(nn4mg_hier *H, const double *x, const double *b, const double *bmean, void *r_full,
                   void *r_coarse, bool to_f32, bool partials, const int *done)
 {
-    StencilArgs a = base_args(H, 0);
+    StencilArgs a = base_args(H, 0, NN4MG_KCLASS_FINE_RESID);
     a.yin = x;
     a.b = b;
     a.k = H->lv[0].k;
@@ -436,7 +436,7 @@ int enqueue_coarse_sweeps(nn4mg_hier *H, int l, const int *done)
     int cur = (nu % 2 == 1) ? 1 : 0;  // the last sweep must land in e
     const void *in = nullptr;
     for (int s = 0; s < nu; ++s) {
-        StencilArgs a = base_args(H, l);
+        StencilArgs a = base_args(H, l, s == 0 ? NN4MG_KCLASS_FINE_SWEEP_PROLONG : NN4MG_KCLASS_FINE_SWEEP);
         a.b = f64 ? (const void *)V.b : (const void *)V.b32;
         a.k = f64 ? (const void *)V.k : V.ks;
         a.yout = buf[cur];
@@ -467,7 +467,7 @@ int enqueue_fine_sweeps(nn4mg_hier *H, const double *b, const double *bmean, dou
         int cur = 0;
         const void *in = nullptr;
         for (int s = 0; s < nu; ++s) {
-            StencilArgs a = base_args(H, 0);
+            StencilArgs a = base_args(H, 0, s == 0 ? NN4MG_KCLASS_FINE_SWEEP_PROLONG : NN4MG_KCLASS_FINE_SWEEP);
             a.b = b;
             a.bmean = bmean;
             a.k = F.k;
@@ -495,7 +495,7 @@ int enqueue_fine_sweeps(nn4mg_hier *H, const double *b, const double *bmean, dou
     const void *in = nullptr;
     for (int s = 0; s < nu; ++s) {
         const bool last = (s == nu - 1);
-        StencilArgs a = base_args(H, 0);
+        StencilArgs a = base_args(H, 0, s == 0 ? NN4MG_KCLASS_FINE_SWEEP_PROLONG : NN4MG_KCLASS_FINE_SWEEP);
         a.b = F.b32;
         a.k = F.ks;
         a.done = done;
@@ -579,7 +579,7 @@ int enqueue_body(nn4mg_hier *H, const double *b, const double *bmean, double *x,
     return enqueue_cycle_body(H, b, bmean, x, done);
 }
 
-int resid_blocks(const nn4mg_hier *H) { return H->lv[0].tiles.blocks(); }
+int resid_blocks(const nn4mg_hier *H) { return H->lv[0].tiles[NN4MG_KCLASS_FINE_RESID].blocks(); }
 
 }  // namespace
 
@@ -657,8 +657,8 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
         V.nz = cfg->nz >> l;
         V.h = cfg->h * (double)(1 << l);
         V.n = (size_t)V.nx * V.ny * V.nz;
-        V.tiles = default_tiles(V.nx, V.ny, V.nz);
-        if (V.tiles.blocks() > maxblk) maxblk = V.tiles.blocks();
+        for (int c = 0; c < 3; ++c) V.tiles[c] = default_tiles(V.nx, V.ny, V.nz);
+        if (V.tiles[0].blocks() > maxblk) maxblk = V.tiles[0].blocks();
         if (nodal) TRY(dalloc(H, &V.k, V.n));
         const bool single = (H->L == 1);
         if (!H->mixed) {
@@ -739,7 +739,7 @@ size_t nn4mg_bytes_held(nn4mg_t H) { return H ? H->bytes : 0; }
 int nn4mg_residual(nn4mg_t H, const double *x, const double *b, double *r, double *norm2_out)
 {
     if (!H || !x || !b) return fail(NN4MG_EINVAL, "NULL argument");
-    StencilArgs a = base_args(H, 0);
+    StencilArgs a = base_args(H, 0, NN4MG_KCLASS_FINE_RESID);
     a.yin = x;
     a.b = b;
     a.k = H->lv[0].k;
@@ -914,27 +914,31 @@ int nn4mg_profile_read(nn4mg_t H, int kclass, int *launches, double *total_ms)
     return nn4mg_profile_read_level(H, 0, kclass, launches, total_ms);
 }
 
-int nn4mg_set_tiles(nn4mg_t H, int level, int tx, int ry, int zc)
+int nn4mg_set_tiles(nn4mg_t H, int level, int kclass, int tx, int ry, int zc)
 {
     if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
     if (level < 0 || level >= H->L) return fail(NN4MG_EINVAL, "bad level");
+    if (kclass < -1 || kclass >= NN4MG_KCLASS_COUNT) return fail(NN4MG_EINVAL, "bad kernel class");
     if ((tx != 64 && tx != 32 && tx != 16) || (ry != 2 && ry != 4) || (tx == 16 && ry != 2) || zc < 2 || (zc & 1))
         return fail(NN4MG_EINVAL, "bad tile shape");
     Level &V = H->lv[level];
     const TileShape t = make_tiles(V.nx, V.ny, V.nz, zc, tx, ry);
     if (t.blocks() > H->max_partials) return fail(NN4MG_EINVAL, "tile shape needs too many workgroups");
     HIP_TRY(hipStreamSynchronize(H->stream));
-    V.tiles = t;
+    for (int c = 0; c < NN4MG_KCLASS_COUNT; ++c)
+        if (kclass < 0 || kclass == c) V.tiles[c] = t;
     return NN4MG_OK;
 }
 
-int nn4mg_get_tiles(nn4mg_t H, int level, int *tx, int *ry, int *zc)
+int nn4mg_get_tiles(nn4mg_t H, int level, int kclass, int *tx, int *ry, int *zc)
 {
     if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
     if (level < 0 || level >= H->L) return fail(NN4MG_EINVAL, "bad level");
-    if (tx) *tx = H->lv[level].tiles.tx;
-    if (ry) *ry = H->lv[level].tiles.ry;
-    if (zc) *zc = H->lv[level].tiles.zc;
+    if (kclass < 0 || kclass >= NN4MG_KCLASS_COUNT) return fail(NN4MG_EINVAL, "bad kernel class");
+    const TileShape &t = H->lv[level].tiles[kclass];
+    if (tx) *tx = t.tx;
+    if (ry) *ry = t.ry;
+    if (zc) *zc = t.zc;
     return NN4MG_OK;
 }
 
@@ -946,10 +950,19 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
     const int rys[5] = {2, 4, 2, 4, 2};
     const int zcs[5] = {2, 4, 8, 16, 32};
     const int reps = 3;
-    std::vector<double> best(L, 1e300);
-    std::vector<TileShape> best_t(L);
-    for (int l = 0; l < L; ++l) best_t[l] = H->lv[l].tiles;
+    constexpr int NC = NN4MG_KCLASS_COUNT;
+    std::vector<double> best((size_t)L * NC, 1e300);
+    std::vector<TileShape> best_t((size_t)L * NC);
+    for (int l = 0; l < L; ++l)
+        for (int c = 0; c < NC; ++c) best_t[(size_t)l * NC + c] = H->lv[l].tiles[c];
     const bool saved_on = H->prof_on;
+    auto clear = [&]() {
+        H->prof_cls.clear();
+        H->prof_lvl.clear();
+        H->prof_tag.clear();
+        H->prof_valid.clear();
+        H->prof_solve_begin = 0;
+    };
     int rc;
     for (int ti = 0; ti < 5; ++ti)
         for (int zi = 0; zi < 5; ++zi) {
@@ -959,23 +972,17 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
                 if (zcs[zi] > V.nz + (V.nz & 1)) continue;
                 const TileShape t = make_tiles(V.nx, V.ny, V.nz, zcs[zi], txs[ti], rys[ti]);
                 if (t.blocks() > H->max_partials) continue;
-                V.tiles = t;
+                for (int c = 0; c < NC; ++c) V.tiles[c] = t;
                 used[l] = true;
             }
             HIP_TRY(hipStreamSynchronize(H->stream));
             H->prof_on = true;
-            H->prof_cls.clear();
-            H->prof_lvl.clear();
-            H->prof_tag.clear();
-            H->prof_valid.clear();
+            clear();
             H->cur_tag = 0;
             for (int r = 0; r < reps + 1; ++r) {
                 if (r == 1) {  // the first cycle warms caches and code; drop it
                     HIP_TRY(hipStreamSynchronize(H->stream));
-                    H->prof_cls.clear();
-                    H->prof_lvl.clear();
-                    H->prof_tag.clear();
-                    H->prof_valid.clear();
+                    clear();
                 }
                 if ((rc = enqueue_resid_for_cycle(H, b, x, nullptr, false, nullptr))) return rc;
                 if ((rc = enqueue_body(H, b, nullptr, x, nullptr))) return rc;
@@ -983,32 +990,29 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
             H->prof_on = false;
             for (int l = 0; l < L; ++l) {
                 if (!used[l]) continue;
-                double tot = 0.0;
-                for (int cls = 0; cls < NN4MG_KCLASS_COUNT; ++cls) {
+                for (int c = 0; c < NC; ++c) {
                     double ms = 0.0;
                     int n = 0;
-                    if ((rc = nn4mg_profile_read_level(H, l, cls, &n, &ms))) return rc;
-                    tot += ms;
-                }
-                if (tot > 0.0 && tot < best[l]) {
-                    best[l] = tot;
-                    best_t[l] = H->lv[l].tiles;
+                    if ((rc = nn4mg_profile_read_level(H, l, c, &n, &ms))) return rc;
+                    if (n > 0 && ms < best[(size_t)l * NC + c]) {
+                        best[(size_t)l * NC + c] = ms;
+                        best_t[(size_t)l * NC + c] = H->lv[l].tiles[c];
+                    }
                 }
             }
         }
-    for (int l = 0; l < L; ++l) H->lv[l].tiles = best_t[l];
+    for (int l = 0; l < L; ++l)
+        for (int c = 0; c < NC; ++c) H->lv[l].tiles[c] = best_t[(size_t)l * NC + c];
     H->prof_on = saved_on;
-    H->prof_cls.clear();
-    H->prof_lvl.clear();
-    H->prof_tag.clear();
-    H->prof_valid.clear();
-    H->prof_solve_begin = 0;
+    clear();
     if (tiles_out)
-        for (int l = 0; l < L && l < max_levels; ++l) {
-            tiles_out[3 * l] = best_t[l].tx;
-            tiles_out[3 * l + 1] = best_t[l].ry;
-            tiles_out[3 * l + 2] = best_t[l].zc;
-        }
+        for (int l = 0; l < L && l < max_levels; ++l)
+            for (int c = 0; c < NC; ++c) {
+                const TileShape &t = best_t[(size_t)l * NC + c];
+                tiles_out[9 * l + 3 * c] = t.tx;
+                tiles_out[9 * l + 3 * c + 1] = t.ry;
+                tiles_out[9 * l + 3 * c + 2] = t.zc;
+            }
     return NN4MG_OK;
 }
 

@@ -105,9 +105,9 @@ def lib():
     L.nn4mg_profile_read_level.restype = i
     L.nn4mg_profile_read_level.argtypes = [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(d)]
     L.nn4mg_set_tiles.restype = i
-    L.nn4mg_set_tiles.argtypes = [vp, i, i, i, i]
+    L.nn4mg_set_tiles.argtypes = [vp, i, i, i, i, i]
     L.nn4mg_get_tiles.restype = i
-    L.nn4mg_get_tiles.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+    L.nn4mg_get_tiles.argtypes = [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
     L.nn4mg_autotune.restype = i
     L.nn4mg_autotune.argtypes = [vp, vp, vp, ctypes.POINTER(i), i]
     L.nn4mg_destroy.restype = i
@@ -220,18 +220,21 @@ class Hierarchy:
                                               ctypes.byref(ms)))
         return n.value, ms.value
 
-    def set_tiles(self, level: int, tx: int, ry: int, zc: int):
-        _check(lib().nn4mg_set_tiles(self.handle, int(level), int(tx), int(ry), int(zc)))
+    def set_tiles(self, level: int, tx: int, ry: int, zc: int, kclass: int = -1):
+        _check(lib().nn4mg_set_tiles(self.handle, int(level), int(kclass), int(tx), int(ry), int(zc)))
 
-    def get_tiles(self, level: int):
+    def get_tiles(self, level: int, kclass: int = 0):
         tx, ry, zc = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
-        _check(lib().nn4mg_get_tiles(self.handle, int(level), ctypes.byref(tx), ctypes.byref(ry), ctypes.byref(zc)))
+        _check(lib().nn4mg_get_tiles(self.handle, int(level), int(kclass), ctypes.byref(tx), ctypes.byref(ry),
+                                     ctypes.byref(zc)))
         return tx.value, ry.value, zc.value
 
     def autotune(self, b: torch.Tensor, x: torch.Tensor):
-        out = (ctypes.c_int * 48)()
+        """Per level, a list of (tx, ry, zc) per kernel class (resid, first sweep, later sweeps)."""
+        out = (ctypes.c_int * (9 * 16))()
         _check(lib().nn4mg_autotune(self.handle, _field(b, self.n, "b"), _field(x, self.n, "x"), out, 16))
-        return [(out[3 * l], out[3 * l + 1], out[3 * l + 2]) for l in range(len(self.levels()))]
+        return [[(out[9 * l + 3 * c], out[9 * l + 3 * c + 1], out[9 * l + 3 * c + 2]) for c in range(3)]
+                for l in range(len(self.levels()))]
 
     def bytes_held(self) -> int:
         return int(lib().nn4mg_bytes_held(self.handle))
