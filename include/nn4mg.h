@@ -181,6 +181,52 @@ int nn4mg_get_tiles(nn4mg_t h, int level, int kclass, int *tx, int *ry, int *zc)
  * may be NULL).  Synchronous. */
 int nn4mg_autotune(nn4mg_t h, const double *b_dev, double *x_dev, int *tiles_out, int max_levels);
 
+/* ---- Continuous-batching solve server ------------------------------------
+ * Serves the pressure solves of a time-stepping or ensemble workload, each with
+ * its own grid size, coefficient and right-hand side (the paper's solver runs
+ * one pressure solve per stage and per time step, Sec. 2.4).  A worker thread
+ * admits queued requests in arrival order as soon as a slot and enough device
+ * memory are free (the budget counts every resident hierarchy), keeps idle
+ * hierarchies resident for reuse by later requests of the same configuration,
+ * runs each admitted request on its own stream so that the cycles of all
+ * active requests overlap on the device, launches each cycle as a captured
+ * hipGraph, and checks every request's stopping rule asynchronously.  Results
+ * do not depend on which other requests run: every kernel reads only its own
+ * request's data, and reductions have a fixed order. */
+typedef struct nn4mg_server *nn4mg_srv_t;
+
+typedef struct {
+    unsigned long long tag;   /* the caller's tag */
+    nn4mg_info info;          /* as from nn4mg_solve; info.status carries the request's status */
+    double t_submit_ms;       /* host clock, ms since the server was created */
+    double t_start_ms;        /* admitted to a slot */
+    double t_done_ms;         /* x written back and the request completed */
+    size_t bytes;             /* device bytes of the request's hierarchy and work buffers */
+} nn4mg_result;
+
+/* hbm_budget_bytes: device memory the server may hold for hierarchies and
+ * work buffers; max_slots: requests in flight at once (1..64).  The server uses
+ * the current device of the calling thread.  Errors: EINVAL, EDEVICE. */
+int nn4mg_server_create(size_t hbm_budget_bytes, int max_slots, nn4mg_srv_t *out);
+/* Queue one solve of A x = b to rtol (at most max_cycles cycles; stationary
+ * outer iteration).  k_dev (NODAL only), b_dev and x_dev (initial guess in,
+ * solution out) are device arrays the caller keeps alive, and does not touch,
+ * until nn4mg_server_poll returns the tag; their contents must be ready on the
+ * device when this call is made.  Errors: EINVAL (bad config or pointers),
+ * EBUSY (the request alone needs more than the whole budget). */
+int nn4mg_server_submit(nn4mg_srv_t s, const nn4mg_config *cfg, const double *k_dev, const double *b_dev,
+                        double *x_dev, double rtol, int max_cycles, unsigned long long tag);
+/* Non-blocking: move up to cap finished requests into out, *n_done of them. */
+int nn4mg_server_poll(nn4mg_srv_t s, nn4mg_result *out, int cap, int *n_done);
+/* Block until every submitted request has finished (timeout_ms < 0: no limit);
+ * EBUSY on timeout. */
+int nn4mg_server_drain(nn4mg_srv_t s, double timeout_ms);
+/* Device bytes held now and at peak, requests running and queued. */
+int nn4mg_server_stats(nn4mg_srv_t s, size_t *bytes_in_use, size_t *peak_bytes, int *active, int *queued);
+/* Stop the worker after the requests in flight finish (queued ones are
+ * dropped), and free every resident hierarchy. */
+int nn4mg_server_destroy(nn4mg_srv_t s);
+
 /* Release the hierarchy (synchronises its stream first).  NULL is accepted. */
 int nn4mg_destroy(nn4mg_t h);
 

@@ -239,6 +239,17 @@ struct nn4mg_hier {
     double *fcg = nullptr;   // FCG vectors (r, z, p, q) at level 0, FP64
     size_t bytes = 0;
     std::vector<void *> allocs;
+    // captured hipGraph of one stationary iteration (body + residual + stopping rule)
+    hipGraphExec_t graph = nullptr;
+    const double *graph_b = nullptr;
+    double *graph_x = nullptr;
+    bool graphs_ok = true;  // cleared after a capture failure
+    int tiles_epoch = 0, graph_epoch = -1;
+    // async solve bookkeeping
+    double solve_rtol = 0.0;
+    int solve_max = 0, solve_fixed = 0, solve_enqueued = 0, solve_planned = 0;
+    double solve_prev_last = -1.0;
+    std::chrono::steady_clock::time_point solve_t0;
     // kernel timing (nn4mg_profile)
     bool prof_on = false;
     int cur_tag = 0;
@@ -267,6 +278,8 @@ int dalloc(nn4mg_hier *H, P **p, size_t count)
 void release(nn4mg_hier *H)
 {
     if (H->stream) (void)hipStreamSynchronize(H->stream);
+    if (H->graph) (void)hipGraphExecDestroy(H->graph);
+    H->graph = nullptr;
     for (hipEvent_t e : H->prof_ev) (void)hipEventDestroy(e);
     H->prof_ev.clear();
     for (void *p : H->allocs) (void)hipFree(p);
@@ -834,40 +847,142 @@ int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady
     return status;
 }
 
-int solve_stationary(nn4mg_hier *H, const double *b, double *x, double rtol, int max_cycles, int fixed,
-                     nn4mg_info *info)
+// Capture one stationary iteration on the handle's stream as a graph bound to
+// (b, x).  Returns false (and launches nothing) if capture is not possible.
+bool capture_iteration(nn4mg_hier *H, const double *b, double *x)
 {
-    const auto t0 = std::chrono::steady_clock::now();
+    if (!H->graphs_ok || H->stream == nullptr || H->prof_on) return false;
+    if (H->graph && H->graph_b == b && H->graph_x == x && H->graph_epoch == H->tiles_epoch) return true;
+    if (H->graph) {
+        (void)hipGraphExecDestroy(H->graph);
+        H->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(H->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        H->graphs_ok = false;
+        return false;
+    }
+    const int saved_tag = H->cur_tag;
+    const int rc = enqueue_stationary_iteration(H, b, x);
+    H->cur_tag = saved_tag;
+    const hipError_t e = hipStreamEndCapture(H->stream, &g);
+    if (rc != NN4MG_OK || e != hipSuccess || !g) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        H->graphs_ok = false;
+        return false;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        (void)hipGetLastError();
+        H->graphs_ok = false;
+        return false;
+    }
+    H->graph = ex;
+    H->graph_b = b;
+    H->graph_x = x;
+    H->graph_epoch = H->tiles_epoch;
+    return true;
+}
+
+}  // namespace
+
+namespace nn4mg {
+
+// ---- asynchronous solve pieces (used by nn4mg_solve and the server) ----
+
+int solve_begin(nn4mg_hier *H, const double *b, double *x, double rtol, int max_cycles, int fixed)
+{
     hipStream_t s = H->stream;
     int rc;
+    H->solve_t0 = std::chrono::steady_clock::now();
+    H->solve_rtol = rtol;
+    H->solve_max = max_cycles;
+    H->solve_fixed = fixed;
+    H->solve_enqueued = 0;
+    H->solve_prev_last = -1.0;
+    H->solve_planned = fixed ? max_cycles : (max_cycles < 4 ? max_cycles : 4);
     HIP_TRY(launch_init_state(H->st, rtol, max_cycles, fixed, s));
     H->cur_tag = 0;
     H->prof_solve_begin = H->prof_cls.size();
     if ((rc = enqueue_b_norm(H, b))) return rc;
     if ((rc = enqueue_resid_for_cycle(H, b, x, H->singular ? &H->st->bmean : nullptr, true, &H->st->done))) return rc;
     HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), s));
-    int enqueued = 0;
-    int planned = fixed ? max_cycles : (max_cycles < 4 ? max_cycles : 4);
-    double prev_last = -1.0;
-    StateHeader hd;
-    while (true) {
-        for (int c = 0; c < planned; ++c)
+    return NN4MG_OK;
+}
+
+// Enqueue the next planned batch of cycles (as graph launches when possible).
+int solve_enqueue_next(nn4mg_hier *H, const double *b, double *x)
+{
+    int rc;
+    const int n = H->solve_planned;
+    if (n <= 0) return NN4MG_OK;
+    if (capture_iteration(H, b, x)) {
+        for (int c = 0; c < n; ++c) HIP_TRY(hipGraphLaunch(H->graph, H->stream));
+        H->cur_tag += n;
+    } else {
+        for (int c = 0; c < n; ++c)
             if ((rc = enqueue_stationary_iteration(H, b, x))) return rc;
-        enqueued += planned;
-        if ((rc = read_header(H, &hd))) return rc;
-        if (hd.done || enqueued >= max_cycles) break;
-        const int remaining = max_cycles - enqueued;
-        int need = 4;
-        if (prev_last > 0.0 && hd.last > 0.0 && hd.last < prev_last) {
-            const double rate = std::pow(hd.last / prev_last, 1.0 / planned);
-            if (rate > 0.0 && rate < 1.0) need = (int)std::ceil(std::log(rtol / hd.last) / std::log(rate));
-        }
-        if (need < 1) need = 1;
-        if (need > 64) need = 64;
-        prev_last = hd.last;
-        planned = need < remaining ? need : remaining;
     }
-    return finish_solve(H, x, info, t0);
+    H->solve_enqueued += n;
+    return NN4MG_OK;
+}
+
+int solve_header_async(nn4mg_hier *H, hipEvent_t ev)
+{
+    HIP_TRY(hipMemcpyAsync(H->st_host, H->st, sizeof(StateHeader), hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipEventRecord(ev, H->stream));
+    return NN4MG_OK;
+}
+
+// After the header copy completed: 1 if the solve is finished, else plan the
+// next batch from the observed convergence rate and return 0.
+int solve_after_header(nn4mg_hier *H)
+{
+    StateHeader hd;
+    std::memcpy(&hd, H->st_host, sizeof(StateHeader));
+    if (hd.done || H->solve_enqueued >= H->solve_max) return 1;
+    const int remaining = H->solve_max - H->solve_enqueued;
+    int need = 4;
+    if (H->solve_prev_last > 0.0 && hd.last > 0.0 && hd.last < H->solve_prev_last) {
+        const double rate = std::pow(hd.last / H->solve_prev_last, 1.0 / (H->solve_planned > 0 ? H->solve_planned : 1));
+        if (rate > 0.0 && rate < 1.0) need = (int)std::ceil(std::log(H->solve_rtol / hd.last) / std::log(rate));
+    }
+    if (need < 1) need = 1;
+    if (need > 64) need = 64;
+    H->solve_prev_last = hd.last;
+    H->solve_planned = need < remaining ? need : remaining;
+    return 0;
+}
+
+int solve_finish(nn4mg_hier *H, double *x, nn4mg_info *info) { return finish_solve(H, x, info, H->solve_t0); }
+
+int hier_set_stream(nn4mg_hier *H, hipStream_t s)
+{
+    if (H->stream) HIP_TRY(hipStreamSynchronize(H->stream));
+    H->stream = s;
+    return NN4MG_OK;
+}
+
+}  // namespace nn4mg
+
+namespace {
+
+int solve_stationary(nn4mg_hier *H, const double *b, double *x, double rtol, int max_cycles, int fixed,
+                     nn4mg_info *info)
+{
+    int rc;
+    if ((rc = nn4mg::solve_begin(H, b, x, rtol, max_cycles, fixed))) return rc;
+    while (true) {
+        if ((rc = nn4mg::solve_enqueue_next(H, b, x))) return rc;
+        StateHeader hd;
+        if ((rc = read_header(H, &hd))) return rc;
+        if (nn4mg::solve_after_header(H)) break;
+    }
+    return finish_solve(H, x, info, H->solve_t0);
 }
 
 }  // namespace
@@ -927,6 +1042,7 @@ int nn4mg_set_tiles(nn4mg_t H, int level, int kclass, int tx, int ry, int zc)
     HIP_TRY(hipStreamSynchronize(H->stream));
     for (int c = 0; c < NN4MG_KCLASS_COUNT; ++c)
         if (kclass < 0 || kclass == c) V.tiles[c] = t;
+    H->tiles_epoch++;
     return NN4MG_OK;
 }
 
@@ -1003,6 +1119,7 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
         }
     for (int l = 0; l < L; ++l)
         for (int c = 0; c < NC; ++c) H->lv[l].tiles[c] = best_t[(size_t)l * NC + c];
+    H->tiles_epoch++;
     H->prof_on = saved_on;
     clear();
     if (tiles_out)

@@ -1,6 +1,8 @@
 // Internal declarations of the nn4mg HIP library (not part of the C-ABI).
 #pragma once
 
+#include "../../include/nn4mg.h"
+
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -116,5 +118,18 @@ hipError_t launch_fill(double *x, size_t n, double v, hipStream_t s);
 hipError_t launch_copy(double *dst, const double *src, size_t n, const int *done, hipStream_t s);
 // x += e (e FP64, or FP32 when e_f32)
 hipError_t launch_add(double *x, const void *e, int e_f32, size_t n, const int *done, hipStream_t s);
+
+// ---- asynchronous solve pieces over a hierarchy (mg_api.hip) ----
+// begin: reset the device state, b-norm, first residual; enqueue_next: the next
+// planned batch of cycles (graph launches when the stream allows capture);
+// header_async: copy the state header to pinned host memory and record ev;
+// after_header (once ev completed): 1 when finished, else plans the next batch;
+// finish: projection / zero fill, full state read-back (synchronous).
+int solve_begin(nn4mg_hier *H, const double *b, double *x, double rtol, int max_cycles, int fixed);
+int solve_enqueue_next(nn4mg_hier *H, const double *b, double *x);
+int solve_header_async(nn4mg_hier *H, hipEvent_t ev);
+int solve_after_header(nn4mg_hier *H);
+int solve_finish(nn4mg_hier *H, double *x, nn4mg_info *info);
+int hier_set_stream(nn4mg_hier *H, hipStream_t s);
 
 }  // namespace nn4mg

@@ -67,6 +67,15 @@ class Info(ctypes.Structure):
         return [self.hist[i] for i in range(self.hist_len)]
 
 
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_ulonglong),
+        ("info", Info),
+        ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+        ("bytes", ctypes.c_size_t),
+    ]
+
+
 _lib = None
 
 
@@ -110,6 +119,18 @@ def lib():
     L.nn4mg_get_tiles.argtypes = [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
     L.nn4mg_autotune.restype = i
     L.nn4mg_autotune.argtypes = [vp, vp, vp, ctypes.POINTER(i), i]
+    L.nn4mg_server_create.restype = i
+    L.nn4mg_server_create.argtypes = [sz, i, ctypes.POINTER(vp)]
+    L.nn4mg_server_submit.restype = i
+    L.nn4mg_server_submit.argtypes = [vp, cfgp, vp, vp, vp, d, i, ctypes.c_ulonglong]
+    L.nn4mg_server_poll.restype = i
+    L.nn4mg_server_poll.argtypes = [vp, ctypes.POINTER(Result), i, ctypes.POINTER(i)]
+    L.nn4mg_server_drain.restype = i
+    L.nn4mg_server_drain.argtypes = [vp, d]
+    L.nn4mg_server_stats.restype = i
+    L.nn4mg_server_stats.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(i), ctypes.POINTER(i)]
+    L.nn4mg_server_destroy.restype = i
+    L.nn4mg_server_destroy.argtypes = [vp]
     L.nn4mg_destroy.restype = i
     L.nn4mg_destroy.argtypes = [vp]
     L.nn4mg_last_error.restype = ctypes.c_char_p
@@ -243,6 +264,55 @@ class Hierarchy:
         if getattr(self, "_h", None):
             lib().nn4mg_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching solve server (nn4mg_server_*).  Tensors passed to
+    submit() must stay alive and untouched until poll() returns their tag."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4):
+        h = ctypes.c_void_p()
+        _check(lib().nn4mg_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, cfg: Config, b: torch.Tensor, x: torch.Tensor, k: torch.Tensor | None = None,
+               rtol: float = 1e-8, max_cycles: int = 1000, tag: int = 0):
+        n = cfg.nx * cfg.ny * cfg.nz
+        kp = _field(k, n, "k") if k is not None else None
+        _check(lib().nn4mg_server_submit(self._h, ctypes.byref(cfg), kp, _field(b, n, "b"), _field(x, n, "x"),
+                                         float(rtol), int(max_cycles), int(tag)))
+        self._keep[int(tag)] = (cfg, b, x, k)
+
+    def poll(self, cap: int = 256):
+        out = (Result * cap)()
+        nd = ctypes.c_int(0)
+        _check(lib().nn4mg_server_poll(self._h, out, cap, ctypes.byref(nd)))
+        res = [out[i] for i in range(nd.value)]
+        for r in res:
+            self._keep.pop(int(r.tag), None)
+        return res
+
+    def drain(self, timeout_ms: float = -1.0):
+        _check(lib().nn4mg_server_drain(self._h, float(timeout_ms)))
+
+    def stats(self):
+        a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        act, q = ctypes.c_int(0), ctypes.c_int(0)
+        _check(lib().nn4mg_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(act), ctypes.byref(q)))
+        return dict(bytes_in_use=a.value, peak_bytes=b.value, active=act.value, queued=q.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nn4mg_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

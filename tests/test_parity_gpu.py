@@ -226,3 +226,32 @@ def test_invalid_configs_rejected(mg):
     k[3, 3, 3] = 0.0
     with pytest.raises(mg.Nn4mgError):  # non-positive k
         mg.Hierarchy(cfg, dev(k))
+
+
+def test_graph_replays_match_direct_launches(mg):
+    """On a non-default stream each cycle is a replay of a captured hipGraph;
+    on the default stream the kernels are launched one by one.  Several solves
+    (many replays each, with eager torch work in between) must reproduce the
+    direct result bitwise."""
+    import torch
+
+    w = inputs.dense_sphere(48, seed=2)
+    cfg = mg.config_default(48, 48, 48, w["h"], bc=w["bc"], coef_mode=1)
+    k, b = dev(w["k"]), dev(w["b"])
+    H1 = mg.Hierarchy(cfg, k)
+    x1 = dev(np.zeros_like(w["b"]))
+    info1 = H1.solve(b, x1, rtol=1e-8, max_cycles=500)
+    ref = x1.cpu().numpy()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    H2 = mg.Hierarchy(cfg, k, stream=s)
+    for rep in range(3):
+        x2 = dev(np.zeros_like(w["b"]))
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        info2 = H2.solve(b, x2, rtol=1e-8, max_cycles=500)
+        torch.cuda.synchronize()
+        assert info2.cycles == info1.cycles and info2.status == 0
+        assert np.array_equal(x2.cpu().numpy(), ref), rep
+        assert info2.history() == info1.history()
+        del junk

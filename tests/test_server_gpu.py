@@ -1,0 +1,99 @@
+"""Continuous-batching server: every result is bitwise identical alone and in
+the mix (stated tolerance 0: kernels read only their own request's data and
+all reductions have a fixed order), the HBM budget is respected, and served
+results satisfy the FP64 system to rtol (oracle residual)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_06755_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_06755_amd import nn4mg
+
+    nn4mg.lib()
+    return nn4mg
+
+
+def make_requests(mg, count, edges=(32, 48, 64), precision=1):
+    import torch
+
+    reqs = []
+    for i in range(count):
+        w = inputs.served_request(i, base_seed=4000, edges=edges)
+        n = w["edge"]
+        cfg = mg.config_default(n, n, n, w["h"], bc=w["bc"], coef_mode=1, precision=precision)
+        k = torch.from_numpy(w["k"].reshape(-1)).cuda()
+        b = torch.from_numpy(w["b"].reshape(-1)).cuda()
+        reqs.append((cfg, k, b, w))
+    torch.cuda.synchronize()
+    return reqs
+
+
+def serve(mg, reqs, budget, slots, one_at_a_time=False):
+    import torch
+
+    srv = mg.Server(budget, slots)
+    xs = [torch.zeros_like(b) for (_, _, b, _) in reqs]
+    torch.cuda.synchronize()
+    results = {}
+    for i, (cfg, k, b, _) in enumerate(reqs):
+        srv.submit(cfg, b, xs[i], k=k, rtol=1e-8, max_cycles=2000, tag=i)
+        if one_at_a_time:
+            srv.drain()
+            for r in srv.poll():
+                results[r.tag] = r
+    srv.drain()
+    for r in srv.poll():
+        results[r.tag] = r
+    stats = srv.stats()
+    srv.close()
+    return [x.cpu().numpy() for x in xs], results, stats
+
+
+def test_alone_vs_mix_bitwise_identical(mg):
+    reqs = make_requests(mg, 10)
+    alone, res_a, _ = serve(mg, reqs, budget=8 << 30, slots=1, one_at_a_time=True)
+    mixed, res_m, stats = serve(mg, reqs, budget=8 << 30, slots=4)
+    assert len(res_a) == len(res_m) == len(reqs)
+    for i in range(len(reqs)):
+        assert res_a[i].info.status == 0 and res_m[i].info.status == 0
+        assert res_a[i].info.cycles == res_m[i].info.cycles
+        assert np.array_equal(alone[i], mixed[i]), i
+    assert stats["peak_bytes"] <= 8 << 30
+
+
+def test_budget_admission_and_oracle_residual(mg):
+    reqs = make_requests(mg, 8, edges=(32, 48))
+    sizes = [mg.bytes_required(c) + 16 * c.nx * c.ny * c.nz for (c, _, _, _) in reqs]
+    budget = int(max(sizes) * 1.5)  # at most one or two hierarchies fit at once
+    xs, res, stats = serve(mg, reqs, budget=budget, slots=4)
+    assert stats["peak_bytes"] <= budget
+    for i, (cfg, _, _, w) in enumerate(reqs):
+        assert res[i].info.status == 0
+        assert res[i].t_submit_ms <= res[i].t_start_ms <= res[i].t_done_ms
+        x = xs[i].reshape(w["b"].shape)
+        bb = w["b"] - w["b"].mean()
+        r = bb - oracle.apply(x, w["h"], w["bc"], w["k"])
+        assert np.linalg.norm(r) <= 1.05e-8 * np.linalg.norm(bb)
+        assert abs(x.mean()) <= 1e-12 * np.abs(x).max()
+
+
+def test_oversize_request_rejected(mg):
+    import torch
+
+    srv = mg.Server(1 << 20, 2)
+    cfg = mg.config_default(64, 64, 64, 1 / 64)
+    b = torch.zeros(64 ** 3, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(mg.Nn4mgError):
+        srv.submit(cfg, b, x, tag=1)
+    srv.close()
