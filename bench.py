@@ -13,9 +13,10 @@ resident; its cost is reported separately.
 
 Prints one JSON line: value = finest cells x V-cycles / second / 1e9
 (Gcell-updates/s), the roofline figure of the dominant kernel from HIP events
-recorded on the solve stream over the timed region, the FP32-smoothing /
-FP64-refinement solve of the same workload beside it, and the FP64 oracle timed
-on the host on one V-cycle of the same workload.
+recorded on the solve stream, the FP32-smoothing / FP64-refinement solve of
+the same workload beside it, the served stream of 512 solves of uneven sizes
+(solves/s, p50/p99 latency), and the FP64 oracle timed on the host on one
+V-cycle of the same workload.
 """
 from __future__ import annotations
 
@@ -149,6 +150,88 @@ def roofline(res, mode):
                   "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None}, per_kernel
 
 
+def percentile(v, p):
+    import numpy as np
+
+    return float(np.percentile(np.asarray(v), p)) if len(v) else None
+
+
+def serving_bench(nn4mg, torch, n_requests, budget_gib, slots, seed_base=4000):
+    """Served stream: n_requests variable-coefficient solves (cube edges drawn
+    from {32, 48, 64, 96, 128}, random dense sphere, Neumann walls), FP32
+    smoothing + FP64 refinement to rtol 1e-8.  First closed loop (everything
+    submitted at once) for the capacity, then open loop with Poisson arrivals
+    at 0.7 x that capacity; latency = completion - arrival."""
+    import numpy as np
+
+    from paper_2401_06755_amd import inputs
+
+    t0 = time.perf_counter()
+    reqs = []
+    for i in range(n_requests):
+        w = inputs.served_request(i, base_seed=seed_base)
+        n = w["edge"]
+        cfg = nn4mg.config_default(n, n, n, w["h"], bc=w["bc"], coef_mode=nn4mg.COEF_NODAL,
+                                   precision=nn4mg.PREC_FP32_SMOOTH)
+        reqs.append((cfg, torch.from_numpy(w["k"].reshape(-1)).cuda(), torch.from_numpy(w["b"].reshape(-1)).cuda()))
+    torch.cuda.synchronize()
+    cells = sum(c.nx * c.ny * c.nz for c, _, _ in reqs)
+    log(f"  generated {n_requests} requests ({cells / n_requests:.0f} cells mean) in {time.perf_counter() - t0:.1f} s")
+    budget = int(budget_gib * 2 ** 30)
+
+    def run(arrivals):
+        srv = nn4mg.Server(budget, slots)
+        xs = [torch.zeros_like(b) for _, _, b in reqs]
+        torch.cuda.synchronize()
+        results = []
+        start = time.perf_counter()
+        nxt = 0
+        last_log = start
+        while len(results) < len(reqs):
+            now = time.perf_counter() - start
+            while nxt < len(reqs) and arrivals[nxt] <= now:
+                cfg, k, b = reqs[nxt]
+                srv.submit(cfg, b, xs[nxt], k=k, rtol=1e-8, max_cycles=2000, tag=nxt)
+                nxt += 1
+            results.extend(srv.poll())
+            if time.perf_counter() - last_log > 20:
+                log(f"    {len(results)}/{len(reqs)} served")
+                last_log = time.perf_counter()
+            if nxt < len(reqs) and arrivals[nxt] > now:
+                time.sleep(min(5e-4, arrivals[nxt] - now))
+            else:
+                time.sleep(2e-4)
+        wall = time.perf_counter() - start
+        st = srv.stats()
+        srv.close()
+        lat = [r.t_done_ms - r.t_submit_ms for r in results]
+        ok = sum(1 for r in results if r.info.status == 0)
+        cyc = [r.info.cycles for r in results]
+        return dict(wall=wall, lat=lat, ok=ok, cycles=cyc, peak=st["peak_bytes"])
+
+    closed = run([0.0] * len(reqs))
+    capacity = len(reqs) / closed["wall"]
+    rate = 0.7 * capacity
+    rng = np.random.default_rng(seed_base)
+    arrivals = list(np.cumsum(rng.exponential(1.0 / rate, size=len(reqs))))
+    opened = run(arrivals)
+    return {"requests": len(reqs), "mean_cells": round(cells / len(reqs)),
+            "precision": "f32 smoothing + f64 residual/coarsest/refinement", "rtol": 1e-8,
+            "hbm_budget_GiB": budget_gib, "slots": slots,
+            "closed_loop": {"solves_per_s": round(capacity, 2), "wall_s": round(closed["wall"], 3),
+                            "p50_ms": round(percentile(closed["lat"], 50), 2),
+                            "p99_ms": round(percentile(closed["lat"], 99), 2), "converged": closed["ok"],
+                            "peak_GiB": round(closed["peak"] / 2 ** 30, 3)},
+            "open_loop": {"arrival_rate_per_s": round(rate, 2),
+                          "solves_per_s": round(len(reqs) / opened["wall"], 2),
+                          "p50_ms": round(percentile(opened["lat"], 50), 2),
+                          "p99_ms": round(percentile(opened["lat"], 99), 2), "converged": opened["ok"],
+                          "peak_GiB": round(opened["peak"] / 2 ** 30, 3)},
+            "mean_cycles": round(float(np.mean(closed["cycles"])), 1),
+            "gcell_updates_per_s_closed": round(sum(c.nx * c.ny * c.nz * cy for (c, _, _), cy in
+                                                    zip(reqs, closed["cycles"])) / closed["wall"] / 1e9, 3)}
+
+
 def cpu_baseline(work):
     """One FP64 V-cycle of the same workload in the oracle (single-threaded C)."""
     import numpy as np
@@ -177,6 +260,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512, help="served-stream requests (0: skip)")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -251,6 +337,9 @@ def main():
                         "speedup_vs_fp64_solve": round(r64["dt"] / rm["dt"], 3),
                         "dtype": "f32 smoothing + f64 residual/coarsest/refinement",
                         "roofline": roofm, "roofline_kernel": bm, "fine_kernels": pkm}
+    if args.serve_requests > 0:
+        log(f"served stream: {args.serve_requests} requests")
+        out["serving"] = serving_bench(nn4mg, torch, args.serve_requests, args.serve_budget_gib, args.serve_slots)
     if not args.no_cpu_baseline:
         log("CPU baseline: oracle, one V-cycle")
         out["cpu_baseline"] = cpu_baseline(work)
