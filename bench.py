@@ -44,6 +44,13 @@ BYTES_PER_CELL = {
 }
 KCLASS = {"resid": 0, "sweep_prolong": 1, "sweep": 2}
 
+# HBM bytes per finest-level launch (256^3, FP64, nodal k) from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for
+# a plain 256 MiB device copy (fetch x2.0, write x1.0); the commands and raw
+# counts are in profiles/dense_sphere_256_fp64_fine_kernels.md.  Valid for the
+# stencil kernel as profiled; set to None when the kernel changes.
+MEASURED_TRAFFIC_FP64_256 = {"resid": 440.8e6, "sweep_prolong": 572.9e6, "sweep": 551.7e6}
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -129,7 +136,7 @@ def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol, autotune=True
                 all_converged=all(i.status == 0 for i in infos))
 
 
-def roofline(res, mode):
+def roofline(res, mode, traffic=None):
     best = None
     for name, (cnt, ms) in res["kern"].items():
         if cnt == 0:
@@ -146,8 +153,9 @@ def roofline(res, mode):
             a = BYTES_PER_CELL[mode][name] * res["n"] / (m / c / 1e3) / 1e9
             per_kernel[name] = {"launches": c, "avg_us": round(m / c * 1e3, 2), "GBps": round(a, 1),
                                 "bytes_per_cell": BYTES_PER_CELL[mode][name]}
+    tr = traffic.get(best) if traffic else None
     return best, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                  "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None}, per_kernel
+                  "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": tr}, per_kernel
 
 
 def percentile(v, p):
@@ -291,7 +299,8 @@ def main():
     r64 = run_solver(nn4mg, torch, work, nn4mg.PREC_FP64, args.steps, args.warmup, args.rtol,
                      autotune=not args.no_autotune)
     value = r64["n"] * r64["cycles"] / r64["dt"] / 1e9
-    best, roof, per_kernel = roofline(r64, "fp64")
+    best, roof, per_kernel = roofline(r64, "fp64",
+                                      MEASURED_TRAFFIC_FP64_256 if args.n == 256 else None)
     model_bytes = cycle_model_bytes(r64["levels"], "fp64")
     out = {
         "metric": "V-cycle Gcell-updates/s (solve to relative residual 1e-8)",
