@@ -81,10 +81,51 @@ def lib():
     return _lib
 
 
+class StepParams(ctypes.Structure):
+    """Physical constants and iteration counts of one time step (Sec. 2.4)."""
+    _fields_ = [("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double), ("mu_l", ctypes.c_double),
+                ("mu_g", ctypes.c_double), ("g", ctypes.c_double), ("sigma_t", ctypes.c_double),
+                ("dt", ctypes.c_double), ("mg_cycles", ctypes.c_int), ("n_corr", ctypes.c_int),
+                ("n_vel_iter", ctypes.c_int)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("relres", ctypes.c_double * 8), ("solves", ctypes.c_int)]
+
+
 def _declare_step(L):
     dp = ctypes.POINTER(ctypes.c_double)
     L.or_step.restype = ctypes.c_int
-    L.or_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_void_p]
+    L.or_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(StepParams),
+                          dp, dp, dp, dp, dp, dp, ctypes.POINTER(StepInfo)]
+    L.or_step_filters.restype = None
+    L.or_step_filters.argtypes = [ctypes.c_double, dp, dp, dp, dp]
+
+
+def step_params(rho_l=1000.0, rho_g=1.0, mu_l=1e-3, mu_g=1.8e-5, g=9.81, sigma_t=0.07, dt=1e-4, mg_cycles=20,
+                n_corr=2, n_vel_iter=2):
+    return StepParams(rho_l, rho_g, mu_l, mu_g, g, sigma_t, dt, mg_cycles, n_corr, n_vel_iter)
+
+
+def step(state, h, params=None):
+    """One time step in place on a dict of (nz, ny, nx) float64 arrays
+    C, u, v, w, p_hs, p_nh; returns the relative residuals of the pressure solves."""
+    params = params or step_params()
+    arrs = [state[k] for k in ("C", "u", "v", "w", "p_hs", "p_nh")]
+    for a in arrs:
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    nz, ny, nx = arrs[0].shape
+    info = StepInfo()
+    rc = lib().or_step(nx, ny, nz, float(h), ctypes.byref(params), *[_d(a) for a in arrs], ctypes.byref(info))
+    if rc != 0:
+        raise RuntimeError("oracle step failed")
+    return [info.relres[i] for i in range(info.solves)]
+
+
+def step_filters(h):
+    wx, wm, wpg, wl = (np.empty(27) for _ in range(4))
+    lib().or_step_filters(float(h), _d(wx), _d(wm), _d(wpg), _d(wl))
+    return wx.reshape(3, 3, 3), wm.reshape(3, 3, 3), wpg.reshape(3, 3, 3), wl.reshape(3, 3, 3)
 
 
 def _d(a: np.ndarray):
