@@ -240,6 +240,44 @@ def serving_bench(nn4mg, torch, n_requests, budget_gib, slots, seed_base=4000):
                                                     zip(reqs, closed["cycles"])) / closed["wall"] / 1e9, 3)}
 
 
+def step_bench(nn4mg, torch, n, steps):
+    """One full two-phase time step (Sec. 2.4 Stages 1-4) on the n^3 collapsing
+    water column (water/air, 20 cycles x 3 pressure solves), each timed step
+    starting from the same initial state; device time from HIP events, split
+    into the pressure solves (H) and the explicit momentum/volume-fraction
+    stencils (M) like Eq. speed."""
+    import numpy as np
+
+    from paper_2401_06755_amd import inputs
+
+    h, st = inputs.water_block(n)
+    init = {k: torch.from_numpy(np.ascontiguousarray(st[k]).reshape(-1)).cuda() for k in nn4mg.STEP_FIELDS}
+    dev = {k: torch.empty_like(v) for k, v in init.items()}
+    S = nn4mg.Stepper(n, n, n, h, nn4mg.step_params())
+    tot, mg = [], []
+    for i in range(steps + 1):
+        for k in dev:
+            dev[k].copy_(init[k])
+        info = S.step(dev)
+        if i > 0:
+            tot.append(info.ms_total)
+            mg.append(info.ms_mg)
+    S.close()
+    t, m = float(np.median(tot)), float(np.median(mg))
+    cells = n ** 3
+    p = nn4mg.step_params()
+    cycles = p.mg_cycles * (1 + p.n_corr)
+    return {"workload": f"collapsing water column {n}^3 (block [0,0.25]x[0,1]x[0,0.5]), water/air, "
+                        f"dt 1e-4, {p.n_vel_iter} predictor iterations, {p.n_corr} corrections, "
+                        f"{p.mg_cycles} cycles per pressure solve",
+            "ms_per_step": round(t, 3), "ms_pressure_solves": round(m, 3), "ms_explicit": round(t - m, 3),
+            "solve_share": round(m / t, 3), "steps_timed": steps,
+            "M_s": (t - m) * 1e-3 / cells, "H_s": m * 1e-3 / (cycles * cells),
+            "relres": [info.relres[i] for i in range(info.solves)],
+            "paper_context": {"M_s": 1.2e-8, "H_s": 1.1e-10, "hardware": "NVIDIA A10",
+                              "note": "Eq. speed coefficients: seconds per node (times polynomial order p; here p = 1)"}}
+
+
 def cpu_baseline(work):
     """One FP64 V-cycle of the same workload in the oracle (single-threaded C)."""
     import numpy as np
@@ -271,6 +309,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512, help="served-stream requests (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--step-n", type=int, default=128, help="time-step grid edge (0: skip)")
+    ap.add_argument("--step-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -349,6 +389,9 @@ def main():
     if args.serve_requests > 0:
         log(f"served stream: {args.serve_requests} requests")
         out["serving"] = serving_bench(nn4mg, torch, args.serve_requests, args.serve_budget_gib, args.serve_slots)
+    if args.step_n > 0:
+        log(f"time step: {args.step_n}^3 collapsing column")
+        out["step"] = step_bench(nn4mg, torch, args.step_n, args.step_steps)
     if not args.no_cpu_baseline:
         log("CPU baseline: oracle, one V-cycle")
         out["cpu_baseline"] = cpu_baseline(work)

@@ -227,6 +227,54 @@ int nn4mg_server_stats(nn4mg_srv_t s, size_t *bytes_in_use, size_t *peak_bytes, 
  * dropped), and free every resident hierarchy. */
 int nn4mg_server_destroy(nn4mg_srv_t s);
 
+/* ---- One two-phase time step (Sec. 2.4, Stages 1-4) -----------------------
+ * The explicit momentum and compressive volume-of-fluid stencils around the
+ * three pressure solves of one step, with linear (p = 1) filters on a uniform
+ * grid: Stage 1 the hydrostatic + surface-tension pressure (Eq. ph_disc),
+ * Stage 2 n_vel_iter Petrov-Galerkin velocity predictor iterations
+ * (Eqs. Petrov, k_Psi-n, velocity-1), Stage 3 n_corr non-hydrostatic
+ * corrections (Eqs. ph_disc2, vel-cor), Stage 4 the volume fraction update
+ * (Eqs. Petrov-C, transport-indicator-1) with the compressive coefficients of
+ * Sec. 2.3.5.  Boundaries are those of the paper's tank (Sec. 3.1): free-slip
+ * walls on the sides and the bottom, an outlet on top with zero pressure;
+ * C and rho zero-normal-derivative; hydrostatic pressure gradient -rho g at
+ * the bottom.  Each pressure solve runs a fixed number of cycles (Sec. 2.4). */
+typedef struct nn4mg_stepper *nn4mg_step_t;
+
+typedef struct {
+    double rho_l, rho_g;  /* densities of fluid (C = 1) and gas (C = 0) */
+    double mu_l, mu_g;    /* dynamic viscosities */
+    double g;             /* gravity, acting in -z */
+    double sigma_t;       /* surface tension coefficient */
+    double dt;            /* time step */
+    int mg_cycles;        /* cycles per pressure solve (paper: 20) */
+    int n_corr;           /* pressure-velocity corrections (paper: 2) */
+    int n_vel_iter;       /* velocity predictor iterations (paper: 2) */
+    int reserved[5];      /* zero */
+} nn4mg_step_params;
+
+typedef struct {
+    int solves;           /* pressure solves run (1 + n_corr) */
+    double relres[8];     /* final relative residual of each */
+    double ms_total;      /* device time of the step (HIP events) */
+    double ms_mg;         /* device time inside the pressure solves */
+} nn4mg_step_info;
+
+/* Water/air defaults: rho 1000/1, mu 1e-3/1.8e-5, g 9.81, sigma 0.07, dt 1e-4,
+ * 20 cycles, 2 corrections, 2 predictor iterations. */
+void nn4mg_step_params_default(nn4mg_step_params *p);
+/* Workspace for an nx x ny x nz grid of spacing h (each dim >= 4, even and
+ * coarsenable like nn4mg_setup's grids).  Errors: EINVAL, ENOMEM, EDEVICE. */
+int nn4mg_step_create(int nx, int ny, int nz, double h, const nn4mg_step_params *p, void *hip_stream,
+                      nn4mg_step_t *out);
+/* Advance the caller's device fields (nx*ny*nz doubles each, updated in
+ * place) by one step: C volume fraction, u v w velocity, p_hs hydrostatic and
+ * surface-tension pressure (also the initial guess of its solve), p_nh
+ * non-hydrostatic pressure.  Synchronous. */
+int nn4mg_step(nn4mg_step_t s, double *C, double *u, double *v, double *w, double *p_hs, double *p_nh,
+               nn4mg_step_info *info);
+int nn4mg_step_destroy(nn4mg_step_t s);
+
 /* Release the hierarchy (synchronises its stream first).  NULL is accepted. */
 int nn4mg_destroy(nn4mg_t h);
 

@@ -626,6 +626,7 @@ size_t nn4mg_bytes_required(const nn4mg_config *cfg)
 
 const char *nn4mg_last_error(void) { return g_err.c_str(); }
 
+
 int nn4mg_destroy(nn4mg_t h)
 {
     if (!h) return NN4MG_OK;
@@ -1151,3 +1152,5 @@ int nn4mg_solve(nn4mg_t H, const double *b, double *x, double rtol, int max_cycl
 }
 
 }  // extern "C"
+
+int nn4mg::set_error(int code, const char *msg) { return fail(code, msg ? msg : ""); }

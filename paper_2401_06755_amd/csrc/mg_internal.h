@@ -132,4 +132,7 @@ int solve_after_header(nn4mg_hier *H);
 int solve_finish(nn4mg_hier *H, double *x, nn4mg_info *info);
 int hier_set_stream(nn4mg_hier *H, hipStream_t s);
 
+// Record the message returned by nn4mg_last_error() on this thread; returns code.
+int set_error(int code, const char *msg);
+
 }  // namespace nn4mg

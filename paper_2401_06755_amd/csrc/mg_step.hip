@@ -1,0 +1,698 @@
+// One two-phase time step of arXiv 2401.06755, Sec. 2.4 (Stages 1-4), with
+// linear (p = 1) filters, on gfx950.
+//
+// Every operator of the step is a 3x3x3 filter sum f(u; w) (Sec. 2.2.2) over a
+// field whose halo is synthesised at load time from that field's boundary
+// rule: a mirror with sign +1 or -1 per face, and for the hydrostatic pressure
+// a bottom halo that adds g h rho (Sec. 2.3.3).  The filters are tensor
+// products of the 1D linear-element vectors
+//     M = h [1, 4, 1] / 6 (mass),  G = [-1, 0, 1] / 2 (first derivative),
+//     K = [-1, 2, -1] / h (stiffness),
+// so each is evaluated separably on a 27-value neighbourhood held in
+// registers.  One thread owns one cell; the neighbourhoods of adjacent threads
+// overlap in L1/L2, which carries the re-reads.  This explicit part moves
+// about a kilobyte per cell per step; the three pressure solves, run by the
+// multigrid hierarchy of this library with a fixed cycle count, dominate.
+//
+// Boundary rules on the tank box (Sec. 3.1: free-slip side and bottom walls,
+// an outlet with zero pressure on top):
+//   C, rho, mu, k and the scalars made from them: +mirror on all faces;
+//   velocity component d: -mirror on the walls normal to d, except the top;
+//   component d of a vector made from grad C: -mirror on both faces normal to d;
+//   p_nh and its increment: +mirror, -mirror on top;
+//   p_hs: +mirror on the sides, -mirror on top, mirror + g h rho on the bottom.
+// In the Petrov-Galerkin formulas (Eqs. k-abs special case, k-square, a_psi,
+// the normalisation and Eq. negativek) the gradient Psi_x is taken in
+// derivative units, f(Psi; w_x) / m_l; the residuals use the filters as
+// printed.  mu blends like Eq. rho.  The velocities take the isotropic
+// coefficient of Eq. k_Psi-n; the volume fraction the anisotropic compressive
+// coefficients of Sec. 2.3.5 with the linear detectors, evaluated with the
+// new velocity.
+#include "mg_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+using namespace nn4mg;
+
+namespace {
+
+struct Grid {
+    int nx, ny, nz;
+    double h;
+    size_t n;
+};
+
+// Face bits of a boundary rule: bit f set = -mirror on face f
+// (xlo, xhi, ylo, yhi, zlo, zhi); clear = +mirror.
+constexpr unsigned kEven = 0u;
+constexpr unsigned kOddTop = 32u;  // p_nh, its increment, p_hs above
+__host__ __device__ constexpr unsigned rule_vel(int d) { return d == 0 ? 3u : (d == 1 ? 12u : 16u); }
+__host__ __device__ constexpr unsigned rule_grad(int d) { return 3u << (2 * d); }
+
+__device__ inline size_t at(const Grid &g, int i, int j, int k)
+{
+    return (size_t)i + (size_t)g.nx * ((size_t)j + (size_t)g.ny * (size_t)k);
+}
+
+// Value of the padded field at (i, j, k), each index at most one cell outside.
+__device__ inline double tap(const double *u, unsigned odd, const Grid &g, int i, int j, int k)
+{
+    double s = 1.0;
+    if (i < 0) {
+        i = 0;
+        if (odd & 1u) s = -s;
+    } else if (i >= g.nx) {
+        i = g.nx - 1;
+        if (odd & 2u) s = -s;
+    }
+    if (j < 0) {
+        j = 0;
+        if (odd & 4u) s = -s;
+    } else if (j >= g.ny) {
+        j = g.ny - 1;
+        if (odd & 8u) s = -s;
+    }
+    if (k < 0) {
+        k = 0;
+        if (odd & 16u) s = -s;
+    } else if (k >= g.nz) {
+        k = g.nz - 1;
+        if (odd & 32u) s = -s;
+    }
+    return s * u[at(g, i, j, k)];
+}
+
+// 27 values around a cell: v[(c+1)*9 + (b+1)*3 + (a+1)] at (i+a, j+b, k+c).
+struct Nb {
+    double v[27];
+    __device__ double mid() const { return v[13]; }
+};
+
+__device__ inline void load(Nb &n, const double *u, unsigned odd, const Grid &g, int i, int j, int k)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) n.v[c * 9 + b * 3 + a] = tap(u, odd, g, i + a - 1, j + b - 1, k + c - 1);
+}
+
+// p_hs with its bottom halo p(-1) = p(0) + g h rho(0) (rho +mirror elsewhere).
+__device__ inline void load_phs(Nb &n, const double *p, const double *rho, double gh, const Grid &g, int i, int j,
+                                int k)
+{
+    load(n, p, kOddTop, g, i, j, k);
+    if (k == 0)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) n.v[b * 3 + a] += gh * tap(rho, kEven, g, i + a - 1, j + b - 1, 0);
+}
+
+struct V3 {
+    double m, z, p;  // weights at offsets -1, 0, +1
+};
+
+// f(u; X (x) Y (x) Z), X along i.
+__device__ inline double sep(const Nb &n, const V3 &X, const V3 &Y, const V3 &Z)
+{
+    double out = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double pl = 0.0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double *r = &n.v[c * 9 + b * 3];
+            const double row = X.m * r[0] + X.z * r[1] + X.p * r[2];
+            pl += (b == 0 ? Y.m : (b == 1 ? Y.z : Y.p)) * row;
+        }
+        out += (c == 0 ? Z.m : (c == 1 ? Z.z : Z.p)) * pl;
+    }
+    return out;
+}
+
+struct Filt {
+    V3 M, G, K, m;  // m = M / h
+    double ml;      // lumped mass h^3
+    __device__ explicit Filt(double h)
+    {
+        M = {h / 6.0, 4.0 * h / 6.0, h / 6.0};
+        G = {-0.5, 0.0, 0.5};
+        K = {-1.0 / h, 2.0 / h, -1.0 / h};
+        m = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+        ml = h * h * h;
+    }
+    // w_d = G along d, M across (the printed w_x of Sec. 2.2.3 for d = 0)
+    __device__ double d(const Nb &n, int dir) const
+    {
+        return dir == 0 ? sep(n, G, M, M) : (dir == 1 ? sep(n, M, G, M) : sep(n, M, M, G));
+    }
+    // w_dd^PG = K along d, M across
+    __device__ double pg(const Nb &n, int dir) const
+    {
+        return dir == 0 ? sep(n, K, M, M) : (dir == 1 ? sep(n, M, K, M) : sep(n, M, M, K));
+    }
+    __device__ double lap(const Nb &n) const { return sep(n, K, M, M) + sep(n, M, K, M) + sep(n, M, M, K); }
+    __device__ double mass(const Nb &n) const { return sep(n, M, M, M); }
+    // w_m / m_l - E: the residual filter of Eq. a_psi
+    __device__ double mass_resid(const Nb &n) const { return sep(n, m, m, m) - n.mid(); }
+};
+
+// Eq. k-Txx: 1/2 [f(k C; w) + k f(C; w) - C f(k; w)] with the product of the
+// padded values as the halo of k C.  which: 0..2 = w_dd^PG, 3 = w_lap.
+__device__ inline double fdiff(const Filt &F, const Nb &Cn, const Nb &kn, int which)
+{
+    Nb kc;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) kc.v[q] = kn.v[q] * Cn.v[q];
+    if (which == 3) return 0.5 * (F.lap(kc) + kn.mid() * F.lap(Cn) - Cn.mid() * F.lap(kn));
+    return 0.5 * (F.pg(kc, which) + kn.mid() * F.pg(Cn, which) - Cn.mid() * F.pg(kn, which));
+}
+
+struct Phys {
+    double rho_l, rho_g, mu_l, mu_g, g, sigma, dt;
+};
+
+template <typename F>
+__device__ inline bool cell_of(const Grid &g, F &&body)
+{
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.n) return false;
+    const int i = (int)(id % (size_t)g.nx);
+    const size_t t = id / (size_t)g.nx;
+    body(id, i, (int)(t % (size_t)g.ny), (int)(t / (size_t)g.ny));
+    return true;
+}
+
+struct F3 {
+    double *p[3];
+};
+struct C3 {
+    const double *p[3];
+};
+
+// ------------------------------------------------------------------ kernels
+
+// rho, mu (Eq. rho), grad C in derivative units, unit normals.
+__global__ __launch_bounds__(256) void props_kernel(Grid g, Phys P, const double *C, double *rho, double *mu, F3 Cd,
+                                                    F3 nrm)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt F(g.h);
+        Nb c;
+        load(c, C, kEven, g, i, j, k);
+        const double c0 = c.mid();
+        rho[id] = P.rho_l * c0 + P.rho_g * (1.0 - c0);
+        mu[id] = P.mu_l * c0 + P.mu_g * (1.0 - c0);
+        double gd[3];
+        for (int d = 0; d < 3; ++d) gd[d] = F.d(c, d) / F.ml;
+        const double l = sqrt(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
+        const double eps = 1e-7 / g.h;
+        for (int d = 0; d < 3; ++d) {
+            Cd.p[d][id] = gd[d];
+            nrm.p[d][id] = gd[d] / (eps + l);
+        }
+    });
+}
+
+// Curvature kappa = div n (Eq. curvature) and the surface-tension force
+// sigma kappa grad C (Eq. surface-tension-k).
+__global__ __launch_bounds__(256) void surface_kernel(Grid g, double sigma, C3 nrm, C3 Cd, F3 st)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt F(g.h);
+        double kap = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            Nb n;
+            load(n, nrm.p[d], rule_grad(d), g, i, j, k);
+            kap += F.d(n, d);
+        }
+        kap /= F.ml;
+        for (int d = 0; d < 3; ++d) st.p[d][id] = sigma * kap * Cd.p[d][id];
+    });
+}
+
+// Right-hand side of Eq. ph_disc: sum_d f(s_t,d; w_d) + f(g rho; w_z), minus
+// the Laplacian filter applied to the affine part of p_hs's bottom halo, so the
+// solve sees homogeneous rules.
+__global__ __launch_bounds__(256) void rhs_hydrostatic_kernel(Grid g, double grav, C3 st, const double *rho,
+                                                              double *b)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt F(g.h);
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            Nb n;
+            load(n, st.p[d], rule_grad(d), g, i, j, k);
+            s += F.d(n, d);
+        }
+        Nb r, lift;
+        load(r, rho, kEven, g, i, j, k);
+        // the halo plane below k = 0 carries g h rho(i, j, 0); everything else is zero
+        const double gh = grav * g.h;
+        for (int q = 0; q < 27; ++q) lift.v[q] = (k == 0 && q < 9) ? gh * r.v[q] : 0.0;
+        for (int q = 0; q < 27; ++q) r.v[q] *= grav;
+        s += F.d(r, 2);
+        if (k == 0) s -= F.lap(lift);
+        b[id] = s;
+    });
+}
+
+// Advection of each velocity component by the iterate: adv_c = q . grad q_c.
+__global__ __launch_bounds__(256) void advection_kernel(Grid g, C3 q, F3 adv)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt F(g.h);
+        const double q0[3] = {q.p[0][id], q.p[1][id], q.p[2][id]};
+        for (int c = 0; c < 3; ++c) {
+            Nb n;
+            load(n, q.p[c], rule_vel(c), g, i, j, k);
+            double a = 0.0;
+            for (int d = 0; d < 3; ++d) a += q0[d] * (F.d(n, d) / F.ml);
+            adv.p[c][id] = a;
+        }
+    });
+}
+
+// Isotropic Petrov-Galerkin diffusivity of each component (Eq. k_Psi-n with
+// Eqs. efficient-kabs-special-case, k-square with h_Psi = h, max-k and the
+// residual a_Psi of Eq. a_psi, alpha_a = 2): k_c = rho min(k_max, k_abs, k_sq) + mu.
+__global__ __launch_bounds__(256) void pg_velocity_kernel(Grid g, C3 q, C3 adv, const double *rho,
+                                                          const double *mu, F3 kq)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt F(g.h);
+        const double eps_k = 1e-7, a_kabs = 1.0 / 16.0, a_ksq = 4.0, h = g.h;
+        const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
+        for (int c = 0; c < 3; ++c) {
+            Nb n;
+            load(n, q.p[c], rule_vel(c), g, i, j, k);
+            const double px = F.d(n, 0) / F.ml, py = F.d(n, 1) / F.ml, pz = F.d(n, 2) / F.ml;
+            Nb an;
+            load(an, adv.p[c], kEven, g, i, j, k);
+            const double a = 2.0 * F.mass_resid(an);
+            const double G = fabs(px) + fabs(py) + fabs(pz);
+            const double kabs = a_kabs * h * fabs(a) / (eps_k + G / 3.0);
+            const double g2 = px * px + py * py + pz * pz;
+            const double advabs = fabs(u * px) + fabs(v * py) + fabs(w * pz);
+            const double ksq = a_ksq * a * a * h / (eps_k + advabs / 3.0 * g2);
+            const double kmax = h * (fabs(u) + fabs(v) + fabs(w));
+            const double m = fmin(kmax, fmin(kabs, ksq));
+            kq.p[c][id] = rho[id] * m + mu[id];
+        }
+    });
+}
+
+// One predictor iteration (Eqs. Petrov, velocity-1): the momentum residual
+// s_c = rho m_l adv_c + f_lap(q_c, k_c) + f(p_hs + p_nh; w_c) - f(s_t,c; w_m)
+// [- f(-g rho; w_m) for c = z] gives q~_c = (-s_c / m_l + rho q^n_c / dt) / (rho / dt),
+// and the next iterate is (q^n + q~) / 2.
+__global__ __launch_bounds__(256) void momentum_kernel(Grid g, Phys P, C3 qn, C3 q, C3 kq, C3 adv,
+                                                       const double *p_hs, const double *p_nh, C3 st,
+                                                       const double *rho, F3 qt, F3 qnext)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt F(g.h);
+        const double r0 = rho[id];
+        for (int c = 0; c < 3; ++c) {
+            double s;
+            {
+                Nb qv, kv;
+                load(qv, q.p[c], rule_vel(c), g, i, j, k);
+                load(kv, kq.p[c], kEven, g, i, j, k);
+                s = fdiff(F, qv, kv, 3);
+            }
+            {
+                Nb p;
+                load_phs(p, p_hs, rho, P.g * g.h, g, i, j, k);
+                s += F.d(p, c);
+            }
+            {
+                Nb p;
+                load(p, p_nh, kOddTop, g, i, j, k);
+                s += F.d(p, c);
+            }
+            {
+                Nb t;
+                load(t, st.p[c], rule_grad(c), g, i, j, k);
+                s -= F.mass(t);
+            }
+            if (c == 2) {
+                Nb r;
+                load(r, rho, kEven, g, i, j, k);
+                for (int e = 0; e < 27; ++e) r.v[e] *= -P.g;
+                s -= F.mass(r);
+            }
+            s += r0 * F.ml * adv.p[c][id];
+            const double qnc = qn.p[c][id];
+            const double t = (-s / F.ml + r0 * qnc / P.dt) / (r0 / P.dt);
+            qt.p[c][id] = t;
+            qnext.p[c][id] = 0.5 * (qnc + t);
+        }
+    });
+}
+
+// Right-hand side of Eq. ph_disc2 for the pressure increment:
+// -(1/dt) sum_d f(rho q~_d; w_d) + (1/dt) sum_d q~_d f(rho; w_d).
+__global__ __launch_bounds__(256) void rhs_nonhydrostatic_kernel(Grid g, double dt, C3 qt, const double *rho,
+                                                                 double *b)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt F(g.h);
+        Nb r;
+        load(r, rho, kEven, g, i, j, k);
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            Nb m;
+            load(m, qt.p[d], rule_vel(d), g, i, j, k);
+            for (int e = 0; e < 27; ++e) m.v[e] *= r.v[e];
+            s -= F.d(m, d) / dt;
+            s += qt.p[d][id] * F.d(r, d) / dt;
+        }
+        b[id] = s;
+    });
+}
+
+// Eq. vel-cor: q~_d -= dt f(dp; w_d) / (m_l rho); p_nh += dp.
+__global__ __launch_bounds__(256) void correct_kernel(Grid g, double dt, const double *dp, const double *rho, C3 qin,
+                                                      F3 qout, double *p_nh)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt F(g.h);
+        Nb n;
+        load(n, dp, kOddTop, g, i, j, k);
+        const double r0 = rho[id];
+        for (int d = 0; d < 3; ++d) qout.p[d][id] = qin.p[d][id] + -dt * (F.d(n, d) / F.ml) / r0;
+        p_nh[id] += n.mid();
+    });
+}
+
+// u . grad C with the new velocity (input of the residual of Eq. a_psi for C).
+__global__ __launch_bounds__(256) void advection_c_kernel(Grid g, C3 q, C3 Cd, double *out)
+{
+    cell_of(g, [&](size_t id, int, int, int) {
+        out[id] = q.p[0][id] * Cd.p[0][id] + q.p[1][id] * Cd.p[1][id] + q.p[2][id] * Cd.p[2][id];
+    });
+}
+
+// Anisotropic compressive diffusivities of the volume fraction (Sec. 2.3.5):
+// linear interface detectors S_d, weights w+ and w-, k+ = 3 k_abs and the
+// negative (compressive) k- of Eq. negativek with its normalisation, clamped
+// to [-alpha_min h^2 / dt, alpha_max h^2 / dt] (Eq. alpha_min_and_max).
+__global__ __launch_bounds__(256) void pg_volume_fraction_kernel(Grid g, double dt, const double *C, C3 Cd, C3 q,
+                                                                 const double *advc, F3 kd)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt F(g.h);
+        const double Kp = 300.0, Km = 300.0, beta = 0.1, eps_x = 1e-4, Kpos = 3.0, eps_k = 1e-7, h = g.h;
+        const double kmin = 1e-4 / dt * h * h, kclamp = 0.05 / dt * h * h;
+        Nb an;
+        load(an, advc, kEven, g, i, j, k);
+        const double a = 2.0 * F.mass_resid(an);
+        const double c0 = C[id];
+        double S[3];
+        S[0] = (c0 - tap(C, kEven, g, i - 1, j, k)) * (tap(C, kEven, g, i + 1, j, k) - c0);
+        S[1] = (c0 - tap(C, kEven, g, i, j - 1, k)) * (tap(C, kEven, g, i, j + 1, k) - c0);
+        S[2] = (c0 - tap(C, kEven, g, i, j, k - 1)) * (tap(C, kEven, g, i, j, k + 1) - c0);
+        if (c0 > 0.95 || c0 < 0.05) S[0] = S[1] = S[2] = -1.0;
+        const double cx = Cd.p[0][id], cy = Cd.p[1][id], cz = Cd.p[2][id];
+        const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
+        const double g2 = cx * cx + cy * cy + cz * cz;
+        const double proj = (u * cx + v * cy + w * cz) / (eps_x + g2);
+        const double us = cx * proj, vs = cy * proj, ws = cz * proj;
+        const double kneg = -beta * (u * u + v * v + w * w) / (eps_x + g2 * (fabs(us) + fabs(vs) + fabs(ws)) / 3.0);
+        const double G = fabs(cx) + fabs(cy) + fabs(cz);
+        const double kabs = (1.0 / 16.0) * h * fabs(a) / (eps_k + G / 3.0);
+        for (int d = 0; d < 3; ++d) {
+            const double wp = -fmax(-1.0, fmin(0.0, Kp * S[d]));
+            const double wm = fmin(1.0, fmax(0.0, Km * S[d]));
+            const double kk = wp * (Kpos * kabs) + wm * (kneg / h);
+            kd.p[d][id] = fmax(-kmin, fmin(kclamp, kk));
+        }
+    });
+}
+
+// Eqs. Petrov-C, transport-indicator-1: C^{n+1} = C - dt s_C / m_l with
+// s_C = m_l u . grad C + sum_d f_d(C, k_d; w_dd^PG).
+__global__ __launch_bounds__(256) void volume_fraction_kernel(Grid g, double dt, const double *C, C3 kd, C3 q, C3 Cd,
+                                                              double *Cnew)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt F(g.h);
+        double s = F.ml * (q.p[0][id] * Cd.p[0][id] + q.p[1][id] * Cd.p[1][id] + q.p[2][id] * Cd.p[2][id]);
+        Nb cn;
+        load(cn, C, kEven, g, i, j, k);
+        for (int d = 0; d < 3; ++d) {
+            Nb kn;
+            load(kn, kd.p[d], kEven, g, i, j, k);
+            s += fdiff(F, cn, kn, d);
+        }
+        Cnew[id] = cn.mid() - dt * s / F.ml;
+    });
+}
+
+__global__ __launch_bounds__(256) void copy3_kernel(size_t n, C3 src, F3 dst)
+{
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    for (int d = 0; d < 3; ++d) dst.p[d][id] = src.p[d][id];
+}
+
+C3 c3(double *const p[3]) { return C3{{p[0], p[1], p[2]}}; }
+F3 f3(double *const p[3]) { return F3{{p[0], p[1], p[2]}}; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+
+struct nn4mg_stepper {
+    Grid g{};
+    nn4mg_step_params p{};
+    hipStream_t s = nullptr;
+    nn4mg_t P = nullptr;       // constant-coefficient pressure hierarchy
+    double *mem = nullptr;     // all work fields, one allocation
+    double *rho, *mu, *Cd[3], *nrm[3], *st[3], *b, *px, *qa[3], *qb[3], *qt[3], *adv[3], *kq[3], *tmp;
+    hipEvent_t ev[4]{};        // step start / end, solve start / end
+};
+
+namespace {
+
+constexpr int kFields = 29;
+
+int hip_fail(hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return set_error(NN4MG_EDEVICE, m.c_str());
+}
+
+#define STEP_TRY(expr, what)                          \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+dim3 cells_grid(const Grid &g) { return dim3((unsigned)((g.n + 255) / 256)); }
+
+// Fixed-cycle solve of A x = b on the pressure hierarchy; the work pair
+// (b, px) is the same for every solve, so a captured cycle stays valid.
+int pressure_solve(nn4mg_stepper *S, int slot, nn4mg_step_info *info, float *ms_mg)
+{
+    nn4mg_info si;
+    STEP_TRY(hipEventRecord(S->ev[2], S->s), "hipEventRecord");
+    int rc = nn4mg_solve(S->P, S->b, S->px, 0.0, S->p.mg_cycles, 1, &si);
+    if (rc != NN4MG_OK && rc != NN4MG_ENOTCONV) return rc;
+    STEP_TRY(hipEventRecord(S->ev[3], S->s), "hipEventRecord");
+    STEP_TRY(hipEventSynchronize(S->ev[3]), "hipEventSynchronize");
+    float ms = 0.0f;
+    STEP_TRY(hipEventElapsedTime(&ms, S->ev[2], S->ev[3]), "hipEventElapsedTime");
+    *ms_mg += ms;
+    if (info) {
+        info->relres[slot] = si.relres;
+        info->solves = slot + 1;
+    }
+    return NN4MG_OK;
+}
+
+int check_params(const nn4mg_step_params *p)
+{
+    if (!p) return set_error(NN4MG_EINVAL, "params is NULL");
+    if (!(p->rho_l > 0.0) || !(p->rho_g > 0.0)) return set_error(NN4MG_EINVAL, "densities must be > 0");
+    if (!(p->mu_l >= 0.0) || !(p->mu_g >= 0.0)) return set_error(NN4MG_EINVAL, "viscosities must be >= 0");
+    if (!(p->dt > 0.0)) return set_error(NN4MG_EINVAL, "dt must be > 0");
+    if (!std::isfinite(p->g) || !std::isfinite(p->sigma_t)) return set_error(NN4MG_EINVAL, "g, sigma_t must be finite");
+    if (p->mg_cycles < 1 || p->mg_cycles > 511) return set_error(NN4MG_EINVAL, "mg_cycles must be in [1, 511]");
+    if (p->n_corr < 0 || p->n_corr > 7) return set_error(NN4MG_EINVAL, "n_corr must be in [0, 7]");
+    if (p->n_vel_iter < 1 || p->n_vel_iter > 64) return set_error(NN4MG_EINVAL, "n_vel_iter must be in [1, 64]");
+    return NN4MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void nn4mg_step_params_default(nn4mg_step_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->rho_l = 1000.0;
+    p->rho_g = 1.0;
+    p->mu_l = 1e-3;
+    p->mu_g = 1.8e-5;
+    p->g = 9.81;
+    p->sigma_t = 0.07;
+    p->dt = 1e-4;
+    p->mg_cycles = 20;
+    p->n_corr = 2;
+    p->n_vel_iter = 2;
+}
+
+int nn4mg_step_destroy(nn4mg_step_t S)
+{
+    if (!S) return NN4MG_OK;
+    if (S->s) (void)hipStreamSynchronize(S->s);
+    else (void)hipDeviceSynchronize();
+    if (S->P) nn4mg_destroy(S->P);
+    if (S->mem) (void)hipFree(S->mem);
+    for (auto &e : S->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete S;
+    return NN4MG_OK;
+}
+
+int nn4mg_step_create(int nx, int ny, int nz, double h, const nn4mg_step_params *p, void *hip_stream,
+                      nn4mg_step_t *out)
+{
+    if (!out) return set_error(NN4MG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (nx < 4 || ny < 4 || nz < 4) return set_error(NN4MG_EINVAL, "grid dims must be >= 4");
+    if (!(h > 0.0)) return set_error(NN4MG_EINVAL, "h must be > 0");
+    // pressure: zero-normal-derivative walls, zero pressure on the top outlet
+    nn4mg_config cfg;
+    nn4mg_config_default(&cfg, nx, ny, nz, h);
+    for (int f = 0; f < 5; ++f) cfg.bc[f] = NN4MG_BC_NEUMANN0;
+    cfg.bc[5] = NN4MG_BC_DIRICHLET0;
+    nn4mg_stepper *S = new nn4mg_stepper();
+    S->g = Grid{nx, ny, nz, h, (size_t)nx * ny * nz};
+    S->p = *p;
+    S->s = (hipStream_t)hip_stream;
+    if ((rc = nn4mg_setup(&cfg, nullptr, hip_stream, &S->P))) {
+        S->P = nullptr;
+        nn4mg_step_destroy(S);
+        return rc;
+    }
+    const size_t n = S->g.n;
+    hipError_t e = hipMalloc((void **)&S->mem, (size_t)kFields * n * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        S->mem = nullptr;
+        nn4mg_step_destroy(S);
+        return set_error(NN4MG_ENOMEM, "step work fields: hipMalloc failed");
+    }
+    double *q = S->mem;
+    auto take = [&]() {
+        double *r = q;
+        q += n;
+        return r;
+    };
+    S->rho = take();
+    S->mu = take();
+    for (int d = 0; d < 3; ++d) S->Cd[d] = take();
+    for (int d = 0; d < 3; ++d) S->nrm[d] = take();
+    for (int d = 0; d < 3; ++d) S->st[d] = take();
+    S->b = take();
+    S->px = take();
+    for (int d = 0; d < 3; ++d) S->qa[d] = take();
+    for (int d = 0; d < 3; ++d) S->qb[d] = take();
+    for (int d = 0; d < 3; ++d) S->qt[d] = take();
+    for (int d = 0; d < 3; ++d) S->adv[d] = take();
+    for (int d = 0; d < 3; ++d) S->kq[d] = take();
+    S->tmp = take();
+    for (auto &ev : S->ev)
+        if ((e = hipEventCreate(&ev)) != hipSuccess) {
+            ev = nullptr;
+            nn4mg_step_destroy(S);
+            return hip_fail(e, "hipEventCreate");
+        }
+    *out = S;
+    return NN4MG_OK;
+}
+
+int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, double *p_hs, double *p_nh,
+               nn4mg_step_info *info)
+{
+    if (!S || !C || !u || !v || !w || !p_hs || !p_nh) return set_error(NN4MG_EINVAL, "NULL argument");
+    if (info) std::memset(info, 0, sizeof(*info));
+    const Grid g = S->g;
+    const nn4mg_step_params &p = S->p;
+    const Phys P{p.rho_l, p.rho_g, p.mu_l, p.mu_g, p.g, p.sigma_t, p.dt};
+    const hipStream_t s = S->s;
+    const dim3 grid = cells_grid(g), blk(256);
+    double *q[3] = {u, v, w};
+    float ms_mg = 0.0f;
+    int rc;
+
+    STEP_TRY(hipEventRecord(S->ev[0], s), "hipEventRecord");
+    hipLaunchKernelGGL(props_kernel, grid, blk, 0, s, g, P, (const double *)C, S->rho, S->mu, f3(S->Cd), f3(S->nrm));
+    hipLaunchKernelGGL(surface_kernel, grid, blk, 0, s, g, p.sigma_t, c3(S->nrm), c3(S->Cd), f3(S->st));
+
+    // Stage 1: hydrostatic + surface-tension pressure, warm-started from p_hs
+    hipLaunchKernelGGL(rhs_hydrostatic_kernel, grid, blk, 0, s, g, p.g, c3(S->st), (const double *)S->rho, S->b);
+    STEP_TRY(hipGetLastError(), "step kernels");
+    STEP_TRY(hipMemcpyAsync(S->px, p_hs, g.n * sizeof(double), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+    if ((rc = pressure_solve(S, 0, info, &ms_mg))) return rc;
+    STEP_TRY(hipMemcpyAsync(p_hs, S->px, g.n * sizeof(double), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+
+    // Stage 2: velocity predictor iterations, q^ from q^n
+    double **cur = S->qa, **nxt = S->qb;
+    hipLaunchKernelGGL(copy3_kernel, grid, blk, 0, s, g.n, c3(q), f3(cur));
+    for (int it = 0; it < p.n_vel_iter; ++it) {
+        hipLaunchKernelGGL(advection_kernel, grid, blk, 0, s, g, c3(cur), f3(S->adv));
+        hipLaunchKernelGGL(pg_velocity_kernel, grid, blk, 0, s, g, c3(cur), c3(S->adv), (const double *)S->rho,
+                           (const double *)S->mu, f3(S->kq));
+        hipLaunchKernelGGL(momentum_kernel, grid, blk, 0, s, g, P, c3(q), c3(cur), c3(S->kq), c3(S->adv),
+                           (const double *)p_hs, (const double *)p_nh, c3(S->st), (const double *)S->rho,
+                           f3(S->qt), f3(nxt));
+        double **t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    STEP_TRY(hipGetLastError(), "step kernels");
+
+    // Stage 3: non-hydrostatic corrections; the corrected velocity lands in q
+    double **qin = S->qt;
+    for (int it = 0; it < p.n_corr; ++it) {
+        hipLaunchKernelGGL(rhs_nonhydrostatic_kernel, grid, blk, 0, s, g, p.dt, c3(qin), (const double *)S->rho,
+                           S->b);
+        STEP_TRY(launch_fill(S->px, g.n, 0.0, s), "fill");
+        if ((rc = pressure_solve(S, 1 + it, info, &ms_mg))) return rc;
+        hipLaunchKernelGGL(correct_kernel, grid, blk, 0, s, g, p.dt, (const double *)S->px, (const double *)S->rho,
+                           c3(qin), f3(q), p_nh);
+        qin = q;
+    }
+    if (p.n_corr == 0) hipLaunchKernelGGL(copy3_kernel, grid, blk, 0, s, g.n, c3(S->qt), f3(q));
+
+    // Stage 4: volume fraction with the new velocity
+    hipLaunchKernelGGL(advection_c_kernel, grid, blk, 0, s, g, c3(q), c3(S->Cd), S->tmp);
+    hipLaunchKernelGGL(pg_volume_fraction_kernel, grid, blk, 0, s, g, p.dt, (const double *)C, c3(S->Cd), c3(q),
+                       (const double *)S->tmp, f3(S->kq));
+    hipLaunchKernelGGL(volume_fraction_kernel, grid, blk, 0, s, g, p.dt, (const double *)C, c3(S->kq), c3(q),
+                       c3(S->Cd), S->b);
+    STEP_TRY(hipMemcpyAsync(C, S->b, g.n * sizeof(double), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+    STEP_TRY(hipGetLastError(), "step kernels");
+    STEP_TRY(hipEventRecord(S->ev[1], s), "hipEventRecord");
+    STEP_TRY(hipEventSynchronize(S->ev[1]), "hipEventSynchronize");
+    if (info) {
+        float ms = 0.0f;
+        STEP_TRY(hipEventElapsedTime(&ms, S->ev[0], S->ev[1]), "hipEventElapsedTime");
+        info->ms_total = ms;
+        info->ms_mg = ms_mg;
+    }
+    return NN4MG_OK;
+}
+
+}  // extern "C"

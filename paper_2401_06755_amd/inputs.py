@@ -119,3 +119,18 @@ def rising_bubble(nx: int = 256, seed: int = 5, radius: float = 0.25):
     k = two_phase_k(frac, 1.0, 1000.0)
     b = gaussian(shape, seed, zero_mean=False)
     return dict(shape=shape, h=h, bc=TOP_DIRICHLET, k=k, b=b)
+
+
+def water_block(nx: int = 128, ny: int | None = None, nz: int | None = None, x1: float = 0.25, z1: float = 0.5):
+    """Collapsing water column on the unit-spacing tank (Sec. 3.1 set-up): C = 1 in
+    cells whose centre lies in [0, x1] x [0, 1] x [0, z1] (box units of h = 1/nx),
+    else 0; fluid at rest, pressures zero.  Returns (h, dict of (nz, ny, nx) arrays)."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    h = 1.0 / nx
+    x = (np.arange(nx) + 0.5) * h
+    z = (np.arange(nz) + 0.5) * h
+    C = ((x[None, None, :] <= x1) & (z[:, None, None] <= z1)).astype(np.float64)
+    C = np.ascontiguousarray(np.broadcast_to(C, (nz, ny, nx)))
+    zero = np.zeros((nz, ny, nx))
+    return h, dict(C=C, u=zero.copy(), v=zero.copy(), w=zero.copy(), p_hs=zero.copy(), p_nh=zero.copy())

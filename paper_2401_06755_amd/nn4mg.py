@@ -76,6 +76,24 @@ class Result(ctypes.Structure):
     ]
 
 
+class StepParams(ctypes.Structure):
+    _fields_ = [
+        ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double),
+        ("mu_l", ctypes.c_double), ("mu_g", ctypes.c_double),
+        ("g", ctypes.c_double), ("sigma_t", ctypes.c_double), ("dt", ctypes.c_double),
+        ("mg_cycles", ctypes.c_int), ("n_corr", ctypes.c_int), ("n_vel_iter", ctypes.c_int),
+        ("reserved", ctypes.c_int * 5),
+    ]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [
+        ("solves", ctypes.c_int),
+        ("relres", ctypes.c_double * 8),
+        ("ms_total", ctypes.c_double), ("ms_mg", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -131,6 +149,15 @@ def lib():
     L.nn4mg_server_stats.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(i), ctypes.POINTER(i)]
     L.nn4mg_server_destroy.restype = i
     L.nn4mg_server_destroy.argtypes = [vp]
+    stp = ctypes.POINTER(StepParams)
+    L.nn4mg_step_params_default.restype = None
+    L.nn4mg_step_params_default.argtypes = [stp]
+    L.nn4mg_step_create.restype = i
+    L.nn4mg_step_create.argtypes = [i, i, i, d, stp, vp, ctypes.POINTER(vp)]
+    L.nn4mg_step.restype = i
+    L.nn4mg_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(StepInfo)]
+    L.nn4mg_step_destroy.restype = i
+    L.nn4mg_step_destroy.argtypes = [vp]
     L.nn4mg_destroy.restype = i
     L.nn4mg_destroy.argtypes = [vp]
     L.nn4mg_last_error.restype = ctypes.c_char_p
@@ -313,6 +340,51 @@ class Server:
             lib().nn4mg_server_destroy(self._h)
             self._h = None
             self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+STEP_FIELDS = ("C", "u", "v", "w", "p_hs", "p_nh")
+
+
+def step_params(**kw) -> StepParams:
+    p = StepParams()
+    lib().nn4mg_step_params_default(ctypes.byref(p))
+    for key, val in kw.items():
+        setattr(p, key, val)
+    return p
+
+
+class Stepper:
+    """Two-phase time step (nn4mg_step_*) on an nx x ny x nz grid, bound to the
+    current torch stream.  step() advances a dict of device float64 tensors
+    C, u, v, w, p_hs, p_nh in place."""
+
+    def __init__(self, nx, ny, nz, h, params: StepParams | None = None, stream: torch.cuda.Stream | None = None):
+        self.params = params if params is not None else step_params()
+        self.n = int(nx) * int(ny) * int(nz)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h_ = ctypes.c_void_p()
+        _check(lib().nn4mg_step_create(int(nx), int(ny), int(nz), float(h), ctypes.byref(self.params),
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h_)))
+        self._h = h_
+
+    def step(self, state: dict) -> StepInfo:
+        if not self._h:
+            raise RuntimeError("stepper destroyed")
+        ptrs = [_field(state[k], self.n, k) for k in STEP_FIELDS]
+        info = StepInfo()
+        _check(lib().nn4mg_step(self._h, *ptrs, ctypes.byref(info)))
+        return info
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nn4mg_step_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:
