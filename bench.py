@@ -70,11 +70,11 @@ def cycle_model_bytes(levels, mode):
     return tot
 
 
-def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol, autotune=True):
+def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol, autotune=True, outer=0, profile=True):
     nx, ny, nz = work["shape"]
     n = nx * ny * nz
     cfg = nn4mg.config_default(nx, ny, nz, work["h"], bc=work["bc"], coef_mode=nn4mg.COEF_NODAL,
-                               precision=precision)
+                               precision=precision, outer=outer)
     kd = torch.from_numpy(work["k"].reshape(-1)).cuda()
     bd = torch.from_numpy(work["b"].reshape(-1)).cuda()
     xd = torch.zeros_like(bd)
@@ -115,19 +115,20 @@ def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol, autotune=True
     # the same K solves again with every finest-level launch bracketed by HIP
     # events on the solve stream (event records add a little host overhead,
     # so they are kept out of the timed region above)
-    H.profile(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for s in range(steps):
-        xd.zero_()
-        H.solve(bd, xd, rtol=rtol, max_cycles=2000)
-    torch.cuda.synchronize()
-    dt_prof = time.perf_counter() - t1
-    H.profile(False)
-    kern = {}
-    for name, cls in KCLASS.items():
-        cnt, ms = H.profile_read(cls)
-        kern[name] = (cnt, ms)
+    kern, dt_prof = {}, 0.0
+    if profile:
+        H.profile(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for s in range(steps):
+            xd.zero_()
+            H.solve(bd, xd, rtol=rtol, max_cycles=2000)
+        torch.cuda.synchronize()
+        dt_prof = time.perf_counter() - t1
+        H.profile(False)
+        for name, cls in KCLASS.items():
+            cnt, ms = H.profile_read(cls)
+            kern[name] = (cnt, ms)
     levels = H.levels()
     H.close()
     return dict(n=n, dt=dt, dt_prof=dt_prof, cycles=cycles, info=infos[-1], kern=kern, levels=levels,
@@ -306,6 +307,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-fcg", action="store_true", help="skip the flexible-CG outer iteration legs")
     ap.add_argument("--serve-requests", type=int, default=512, help="served-stream requests (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -386,6 +388,19 @@ def main():
                         "speedup_vs_fp64_solve": round(r64["dt"] / rm["dt"], 3),
                         "dtype": "f32 smoothing + f64 residual/coarsest/refinement",
                         "roofline": roofm, "roofline_kernel": bm, "fine_kernels": pkm}
+    if not args.no_fcg:
+        fcg = {}
+        for name, prec in (("fp64", nn4mg.PREC_FP64), ("mixed", nn4mg.PREC_FP32_SMOOTH)):
+            if name == "mixed" and args.no_mixed:
+                continue
+            log(f"flexible CG outer iteration, {name} cycle")
+            rf = run_solver(nn4mg, torch, work, prec, args.steps, args.warmup, args.rtol,
+                            autotune=not args.no_autotune, outer=nn4mg.OUTER_FCG, profile=False)
+            ms = rf["dt"] / args.steps * 1e3
+            fcg[name] = {"ms_per_solve": round(ms, 3), "iterations_per_solve": rf["info"].cycles,
+                         "relres": rf["info"].relres, "all_converged": rf["all_converged"],
+                         "speedup_vs_stationary_fp64": round(r64["dt"] / rf["dt"], 3)}
+        out["fcg"] = fcg
     if args.serve_requests > 0:
         log(f"served stream: {args.serve_requests} requests")
         out["serving"] = serving_bench(nn4mg, torch, args.serve_requests, args.serve_budget_gib, args.serve_slots)

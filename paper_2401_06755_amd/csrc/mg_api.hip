@@ -116,6 +116,7 @@ int validate(const nn4mg_config *c)
     const int L = count_levels(c->nx, c->ny, c->nz, c->min_coarse);
     const double nc = (double)(c->nx >> (L - 1)) * (c->ny >> (L - 1)) * (c->nz >> (L - 1));
     if (nc > kMaxCoarse) return fail(NN4MG_EINVAL, "coarsest level has more than 512 cells (dims not divisible enough)");
+    if (c->outer == NN4MG_OUTER_FCG && L < 2) return fail(NN4MG_EINVAL, "the FCG outer iteration needs two levels or more");
     return NN4MG_OK;
 }
 
@@ -236,7 +237,8 @@ struct nn4mg_hier {
     int max_partials = 0;
     double *scal = nullptr;  // device scalars: [0] sum, [1] mean of x, [2..7] spare
     int *flag = nullptr;
-    double *fcg = nullptr;   // FCG vectors (r, z, p, q) at level 0, FP64
+    double *fcg = nullptr;   // FCG vectors r, z, p, t = -A p and a zero vector, level 0, FP64
+    double *fcg_part = nullptr;  // FCG dot-product partials
     size_t bytes = 0;
     std::vector<void *> allocs;
     // captured hipGraph of one stationary iteration (body + residual + stopping rule)
@@ -313,7 +315,7 @@ size_t bytes_for(const nn4mg_config *c)
     }
     const size_t nc = (size_t)(c->nx >> (L - 1)) * (c->ny >> (L - 1)) * (c->nz >> (L - 1));
     b += 8 * nc * nc + sizeof(SolveState) + 8 * maxblk + 64 + 4;
-    if (c->outer == NN4MG_OUTER_FCG) b += 4 * 8 * (size_t)c->nx * c->ny * c->nz;
+    if (c->outer == NN4MG_OUTER_FCG) b += 5 * 8 * (size_t)c->nx * c->ny * c->nz + 8 * (size_t)fcg_partials_needed();
     return b;
 }
 
@@ -470,8 +472,10 @@ int enqueue_coarse_sweeps(nn4mg_hier *H, int l, const int *done)
     return NN4MG_OK;
 }
 
-// Finest-level sweeps: FP64: x <- smooth(x + P e_1); mixed: x += smooth(P e_1).
-int enqueue_fine_sweeps(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done)
+// Finest-level sweeps: FP64: x <- smooth(x + P e_1) (x_zero: smooth(P e_1), x
+// not read); mixed: x += smooth(P e_1).
+int enqueue_fine_sweeps(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done,
+                        bool x_zero = false)
 {
     Level &F = H->lv[0];
     const int nu = H->cfg.nu_post;
@@ -488,8 +492,8 @@ int enqueue_fine_sweeps(nn4mg_hier *H, const double *b, const double *bmean, dou
             a.done = done;
             int in_mode = IN_PLAIN;
             if (s == 0) {
-                in_mode = IN_PROLONG_ADD;
-                a.yin = x;
+                in_mode = x_zero ? IN_PROLONG : IN_PROLONG_ADD;
+                a.yin = x_zero ? nullptr : x;
                 a.ec = H->lv[1].e;
             } else {
                 a.yin = in;
@@ -538,7 +542,8 @@ int enqueue_fine_sweeps(nn4mg_hier *H, const double *b, const double *bmean, dou
 // Everything of one cycle after the finest residual has been restricted to
 // level 1 (FP64: lv[1].b; mixed: lv[1].b32 and the FP32 finest residual in
 // lv[0].b32).
-int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done)
+int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done,
+                       bool x_zero = false)
 {
     const bool f64 = !H->mixed;
     const int L = H->L;
@@ -554,7 +559,7 @@ int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, doub
                                 H->ainv, H->nc, H->singular, done, s));
     for (int l = L - 2; l >= 1; --l)
         if ((rc = enqueue_coarse_sweeps(H, l, done))) return rc;
-    return enqueue_fine_sweeps(H, b, bmean, x, done);
+    return enqueue_fine_sweeps(H, b, bmean, x, done, x_zero);
 }
 
 // One outer iteration starting with the finest residual.  For a single-level
@@ -643,8 +648,6 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
     if (rc) return rc;
     const bool nodal = cfg->coef_mode == NN4MG_COEF_NODAL;
     if (nodal && !k_dev) return fail(NN4MG_EINVAL, "nodal coefficient requires k");
-    if (cfg->outer == NN4MG_OUTER_FCG && cfg->precision != NN4MG_PREC_FP64 && false)
-        return fail(NN4MG_EINVAL, "unsupported");
     nn4mg_hier *H = new nn4mg_hier();
     H->cfg = *cfg;
     H->stream = (hipStream_t)hip_stream;
@@ -712,7 +715,15 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
     H->max_partials = maxblk;
     TRY(dalloc(H, &H->scal, 8));
     TRY(dalloc(H, &H->flag, 1));
-    if (cfg->outer == NN4MG_OUTER_FCG) TRY(dalloc(H, &H->fcg, 4 * H->lv[0].n));
+    if (cfg->outer == NN4MG_OUTER_FCG) {
+        TRY(dalloc(H, &H->fcg, 5 * H->lv[0].n));
+        TRY(dalloc(H, &H->fcg_part, (size_t)fcg_partials_needed()));
+        if (launch_fill(H->fcg + 4 * H->lv[0].n, H->lv[0].n, 0.0, H->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            nn4mg_destroy(H);
+            return fail(NN4MG_EDEVICE, "zero fill failed");
+        }
+    }
     if (hipHostMalloc((void **)&H->st_host, sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         nn4mg_destroy(H);
@@ -815,6 +826,76 @@ int enqueue_stationary_iteration(nn4mg_hier *H, const double *b, double *x)
     return NN4MG_OK;
 }
 
+// ---- flexible CG outer iteration: one sawtooth cycle from zero is the
+// preconditioner M.  Vectors (level 0, FP64): r, z, p, t = -A p, zero.
+struct FcgVec {
+    double *r, *z, *p, *t, *zero;
+};
+FcgVec fcg_vec(nn4mg_hier *H)
+{
+    const size_t n = H->lv[0].n;
+    return FcgVec{H->fcg, H->fcg + n, H->fcg + 2 * n, H->fcg + 3 * n, H->fcg + 4 * n};
+}
+
+// z = M r.  FP64: the cycle's right-hand side is r itself; mixed: the FP32
+// copy of r already sits in lv[0].b32 and the cycle adds its correction to z.
+int enqueue_precondition(nn4mg_hier *H, const double *r, double *z, const int *done)
+{
+    Level &F = H->lv[0];
+    hipStream_t s = H->stream;
+    if (!H->mixed) {
+        HIP_TRY(launch_restrict(1, r, H->lv[1].b, F.nx, F.ny, F.nz, done, s));
+        return enqueue_cycle_body(H, r, nullptr, z, done, true);
+    }
+    HIP_TRY(launch_restrict(0, F.b32, H->lv[1].b32, F.nx, F.ny, F.nz, done, s));
+    HIP_TRY(launch_zero(z, F.n, done, s));
+    return enqueue_cycle_body(H, nullptr, nullptr, z, done);
+}
+
+// Start: r = (b - mean) - A x, its norm (stopping rule), z = M r, rho = z.r, p = z.
+int enqueue_fcg_start(nn4mg_hier *H, const double *b, double *x)
+{
+    const FcgVec v = fcg_vec(H);
+    const size_t n = H->lv[0].n;
+    hipStream_t s = H->stream;
+    const int *done = &H->st->done;
+    int rc;
+    if ((rc = enqueue_resid(H, x, b, H->singular ? &H->st->bmean : nullptr, v.r, nullptr, false, true, done)))
+        return rc;
+    HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), s));
+    if (H->mixed) HIP_TRY(launch_cast_f32(v.r, H->lv[0].b32, n, done, s));
+    if ((rc = enqueue_precondition(H, v.r, v.z, done))) return rc;
+    HIP_TRY(launch_fcg_dots(v.z, v.r, nullptr, n, H->fcg_part, H->st, 0, s));
+    HIP_TRY(launch_copy(v.p, v.z, n, done, s));
+    return NN4MG_OK;
+}
+
+// One FCG(1) iteration: t = -A p, alpha, x and r update with the stopping
+// rule on ||r||, z = M r, beta, p = z + beta p.
+int enqueue_fcg_iteration(nn4mg_hier *H, double *x)
+{
+    const FcgVec v = fcg_vec(H);
+    const size_t n = H->lv[0].n;
+    hipStream_t s = H->stream;
+    const int *done = &H->st->done;
+    int rc;
+    H->cur_tag += 1;
+    if ((rc = enqueue_resid(H, v.p, v.zero, nullptr, v.t, nullptr, false, false, done))) return rc;
+    HIP_TRY(launch_fcg_alpha(v.p, v.t, n, H->fcg_part, H->st, s));
+    HIP_TRY(launch_fcg_update(H->st, x, v.p, v.r, v.t, H->mixed ? H->lv[0].b32 : nullptr, n, H->partials, s));
+    HIP_TRY(launch_finish_norm(H->st, H->partials, fcg_update_blocks(n), s));
+    if ((rc = enqueue_precondition(H, v.r, v.z, done))) return rc;
+    HIP_TRY(launch_fcg_dots(v.z, v.r, v.t, n, H->fcg_part, H->st, 2, s));
+    HIP_TRY(launch_fcg_direction(H->st, v.z, v.p, n, s));
+    return NN4MG_OK;
+}
+
+int enqueue_iteration(nn4mg_hier *H, const double *b, double *x)
+{
+    if (H->cfg.outer == NN4MG_OUTER_FCG) return enqueue_fcg_iteration(H, x);
+    return enqueue_stationary_iteration(H, b, x);
+}
+
 int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady_clock::time_point t0)
 {
     hipStream_t s = H->stream;
@@ -865,7 +946,7 @@ bool capture_iteration(nn4mg_hier *H, const double *b, double *x)
         return false;
     }
     const int saved_tag = H->cur_tag;
-    const int rc = enqueue_stationary_iteration(H, b, x);
+    const int rc = enqueue_iteration(H, b, x);
     H->cur_tag = saved_tag;
     const hipError_t e = hipStreamEndCapture(H->stream, &g);
     if (rc != NN4MG_OK || e != hipSuccess || !g) {
@@ -910,6 +991,7 @@ int solve_begin(nn4mg_hier *H, const double *b, double *x, double rtol, int max_
     H->cur_tag = 0;
     H->prof_solve_begin = H->prof_cls.size();
     if ((rc = enqueue_b_norm(H, b))) return rc;
+    if (H->cfg.outer == NN4MG_OUTER_FCG) return enqueue_fcg_start(H, b, x);
     if ((rc = enqueue_resid_for_cycle(H, b, x, H->singular ? &H->st->bmean : nullptr, true, &H->st->done))) return rc;
     HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), s));
     return NN4MG_OK;
@@ -926,7 +1008,7 @@ int solve_enqueue_next(nn4mg_hier *H, const double *b, double *x)
         H->cur_tag += n;
     } else {
         for (int c = 0; c < n; ++c)
-            if ((rc = enqueue_stationary_iteration(H, b, x))) return rc;
+            if ((rc = enqueue_iteration(H, b, x))) return rc;
     }
     H->solve_enqueued += n;
     return NN4MG_OK;

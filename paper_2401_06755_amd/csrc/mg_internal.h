@@ -132,6 +132,23 @@ int solve_after_header(nn4mg_hier *H);
 int solve_finish(nn4mg_hier *H, double *x, nn4mg_info *info);
 int hier_set_stream(nn4mg_hier *H, hipStream_t s);
 
+// ---- flexible CG vector kernels (mg_fcg.hip); t = -A p, q = A p = -t ----
+// dots: rho = z.r (mode 0), or rho = z.r and beta = -(z.q)/(p.q) (mode 2);
+// alpha: alpha = rho / (p.q) (breakdown if p.q <= 0); update: x += alpha p,
+// r -= alpha q, r32 = (float) r if r32 != NULL, per-block r^2 partials
+// (fcg_update_blocks of them, for launch_finish_norm); direction: p = z + beta p.
+int fcg_partials_needed();
+int fcg_update_blocks(size_t n);
+hipError_t launch_fcg_dots(const double *z, const double *r, const double *t, size_t n, double *partials,
+                           SolveState *st, int mode, hipStream_t s);
+hipError_t launch_fcg_alpha(const double *p, const double *t, size_t n, double *partials, SolveState *st,
+                            hipStream_t s);
+hipError_t launch_fcg_update(SolveState *st, double *x, const double *p, double *r, const double *t, float *r32,
+                             size_t n, double *partials, hipStream_t s);
+hipError_t launch_fcg_direction(SolveState *st, const double *z, double *p, size_t n, hipStream_t s);
+hipError_t launch_cast_f32(const double *src, float *dst, size_t n, const int *done, hipStream_t s);
+hipError_t launch_zero(double *x, size_t n, const int *done, hipStream_t s);
+
 // Record the message returned by nn4mg_last_error() on this thread; returns code.
 int set_error(int code, const char *msg);
 
