@@ -52,15 +52,25 @@ struct HasK<NoK> {
     static constexpr bool value = false;
 };
 
+// Storage type of a prefetched coefficient value (the value as loaded).
 template <typename T, typename KT>
-__device__ __forceinline__ T kload(const KT *k, size_t g)
+struct KStore {
+    using type = KT;
+};
+template <typename T>
+struct KStore<T, NoK> {
+    using type = T;
+};
+
+template <typename T, typename KT>
+__device__ __forceinline__ T kconv(typename KStore<T, KT>::type v)
 {
     if constexpr (std::is_same<KT, __half>::value)
-        return (T)__half2float(k[g]);
+        return (T)__half2float(v);
     else if constexpr (std::is_same<KT, NoK>::value)
         return (T)0;
     else
-        return (T)k[g];
+        return (T)v;
 }
 
 // 1/d: hardware reciprocal refined by Newton steps (two in FP64).
@@ -180,21 +190,30 @@ __device__ __forceinline__ void make_geo(Geo<TX, RY, PRO> &G, const StencilArgs 
     }
 }
 
-template <typename T, int TX, int RY, bool HK, bool PRO, bool ADD>
+// Registers of one prefetched plane, holding the values exactly as loaded:
+// halo signs, the z-interpolation of the coarse correction and coefficient
+// conversions are applied when the plane is committed to LDS, so no load
+// result is consumed before then and every load of the plane stays in flight.
+template <typename T, typename KT, int TX, int RY, bool PRO, bool ADD>
 struct Prefetch {
     T x[Tile<TX, RY>::NPRE];
-    T k[HK ? Tile<TX, RY>::NPRE : 1];
-    T c[PRO ? Tile<TX, RY>::NPREC : 1];
+    typename KStore<T, KT>::type k[HasK<KT>::value ? Tile<TX, RY>::NPRE : 1];
+    T c1[PRO ? Tile<TX, RY>::NPREC : 1];  // coarse plane nearest to z
+    T c2[PRO ? Tile<TX, RY>::NPREC : 1];  // the other coarse plane
     T bo[RY];                 // right-hand side of the output plane one below
     double xo[ADD ? RY : 1];  // FP64 field of that plane (OUT_ADD64)
+    bool zneg;                // the plane is a -mirror halo plane
+    T wK, wK2;                // z-interpolation weights with halo signs
 };
 
-// Issue the loads of fine plane z (field and k), of the z-interpolated coarse
-// footprint (prolongation modes) and of the output-plane values of z - 1.
+// Issue the loads of fine plane z (field and k), of the two coarse planes of
+// its z-interpolation (prolongation modes) and of the output-plane values of
+// z - 1.  Every address is in range (slots past the tile repeat the last
+// cell; rows past the grid read a clamped row), so the loads need no guards.
 template <typename T, typename KT, int IN, int TX, int RY, bool ADD>
-__device__ __forceinline__ void fetch(Prefetch<T, TX, RY, HasK<KT>::value, IN != IN_PLAIN, ADD> &p,
+__device__ __forceinline__ void fetch(Prefetch<T, KT, TX, RY, IN != IN_PLAIN, ADD> &p,
                                       const Geo<TX, RY, IN != IN_PLAIN> &G, const StencilArgs &a, int z, int z0,
-                                      size_t g0, const bool *valid)
+                                      const size_t *gb)
 {
     using TL = Tile<TX, RY>;
     const size_t plane = (size_t)a.g.nx * a.g.ny;
@@ -203,25 +222,21 @@ __device__ __forceinline__ void fetch(Prefetch<T, TX, RY, HasK<KT>::value, IN !=
         const size_t pl = plane * (size_t)(z - 1);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            p.bo[r] = valid[r] ? b[g0 + (size_t)r * a.g.nx + pl] : (T)0;
-            if constexpr (ADD) p.xo[r] = valid[r] ? a.x64[g0 + (size_t)r * a.g.nx + pl] : 0.0;
+            p.bo[r] = b[gb[r] + pl];
+            if constexpr (ADD) p.xo[r] = a.x64[gb[r] + pl];
         }
     }
     int sz = 1;
     const int fk = fold(z, a.g.nz, a.g.bc[4], a.g.bc[5], sz);
+    p.zneg = sz < 0;
     const size_t pz = plane * (size_t)fk;
     const T *yin = (const T *)a.yin;
     const KT *kp = (const KT *)a.k;
 #pragma unroll
     for (int q = 0; q < TL::NPRE; ++q) {
-        if (q * NT + (int)threadIdx.x < TL::PN) {
-            const size_t g = pz + (size_t)G.off[q];
-            if constexpr (IN != IN_PROLONG) {
-                const T v = yin[g];
-                p.x[q] = (G.neg[q] != (sz < 0)) ? -v : v;
-            }
-            if constexpr (HasK<KT>::value) p.k[q] = kload<T, KT>(kp, g);
-        }
+        const size_t g = pz + (size_t)G.off[q];
+        if constexpr (IN != IN_PROLONG) p.x[q] = yin[g];
+        if constexpr (HasK<KT>::value) p.k[q] = kp[g];
     }
     if constexpr (IN != IN_PLAIN) {
         const T *e = (const T *)a.ec;
@@ -229,30 +244,33 @@ __device__ __forceinline__ void fetch(Prefetch<T, TX, RY, HasK<KT>::value, IN !=
         int sK = 1, sK2 = 1;
         const int fK = fold(K, a.cnz, a.g.bc[4], a.g.bc[5], sK);
         const int fK2 = fold(K + ((z & 1) ? 1 : -1), a.cnz, a.g.bc[4], a.g.bc[5], sK2);
-        const T wK = (T)(0.75 * sK), wK2 = (T)(0.25 * sK2);
+        p.wK = (T)(0.75 * sK);
+        p.wK2 = (T)(0.25 * sK2);
         const size_t cpl = (size_t)a.cnx * a.cny;
         const size_t p1 = cpl * (size_t)fK, p2 = cpl * (size_t)fK2;
 #pragma unroll
         for (int q = 0; q < TL::NPREC; ++q) {
-            if (q * NT + (int)threadIdx.x < TL::CN) {
-                const size_t g = (size_t)G.coff[q];
-                const T v = wK * e[g + p1] + wK2 * e[g + p2];
-                p.c[q] = G.cneg[q] ? -v : v;
-            }
+            const size_t g = (size_t)G.coff[q];
+            p.c1[q] = e[g + p1];
+            p.c2[q] = e[g + p2];
         }
     }
 }
 
 // Write a prefetched plane to LDS (forming x + P e for the prolongation modes).
-template <typename T, bool HK, int IN, int TX, int RY, bool ADD>
-__device__ __forceinline__ void commit(const Prefetch<T, TX, RY, HK, IN != IN_PLAIN, ADD> &p,
+template <typename T, typename KT, int IN, int TX, int RY, bool ADD>
+__device__ __forceinline__ void commit(const Prefetch<T, KT, TX, RY, IN != IN_PLAIN, ADD> &p,
                                        const Geo<TX, RY, IN != IN_PLAIN> &G, T *sx, T *sk, T *scoarse)
 {
     using TL = Tile<TX, RY>;
+    constexpr bool HK = HasK<KT>::value;
     if constexpr (IN != IN_PLAIN) {
 #pragma unroll
         for (int q = 0; q < TL::NPREC; ++q)
-            if (q * NT + (int)threadIdx.x < TL::CN) scoarse[q * NT + threadIdx.x] = p.c[q];
+            if (q * NT + (int)threadIdx.x < TL::CN) {
+                const T v = p.wK * p.c1[q] + p.wK2 * p.c2[q];
+                scoarse[q * NT + threadIdx.x] = G.cneg[q] ? -v : v;
+            }
         __syncthreads();
     }
 #pragma unroll
@@ -260,16 +278,16 @@ __device__ __forceinline__ void commit(const Prefetch<T, TX, RY, HK, IN != IN_PL
         const int idx = q * NT + threadIdx.x;
         if (idx < TL::PN) {
             if constexpr (IN == IN_PLAIN) {
-                sx[idx] = p.x[q];
+                sx[idx] = (G.neg[q] != p.zneg) ? -p.x[q] : p.x[q];
             } else {
                 const T w3 = (T)0.75, w1 = (T)0.25;
                 const int t0 = G.tap[q], t1 = t0 + G.tdy[q];
                 T v = w3 * (w3 * scoarse[t0] + w1 * scoarse[t0 + G.tdx[q]]) +
                       w1 * (w3 * scoarse[t1] + w1 * scoarse[t1 + G.tdx[q]]);
-                if constexpr (IN == IN_PROLONG_ADD) v += p.x[q];
+                if constexpr (IN == IN_PROLONG_ADD) v += (G.neg[q] != p.zneg) ? -p.x[q] : p.x[q];
                 sx[idx] = v;
             }
-            if constexpr (HK) sk[idx] = p.k[q];
+            if constexpr (HK) sk[idx] = kconv<T, KT>(p.k[q]);
         }
     }
     __syncthreads();
@@ -367,6 +385,9 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
     for (int r = 0; r < RY; ++r) valid[r] = gi < nx && gj + r < ny;
     const size_t plane = (size_t)nx * ny;
     const size_t g0 = (size_t)gi + (size_t)nx * (size_t)gj;  // (gi, gj, 0); row r adds r * nx
+    size_t gb[RY];  // load offsets of the thread's rows, clamped into the grid
+#pragma unroll
+    for (int r = 0; r < RY; ++r) gb[r] = (size_t)min(gi, nx - 1) + (size_t)nx * (size_t)min(gj + r, ny - 1);
 
     // Scaled filter constants: constant coefficient A y = cw (S - 32 y) with
     // cw = -h/12; nodal A y = cv [(32 k + S[k]) y - k S[y] - S[k y]], cv = h/24.
@@ -379,7 +400,7 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
 
     Geo<TX, RY, PRO> G;
     make_geo<TX, RY, PRO>(G, a, i0, j0);
-    Prefetch<T, TX, RY, HK, PRO, ADD> pA, pB;
+    Prefetch<T, KT, TX, RY, PRO, ADD> pA, pB;
     PlaneSums<T> ps[RY];
     Run<T> run[RY];
 
@@ -406,8 +427,8 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
     // One output plane: commit plane z + 1 from slot p, refill the slot with
     // plane z + 3 (two planes stay in flight), then finish plane z.
     int buf = 0;
-    auto step = [&](Prefetch<T, TX, RY, HK, PRO, ADD> &p, int z) {
-        commit<T, HK, IN, TX, RY, ADD>(p, G, sx[buf], sk[buf], sc);
+    auto step = [&](Prefetch<T, KT, TX, RY, PRO, ADD> &p, int z) {
+        commit<T, KT, IN, TX, RY, ADD>(p, G, sx[buf], sk[buf], sc);
         T bcur[RY];
         double xcur[ADD ? RY : 1];
 #pragma unroll
@@ -415,7 +436,7 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
             bcur[r] = p.bo[r];
             if constexpr (ADD) xcur[r] = p.xo[r];
         }
-        if (z + 3 <= z1) fetch<T, KT, IN, TX, RY, ADD>(p, G, a, z + 3, z0, g0, valid);
+        if (z + 3 <= z1) fetch<T, KT, IN, TX, RY, ADD>(p, G, a, z + 3, z0, gb);
         plane_sums<T, HK, TX, RY>(sx[buf], sk[buf], lx, ly, ps);
         buf ^= 1;
         double rrow[RY];
@@ -479,14 +500,14 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
 
     // prologue: planes z0 - 1 and z0 into the running sums; planes z0 + 1 and
     // z0 + 2 (with the right-hand sides of planes z0 and z0 + 1) in flight
-    fetch<T, KT, IN, TX, RY, ADD>(pA, G, a, z0 - 1, z0, g0, valid);
-    commit<T, HK, IN, TX, RY, ADD>(pA, G, sx[0], sk[0], sc);
-    fetch<T, KT, IN, TX, RY, ADD>(pA, G, a, z0, z0, g0, valid);
+    fetch<T, KT, IN, TX, RY, ADD>(pA, G, a, z0 - 1, z0, gb);
+    commit<T, KT, IN, TX, RY, ADD>(pA, G, sx[0], sk[0], sc);
+    fetch<T, KT, IN, TX, RY, ADD>(pA, G, a, z0, z0, gb);
     plane_sums<T, HK, TX, RY>(sx[0], sk[0], lx, ly, ps);
     absorb(true);
-    commit<T, HK, IN, TX, RY, ADD>(pA, G, sx[1], sk[1], sc);
-    fetch<T, KT, IN, TX, RY, ADD>(pA, G, a, z0 + 1, z0, g0, valid);
-    if (z0 + 2 <= z1) fetch<T, KT, IN, TX, RY, ADD>(pB, G, a, z0 + 2, z0, g0, valid);
+    commit<T, KT, IN, TX, RY, ADD>(pA, G, sx[1], sk[1], sc);
+    fetch<T, KT, IN, TX, RY, ADD>(pA, G, a, z0 + 1, z0, gb);
+    if (z0 + 2 <= z1) fetch<T, KT, IN, TX, RY, ADD>(pB, G, a, z0 + 2, z0, gb);
     plane_sums<T, HK, TX, RY>(sx[1], sk[1], lx, ly, ps);
     absorb(false);
 
