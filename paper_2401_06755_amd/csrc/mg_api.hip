@@ -225,6 +225,7 @@ struct nn4mg_hier {
     hipStream_t stream = nullptr;
     int L = 0;
     Level lv[kMaxLevels];
+    int tail = 0;           // first level of the one-workgroup coarse end (0: none)
     int singular = 0;
     int mixed = 0;
     int kt64 = KT_NONE;     // coefficient type of FP64 launches
@@ -317,6 +318,27 @@ size_t bytes_for(const nn4mg_config *c)
     b += 8 * nc * nc + sizeof(SolveState) + 8 * maxblk + 64 + 4;
     if (c->outer == NN4MG_OUTER_FCG) b += 5 * 8 * (size_t)c->nx * c->ny * c->nz + 8 * (size_t)fcg_partials_needed();
     return b;
+}
+
+// The coarse end of the cycle runs in one workgroup from the first level whose
+// fields (right-hand side and two iterates per level, down to the coarsest)
+// fit the LDS budget.
+constexpr size_t kTailLdsBudget = 128 * 1024;
+// One compute unit sweeps a 16^3 level slower than the whole chip does including
+// its launch; up to about a thousand cells the single workgroup wins.
+constexpr size_t kTailMaxCells = 1024;
+int choose_tail(const nn4mg_hier *H)
+{
+    if (H->L < 2) return 0;
+    const size_t elt = H->mixed ? 4 : 8;
+    const size_t fields = H->cfg.coef_mode == NN4MG_COEF_NODAL ? 4 : 3;
+    for (int T = 1; T < H->L; ++T) {
+        if (H->L - T > kTailMaxLevels) continue;
+        size_t n = 0;
+        for (int l = T; l < H->L; ++l) n += H->lv[l].n;
+        if (fields * n * elt + 48 * 1024 <= kTailLdsBudget && H->lv[T].n <= kTailMaxCells) return T;
+    }
+    return H->L - 1;
 }
 
 int rebuild_coefficients(nn4mg_hier *H)
@@ -549,6 +571,42 @@ int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, doub
     const int L = H->L;
     hipStream_t s = H->stream;
     int rc;
+    if (H->tail > 0) {
+        const int T = H->tail;
+        for (int l = 1; l + 1 < T; ++l) {
+            Level &V = H->lv[l];
+            HIP_TRY(launch_restrict(f64 ? 1 : 0, f64 ? (void *)V.b : (void *)V.b32,
+                                    f64 ? (void *)H->lv[l + 1].b : (void *)H->lv[l + 1].b32, V.nx, V.ny, V.nz, done,
+                                    s));
+        }
+        TailArgs ta;
+        std::memset(&ta, 0, sizeof(ta));
+        ta.levels = L - T;
+        for (int l = T; l < L; ++l) {
+            const Level &V = H->lv[l];
+            ta.nx[l - T] = V.nx;
+            ta.ny[l - T] = V.ny;
+            ta.nz[l - T] = V.nz;
+            ta.h[l - T] = V.h;
+            ta.k[l - T] = f64 ? (const void *)V.k : V.ks;
+        }
+        if (T >= 2)
+            ta.b_above = f64 ? (const void *)H->lv[T - 1].b : (const void *)H->lv[T - 1].b32;
+        else
+            ta.b_first = f64 ? (const void *)H->lv[T].b : (const void *)H->lv[T].b32;
+        ta.e_first = f64 ? (void *)H->lv[T].e : (void *)H->lv[T].e32;
+        ta.ainv = H->ainv;
+        ta.ainv_in_lds = (size_t)H->nc * H->nc * 8 <= 48 * 1024;
+        ta.singular = H->singular;
+        for (int f = 0; f < 6; ++f) ta.bc[f] = H->cfg.bc[f];
+        ta.omega = H->cfg.omega;
+        ta.nu = H->cfg.nu_post;
+        ta.done = done;
+        HIP_TRY(launch_tail(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, ta, s));
+        for (int l = T - 1; l >= 1; --l)
+            if ((rc = enqueue_coarse_sweeps(H, l, done))) return rc;
+        return enqueue_fine_sweeps(H, b, bmean, x, done, x_zero);
+    }
     for (int l = 1; l + 1 < L; ++l) {
         Level &V = H->lv[l];
         HIP_TRY(launch_restrict(f64 ? 1 : 0, f64 ? (void *)V.b : (void *)V.b32,
@@ -709,6 +767,7 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
         }
     const Level &C = H->lv[H->L - 1];
     H->nc = (int)C.n;
+    H->tail = choose_tail(H);
     TRY(dalloc(H, &H->ainv, (size_t)H->nc * H->nc));
     TRY(dalloc(H, &H->st, 1));
     TRY(dalloc(H, &H->partials, (size_t)maxblk));

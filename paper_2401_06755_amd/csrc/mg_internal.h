@@ -149,6 +149,27 @@ hipError_t launch_fcg_direction(SolveState *st, const double *z, double *p, size
 hipError_t launch_cast_f32(const double *src, float *dst, size_t n, const int *done, hipStream_t s);
 hipError_t launch_zero(double *x, size_t n, const int *done, hipStream_t s);
 
+// ---- coarse end of the cycle in one workgroup (mg_tail.hip) ----
+constexpr int kTailMaxLevels = 8;
+struct TailArgs {
+    int levels;                         // tail levels, finest first; the last is the coarsest
+    int nx[kTailMaxLevels], ny[kTailMaxLevels], nz[kTailMaxLevels];
+    double h[kTailMaxLevels];
+    const void *k[kTailMaxLevels];      // coefficient per level (storage type of the launch), NULL if constant
+    const void *b_above;                // right-hand side of the level above the first tail level, or NULL
+    const void *b_first;                // right-hand side of the first tail level (when b_above is NULL)
+    void *e_first;                      // out: correction of the first tail level
+    const double *ainv;                 // coarsest inverse (FP64, symmetric)
+    int ainv_in_lds;                    // stage the inverse in LDS (it fits)
+    int singular;
+    int bc[6];
+    double omega;
+    int nu;
+    const int *done;                    // skip when *done != 0 (may be NULL)
+};
+size_t tail_lds_bytes(const TailArgs &a, int t_is_f64, int nodal);
+hipError_t launch_tail(int T_is_f64, int kt, const TailArgs &a, hipStream_t s);
+
 // Record the message returned by nn4mg_last_error() on this thread; returns code.
 int set_error(int code, const char *msg);
 
