@@ -33,23 +33,25 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0
 
 # Algorithmic bytes per finest cell of each finest-level kernel class: every
-# array the kernel needs is read once and every output written once.
+# array the kernel needs is read once and every output written once.  With the
+# default two post-sweeps, both run in one pass ("sweeps") that smooths the
+# correction against the residual the residual kernel writes out.
 BYTES_PER_CELL = {
-    "fp64": {"resid": 8 + 8 + 8 + 1,          # x, b, k; restricted residual (1/8 cell)
-             "sweep_prolong": 8 + 1 + 8 + 8 + 8,  # x, e_1 (1/8), b, k; y
-             "sweep": 8 + 8 + 8 + 8},          # y, b, k; x
+    "fp64": {"resid": 8 + 8 + 8 + 8 + 1,      # x, b, k; r, restricted residual (1/8 cell)
+             "sweeps": 1 + 8 + 8 + 8 + 8,     # e_1 (1/8), r, k; x read + write
+             "sweep": 8 + 8 + 8 + 8},         # (nu_post != 2 only) y, b, k; x
     "mixed": {"resid": 8 + 8 + 8 + 4 + 0.5,   # x, b, k (FP64); r32, restricted r32
-              "sweep_prolong": 0.5 + 4 + 4 + 4,  # e_1 (FP32, 1/8), r32, k32; y32
-              "sweep": 4 + 4 + 4 + 8 + 8},     # y32, r32, k32; x64 read + write
+              "sweeps": 0.5 + 4 + 4 + 8 + 8,  # e_1 (FP32, 1/8), r32, k32; x64 read + write
+              "sweep": 4 + 4 + 4 + 8 + 8},    # (nu_post != 2 only)
 }
-KCLASS = {"resid": 0, "sweep_prolong": 1, "sweep": 2}
+KCLASS = {"resid": 0, "sweeps": 1, "sweep": 2}
 
 # HBM bytes per finest-level launch (256^3, FP64, nodal k) from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for
 # a plain 256 MiB device copy (fetch x2.0, write x1.0); the commands and raw
 # counts are in profiles/dense_sphere_256_fp64_fine_kernels.md.  Valid for the
 # stencil kernel as profiled; set to None when the kernel changes.
-MEASURED_TRAFFIC_FP64_256 = {"resid": 486.0e6, "sweep_prolong": 572.9e6, "sweep": 572.2e6}
+MEASURED_TRAFFIC_FP64_256 = {"resid": 617.1e6, "sweeps": 589.4e6}
 
 
 def log(msg):
@@ -58,15 +60,15 @@ def log(msg):
 
 def cycle_model_bytes(levels, mode):
     """Algorithmic bytes of one V(0,2) cycle over all levels (finest kernels as
-    above; coarse level l: restriction 8+1 B, two sweeps like the finest ones
-    without x; FP32 on coarse levels in mixed mode)."""
+    above; coarse level l: restriction w + w/8 B, both sweeps in one pass
+    reading e_{l+1} (w/8), b, k and writing e (3w); FP32 on coarse levels in
+    mixed mode)."""
     w = 8 if mode == "fp64" else 4
     n0 = levels[0][0] * levels[0][1] * levels[0][2]
-    tot = n0 * sum(BYTES_PER_CELL[mode].values())
+    tot = n0 * (BYTES_PER_CELL[mode]["resid"] + BYTES_PER_CELL[mode]["sweeps"])
     for l in range(1, len(levels) - 1):
         n = levels[l][0] * levels[l][1] * levels[l][2]
-        restrict = w + w / 8
-        tot += n * (restrict + (w / 8 + 3 * w) + 4 * w)
+        tot += n * ((w + w / 8) + (w / 8 + 3 * w))
     return tot
 
 

@@ -226,6 +226,7 @@ struct nn4mg_hier {
     int L = 0;
     Level lv[kMaxLevels];
     int tail = 0;           // first level of the one-workgroup coarse end (0: none)
+    bool fused = false;     // both post-sweeps of a level in one pass (nu_post == 2)
     int singular = 0;
     int mixed = 0;
     int kt64 = KT_NONE;     // coefficient type of FP64 launches
@@ -463,9 +464,50 @@ int enqueue_resid(nn4mg_hier *H, const double *x, const double *b, const double 
     return NN4MG_OK;
 }
 
+// Launch shape of the two-sweep kernel at level l: the first-sweep class's
+// shape when the kernel has an instance for it.
+TileShape sweep2_tiles(const nn4mg_hier *H, int l)
+{
+    const Level &V = H->lv[l];
+    TileShape t = V.tiles[NN4MG_KCLASS_FINE_SWEEP_PROLONG];
+    if (!sweep2_supports(t.tx, t.ry)) t = make_tiles(V.nx, V.ny, V.nz, t.zc, t.tx == 16 ? 16 : t.tx, t.tx == 16 ? 2 : 1);
+    return t;
+}
+
+// Both sweeps of level l from P e_{l+1} against the right-hand side b:
+// out_mode OUT_STORE into y, or OUT_ADD64 into x64.
+int enqueue_sweep2(nn4mg_hier *H, int l, const void *b, void *y, double *x64, int out_mode, const int *done)
+{
+    const bool f64 = !H->mixed;
+    StencilArgs a = base_args(H, l, NN4MG_KCLASS_FINE_SWEEP_PROLONG);
+    a.t = sweep2_tiles(H, l);
+    a.b = b;
+    a.k = f64 ? (const void *)H->lv[l].k : H->lv[l].ks;
+    a.ec = f64 ? (const void *)H->lv[l + 1].e : (const void *)H->lv[l + 1].e32;
+    a.yout = y;
+    a.x64 = x64;
+    a.done = done;
+    const long pr = prof_begin(H, NN4MG_KCLASS_FINE_SWEEP_PROLONG, l);
+    HIP_TRY(launch_sweep2(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, out_mode, a, H->stream));
+    prof_end(H, pr);
+    return NN4MG_OK;
+}
+
+bool level_fusable(const nn4mg_hier *H, int l)
+{
+    const Level &V = H->lv[l];
+    return H->fused && V.nx >= 4 && V.ny >= 4 && V.nz >= 4;
+}
+
 // nu_post Jacobi sweeps at level l >= 1 (first input: P e_{l+1}); result in e.
 int enqueue_coarse_sweeps(nn4mg_hier *H, int l, const int *done)
 {
+    if (level_fusable(H, l)) {
+        Level &V = H->lv[l];
+        const bool f64 = !H->mixed;
+        return enqueue_sweep2(H, l, f64 ? (const void *)V.b : (const void *)V.b32,
+                              f64 ? (void *)V.e : (void *)V.e32, nullptr, OUT_STORE, done);
+    }
     Level &V = H->lv[l];
     const int nu = H->cfg.nu_post;
     const bool f64 = !H->mixed;
@@ -501,6 +543,13 @@ int enqueue_fine_sweeps(nn4mg_hier *H, const double *b, const double *bmean, dou
 {
     Level &F = H->lv[0];
     const int nu = H->cfg.nu_post;
+    if (level_fusable(H, 0)) {
+        if (H->mixed) return enqueue_sweep2(H, 0, F.b32, nullptr, x, OUT_ADD64, done);
+        // FP64: the correction is smoothed against the full residual (written by
+        // the residual kernel into F.t, or the preconditioner's own r)
+        if (x_zero) return enqueue_sweep2(H, 0, b, x, nullptr, OUT_STORE, done);
+        return enqueue_sweep2(H, 0, F.t, nullptr, x, OUT_ADD64, done);
+    }
     if (!H->mixed) {
         void *buf[2] = {F.t, x};
         int cur = 0;
@@ -632,7 +681,8 @@ int enqueue_resid_for_cycle(nn4mg_hier *H, const double *b, const double *x, con
     }
     if (H->mixed)
         return enqueue_resid(H, x, b, bmean, H->lv[0].b32, H->lv[1].b32, true, with_norm, done);
-    return enqueue_resid(H, x, b, bmean, nullptr, H->lv[1].b, false, with_norm, done);
+    // the fused finest sweeps smooth the correction against the full residual
+    return enqueue_resid(H, x, b, bmean, H->fused ? H->lv[0].t : nullptr, H->lv[1].b, false, with_norm, done);
 }
 
 int enqueue_single_level_body(nn4mg_hier *H, double *x, const int *done)
@@ -768,6 +818,7 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
     const Level &C = H->lv[H->L - 1];
     H->nc = (int)C.n;
     H->tail = choose_tail(H);
+    H->fused = cfg->nu_post == 2 && H->L >= 2;
     TRY(dalloc(H, &H->ainv, (size_t)H->nc * H->nc));
     TRY(dalloc(H, &H->st, 1));
     TRY(dalloc(H, &H->partials, (size_t)maxblk));
@@ -1176,14 +1227,20 @@ int nn4mg_set_tiles(nn4mg_t H, int level, int kclass, int tx, int ry, int zc)
     if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
     if (level < 0 || level >= H->L) return fail(NN4MG_EINVAL, "bad level");
     if (kclass < -1 || kclass >= NN4MG_KCLASS_COUNT) return fail(NN4MG_EINVAL, "bad kernel class");
-    if ((tx != 64 && tx != 32 && tx != 16) || (ry != 2 && ry != 4) || (tx == 16 && ry != 2) || zc < 2 || (zc & 1))
+    if ((tx != 64 && tx != 32 && tx != 16) || (ry != 1 && ry != 2 && ry != 4) || (tx == 16 && ry == 4) || zc < 2 ||
+        (zc & 1))
         return fail(NN4MG_EINVAL, "bad tile shape");
+    if (ry == 1 && kclass == NN4MG_KCLASS_FINE_RESID)
+        return fail(NN4MG_EINVAL, "the residual kernel needs an even number of rows per thread");
     Level &V = H->lv[level];
     const TileShape t = make_tiles(V.nx, V.ny, V.nz, zc, tx, ry);
-    if (t.blocks() > H->max_partials) return fail(NN4MG_EINVAL, "tile shape needs too many workgroups");
+    if (t.blocks() > H->max_partials && (kclass < 0 || kclass == NN4MG_KCLASS_FINE_RESID))
+        return fail(NN4MG_EINVAL, "tile shape needs too many workgroups");
     HIP_TRY(hipStreamSynchronize(H->stream));
-    for (int c = 0; c < NN4MG_KCLASS_COUNT; ++c)
+    for (int c = 0; c < NN4MG_KCLASS_COUNT; ++c) {
+        if (ry == 1 && c == NN4MG_KCLASS_FINE_RESID) continue;  // kclass -1: sweeps only
         if (kclass < 0 || kclass == c) V.tiles[c] = t;
+    }
     H->tiles_epoch++;
     return NN4MG_OK;
 }
@@ -1204,8 +1261,9 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
 {
     if (!H || !b || !x) return fail(NN4MG_EINVAL, "NULL argument");
     const int L = H->L;
-    const int txs[5] = {64, 64, 32, 32, 16};
-    const int rys[5] = {2, 4, 2, 4, 2};
+    constexpr int NT_SHAPES = 8;
+    const int txs[NT_SHAPES] = {64, 64, 32, 32, 16, 64, 32, 16};
+    const int rys[NT_SHAPES] = {2, 4, 2, 4, 2, 1, 1, 1};
     const int zcs[5] = {2, 4, 8, 16, 32};
     const int reps = 3;
     constexpr int NC = NN4MG_KCLASS_COUNT;
@@ -1222,15 +1280,22 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
         H->prof_solve_begin = 0;
     };
     int rc;
-    for (int ti = 0; ti < 5; ++ti)
+    for (int ti = 0; ti < NT_SHAPES; ++ti)
         for (int zi = 0; zi < 5; ++zi) {
             std::vector<bool> used(L, false);
             for (int l = 0; l < L; ++l) {
                 Level &V = H->lv[l];
                 if (zcs[zi] > V.nz + (V.nz & 1)) continue;
                 const TileShape t = make_tiles(V.nx, V.ny, V.nz, zcs[zi], txs[ti], rys[ti]);
-                if (t.blocks() > H->max_partials) continue;
-                for (int c = 0; c < NC; ++c) V.tiles[c] = t;
+                // one row per thread: sweep classes only; the residual keeps its best shape so far
+                if (rys[ti] == 1) {
+                    V.tiles[NN4MG_KCLASS_FINE_RESID] = best_t[(size_t)l * NC + NN4MG_KCLASS_FINE_RESID];
+                    for (int c = 0; c < NC; ++c)
+                        if (c != NN4MG_KCLASS_FINE_RESID) V.tiles[c] = t;
+                } else {
+                    if (t.blocks() > H->max_partials) continue;
+                    for (int c = 0; c < NC; ++c) V.tiles[c] = t;
+                }
                 used[l] = true;
             }
             HIP_TRY(hipStreamSynchronize(H->stream));

@@ -1,0 +1,407 @@
+// Both post-smoothing sweeps of a level in one z-marching pass (gfx950).
+//
+// The sawtooth cycle of Fig. multi-grid (arXiv 2401.06755, Sec. 2.4) ends
+// each level with the prolongation of the coarser correction and nu_post = 2
+// weighted-Jacobi sweeps.  Run as two kernels, the second sweep re-reads from
+// HBM the first one's output, the right-hand side and the coefficient.  Here
+// one workgroup keeps both sweeps in flight, one plane apart:
+//   * the first sweep is computed on the workgroup's TX x TY output tile plus
+//     a one-cell ring (the second sweep's stencil reaches one cell out), from
+//     input planes staged in LDS with a two-cell ring;
+//   * its output plane goes to LDS and feeds the second sweep, whose running
+//     plane sums lag one plane behind.
+// Ring cells that lie outside the grid are computed like any other cell from
+// halo-synthesised inputs: the sweep commutes with the boundary reflections
+// (Dirichlet -mirror, Neumann +mirror, periodic wrap), so they hold the halo
+// values of the first sweep's output.
+// The input of the first sweep is the prolongated correction P e of the
+// coarser level (no fine-level iterate is read), so the pair computes the
+// correction of this level for the right-hand side b: with b = r = b - A x
+// (the residual the finest residual kernel already forms) and x += e this is
+// exactly x <- S S (x + P e), since the Jacobi sweep is affine.  Output: the
+// correction stored (coarse levels, preconditioner z) or added into an FP64
+// field (finest level).
+// Operator and sweep are those of the single-sweep kernel: with the plane
+// sums D (corners) and X (crosses) of the 3x3 neighbourhood,
+//   S = 2 D(z) + 2 (X(z-1) + X(z+1)) + D(z-1) + D(z+1),
+//   constant coefficient  A y = (-h/12) (S[y] - 32 y),
+//   nodal coefficient     A_k y = (h/24) [(32 k + S[k]) y - k S[y] - S[k y]] (Eq. k-T).
+#include "mg_device.h"
+#include "mg_internal.h"
+
+namespace nn4mg {
+
+namespace {
+
+constexpr int FT = 256;
+
+template <int TX, int RY>
+struct FTile {
+    static constexpr int TYT = FT / TX;                             // thread rows
+    static constexpr int TY = RY * TYT;                             // output rows
+    static constexpr int QX = TX + 2, QY = TY + 2, QN = QX * QY;    // first-sweep region
+    static constexpr int PX = TX + 4, PY = TY + 4, PN = PX * PY;    // input region
+    static constexpr int NPRE = (PN + FT - 1) / FT;                 // input slots per thread
+    static constexpr int NS1 = (QN + FT - 1) / FT;                  // first-sweep slots per thread
+    static constexpr int CX = TX / 2 + 4, CY = TY / 2 + 4, CN = CX * CY;  // coarse footprint
+    static constexpr int NPREC = (CN + FT - 1) / FT;
+};
+
+// Plane-invariant geometry of a thread's slots.
+template <int TX, int RY>
+struct FGeo {
+    using TL = FTile<TX, RY>;
+    int off[TL::NPRE];    // folded in-plane offset of each input slot (coefficient)
+    int tap[TL::NPRE];    // prolongation: LDS tap | x-neighbour bit << 16 | y-neighbour bit << 17
+    int coff[TL::NPREC];  // folded in-plane offset of each coarse slot
+    bool cneg[TL::NPREC];
+    int boff[TL::NS1];    // folded in-plane offset of each first-sweep slot (right-hand side)
+    bool bneg[TL::NS1];
+};
+
+template <int TX, int RY>
+__device__ __forceinline__ void make_fgeo(FGeo<TX, RY> &G, const StencilArgs &a, int i0, int j0)
+{
+    using TL = FTile<TX, RY>;
+    const int ci0 = (i0 >> 1) - 2, cj0 = (j0 >> 1) - 2;
+#pragma unroll
+    for (int q = 0; q < TL::NPRE; ++q) {
+        const int idx = min((int)threadIdx.x + q * FT, TL::PN - 1);
+        const int py = idx / TL::PX, px = idx - py * TL::PX;
+        const int ui = i0 + px - 2, uj = j0 + py - 2;  // unfolded fine position
+        int s = 1;
+        G.off[q] = fold(ui, a.g.nx, a.g.bc[0], a.g.bc[1], s) + a.g.nx * fold(uj, a.g.ny, a.g.bc[2], a.g.bc[3], s);
+        const int I = ui >> 1, J = uj >> 1;  // floor
+        const int t0 = (J - cj0) * TL::CX + (I - ci0);
+        G.tap[q] = t0 | ((ui & 1) << 16) | ((uj & 1) << 17);
+    }
+#pragma unroll
+    for (int q = 0; q < TL::NPREC; ++q) {
+        const int idx = min((int)threadIdx.x + q * FT, TL::CN - 1);
+        const int cy = idx / TL::CX, cx = idx - cy * TL::CX;
+        int s = 1;
+        const int fI = fold(ci0 + cx, a.cnx, a.g.bc[0], a.g.bc[1], s);
+        const int fJ = fold(cj0 + cy, a.cny, a.g.bc[2], a.g.bc[3], s);
+        G.coff[q] = fI + a.cnx * fJ;
+        G.cneg[q] = s < 0;
+    }
+#pragma unroll
+    for (int q = 0; q < TL::NS1; ++q) {
+        const int idx = min((int)threadIdx.x + q * FT, TL::QN - 1);
+        const int qy = idx / TL::QX, qx = idx - qy * TL::QX;
+        int s = 1;
+        const int fi = fold(i0 + qx - 1, a.g.nx, a.g.bc[0], a.g.bc[1], s);
+        const int fj = fold(j0 + qy - 1, a.g.ny, a.g.bc[2], a.g.bc[3], s);
+        G.boff[q] = fi + a.g.nx * fj;
+        G.bneg[q] = s < 0;
+    }
+}
+
+// Loads of one input plane zi, as loaded (signs and weights applied later):
+// coefficient and coarse correction of plane zi, first-sweep right-hand side
+// of plane zi - 1 and second-sweep right-hand side (and FP64 field) of zi - 2.
+template <typename T, typename KT, int TX, int RY, bool ADD>
+struct FPre {
+    using TL = FTile<TX, RY>;
+    typename KStore<T, KT>::type k[HasK<KT>::value ? TL::NPRE : 1];
+    T c1[TL::NPREC], c2[TL::NPREC];
+    T b1[TL::NS1];
+    T b2[RY];
+    double xo[ADD ? RY : 1];
+};
+
+template <typename T>
+struct PS {
+    T xc, xa, xo, kc, ka, ko, pa, po;
+};
+
+template <typename T>
+struct Run {
+    T qx, ox, qk, ok, qp, op, xc, kc;
+};
+
+// Plane sums at one position of a plane with row stride W (field v, coefficient k).
+template <typename T, bool HK, int W, int WK>
+__device__ __forceinline__ void sums_at(const T *v, int c, const T *k, int ck, PS<T> &o)
+{
+    const T v00 = v[c - W - 1], v01 = v[c - W], v02 = v[c - W + 1];
+    const T v10 = v[c - 1], v11 = v[c], v12 = v[c + 1];
+    const T v20 = v[c + W - 1], v21 = v[c + W], v22 = v[c + W + 1];
+    const T D = (v00 + v02) + (v20 + v22);
+    const T X = (v01 + v21) + (v10 + v12);
+    o.xc = v11;
+    o.xa = D + D;
+    o.xo = fma((T)2, X, D);
+    if constexpr (HK) {
+        const T k00 = k[ck - WK - 1], k01 = k[ck - WK], k02 = k[ck - WK + 1];
+        const T k10 = k[ck - 1], k11 = k[ck], k12 = k[ck + 1];
+        const T k20 = k[ck + WK - 1], k21 = k[ck + WK], k22 = k[ck + WK + 1];
+        const T Dk = (k00 + k02) + (k20 + k22);
+        const T Xk = (k01 + k21) + (k10 + k12);
+        const T Dp = (k00 * v00 + k02 * v02) + (k20 * v20 + k22 * v22);
+        const T Xp = (k01 * v01 + k21 * v21) + (k10 * v10 + k12 * v12);
+        o.kc = k11;
+        o.ka = Dk + Dk;
+        o.ko = fma((T)2, Xk, Dk);
+        o.pa = Dp + Dp;
+        o.po = fma((T)2, Xp, Dp);
+    }
+}
+
+template <typename T, bool HK>
+__device__ __forceinline__ void absorb(Run<T> &r, const PS<T> &p, bool first)
+{
+    r.qx = first ? p.xa : p.xa + r.ox;
+    r.ox = p.xo;
+    r.xc = p.xc;
+    if constexpr (HK) {
+        r.qk = first ? p.ka : p.ka + r.ok;
+        r.qp = first ? p.pa : p.pa + r.op;
+        r.ok = p.ko;
+        r.op = p.po;
+        r.kc = p.kc;
+    }
+}
+
+// One Jacobi update of the cell whose plane sums complete with plane p.
+template <typename T, bool HK>
+__device__ __forceinline__ T jacobi(const Run<T> &r, const PS<T> &p, T bb, T cw, T om_w0, T om, T icv)
+{
+    const T y0 = r.xc;
+    if constexpr (!HK) {
+        const T S = r.qx + p.xo;
+        return y0 + om_w0 * (bb - cw * (S - (T)32 * y0));
+    } else {
+        const T Sx = r.qx + p.xo, Sk = r.qk + p.ko, Sp = r.qp + p.po;
+        const T Dg = fma((T)32, r.kc, Sk);
+        const T Ays = Dg * y0 - r.kc * Sx - Sp;
+        return y0 + om * (bb * icv - Ays) * recip(Dg);
+    }
+}
+
+template <typename T, typename KT, int OUT, int TX, int RY>
+__global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
+{
+    if (a.done && *a.done) return;
+    using TL = FTile<TX, RY>;
+    constexpr bool HK = HasK<KT>::value;
+    constexpr bool ADD = OUT == OUT_ADD64;
+    __shared__ T sx[3][TL::PN];            // input planes (P e), three in rotation
+    __shared__ T sk[3][HK ? TL::PN : 1];   // coefficient planes
+    __shared__ T sy[2][TL::QN];            // first-sweep output planes
+    __shared__ T sc[TL::CN];               // coarse footprint of the plane being committed
+
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile_x = lb % a.t.tiles_x;
+    const int rest = lb / a.t.tiles_x;
+    const int tile_y = rest % a.t.tiles_y;
+    const int cz = rest / a.t.tiles_y;
+    const int i0 = tile_x * TX, j0 = tile_y * TL::TY;
+    const int z0 = cz * a.t.zc;
+    const int z1 = min(z0 + a.t.zc, nz);
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int gi = i0 + lx, gj = j0 + RY * ly;
+    bool valid[RY];
+    size_t gb[RY];  // in-plane offsets of the thread's output rows, clamped into the grid
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        valid[r] = gi < nx && gj + r < ny;
+        gb[r] = (size_t)min(gi, nx - 1) + (size_t)nx * (size_t)min(gj + r, ny - 1);
+    }
+    const size_t plane = (size_t)nx * ny;
+    const size_t cplane = (size_t)a.cnx * a.cny;
+
+    const T h = (T)a.h, om = (T)a.omega;
+    const T cw = -h / (T)12, cv = h / (T)24;
+    const T om_w0 = om / ((T)(8.0 / 3.0) * h);
+    const T icv = (T)1 / cv;
+
+    FGeo<TX, RY> G;
+    make_fgeo<TX, RY>(G, a, i0, j0);
+    FPre<T, KT, TX, RY, ADD> pA, pB;
+    Run<T> r1[TL::NS1], r2[RY];
+
+    const T *bp = (const T *)a.b;
+    const T *ep = (const T *)a.ec;
+    const KT *kp = (const KT *)a.k;
+
+    auto fetch = [&](FPre<T, KT, TX, RY, ADD> &p, int zi) {
+        int sk_ = 1;
+        const size_t pz = plane * (size_t)fold(zi, nz, a.g.bc[4], a.g.bc[5], sk_);
+        if constexpr (HK) {
+#pragma unroll
+            for (int q = 0; q < TL::NPRE; ++q) p.k[q] = kp[pz + (size_t)G.off[q]];
+        }
+        const int K = zi >> 1;
+        int s1 = 1, s2 = 1;
+        const size_t p1 = cplane * (size_t)fold(K, a.cnz, a.g.bc[4], a.g.bc[5], s1);
+        const size_t p2 = cplane * (size_t)fold(K + ((zi & 1) ? 1 : -1), a.cnz, a.g.bc[4], a.g.bc[5], s2);
+#pragma unroll
+        for (int q = 0; q < TL::NPREC; ++q) {
+            p.c1[q] = ep[p1 + (size_t)G.coff[q]];
+            p.c2[q] = ep[p2 + (size_t)G.coff[q]];
+        }
+        if (zi - 1 >= z0 - 1 && zi - 1 <= z1) {
+            int sb = 1;
+            const size_t pb = plane * (size_t)fold(zi - 1, nz, a.g.bc[4], a.g.bc[5], sb);
+#pragma unroll
+            for (int q = 0; q < TL::NS1; ++q) p.b1[q] = bp[pb + (size_t)G.boff[q]];
+        }
+        if (zi - 2 >= z0 && zi - 2 < z1) {
+            const size_t pl = plane * (size_t)(zi - 2);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                p.b2[r] = bp[pl + gb[r]];
+                if constexpr (ADD) p.xo[r] = a.x64[pl + gb[r]];
+            }
+        }
+    };
+
+    // P e of plane zi into sx[buf] (coarse footprint staged in LDS first),
+    // the coefficient into sk[buf].
+    auto commit = [&](const FPre<T, KT, TX, RY, ADD> &p, int zi, int buf) {
+        const int K = zi >> 1;
+        int s1 = 1, s2 = 1;
+        (void)fold(K, a.cnz, a.g.bc[4], a.g.bc[5], s1);
+        (void)fold(K + ((zi & 1) ? 1 : -1), a.cnz, a.g.bc[4], a.g.bc[5], s2);
+        const T w1 = (T)(0.75 * s1), w2 = (T)(0.25 * s2);
+#pragma unroll
+        for (int q = 0; q < TL::NPREC; ++q)
+            if (q * FT + (int)threadIdx.x < TL::CN) {
+                const T v = w1 * p.c1[q] + w2 * p.c2[q];
+                sc[q * FT + threadIdx.x] = G.cneg[q] ? -v : v;
+            }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TL::NPRE; ++q) {
+            const int idx = q * FT + threadIdx.x;
+            if (idx < TL::PN) {
+                const int t0 = G.tap[q] & 0xffff;
+                const int tdx = ((G.tap[q] >> 16) & 1) ? 1 : -1;
+                const int tdy = ((G.tap[q] >> 17) & 1) ? TL::CX : -TL::CX;
+                const T w3 = (T)0.75, wq = (T)0.25;
+                const int t1 = t0 + tdy;
+                sx[buf][idx] = w3 * (w3 * sc[t0] + wq * sc[t0 + tdx]) + wq * (w3 * sc[t1] + wq * sc[t1 + tdx]);
+                if constexpr (HK) sk[buf][idx] = kconv<T, KT>(p.k[q]);
+            }
+        }
+        __syncthreads();
+    };
+
+    int buf = 0;  // sx/sk buffer of the plane being committed (rotates through 3)
+    auto step = [&](FPre<T, KT, TX, RY, ADD> &p, int zi) {
+        commit(p, zi, buf);
+        T b1[TL::NS1], b2[RY];
+        double xo[ADD ? RY : 1];
+        bool bzneg = false;
+        {
+            int sb = 1;
+            (void)fold(zi - 1, nz, a.g.bc[4], a.g.bc[5], sb);
+            bzneg = sb < 0;
+        }
+#pragma unroll
+        for (int q = 0; q < TL::NS1; ++q) b1[q] = (G.bneg[q] != bzneg) ? -p.b1[q] : p.b1[q];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            b2[r] = p.b2[r];
+            if constexpr (ADD) xo[r] = p.xo[r];
+        }
+        if (zi + 2 <= z1 + 1) fetch(p, zi + 2);
+
+        // first sweep: absorb plane zi at every ring slot, completing y1(zi - 1)
+        const int yb = (zi - 1) & 1;
+#pragma unroll
+        for (int q = 0; q < TL::NS1; ++q) {
+            const int idx = q * FT + threadIdx.x;
+            if (idx < TL::QN) {
+                const int qy = idx / TL::QX, qx = idx - qy * TL::QX;
+                const int c = (qy + 1) * TL::PX + (qx + 1);
+                PS<T> ps;
+                sums_at<T, HK, TL::PX, TL::PX>(sx[buf], c, sk[buf], c, ps);
+                if (zi >= z0) sy[yb][idx] = jacobi<T, HK>(r1[q], ps, b1[q], cw, om_w0, om, icv);
+                absorb<T, HK>(r1[q], ps, zi == z0 - 2);
+            }
+        }
+        if (zi >= z0) {
+            __syncthreads();
+            // second sweep: absorb y1(zi - 1) with the coefficient plane zi - 1,
+            // completing the output plane zi - 2
+            const int kb = (buf + 2) % 3;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const int sxq = lx + 1, syq = RY * ly + r + 1;
+                PS<T> ps;
+                sums_at<T, HK, TL::QX, TL::PX>(sy[yb], syq * TL::QX + sxq, sk[kb], (syq + 1) * TL::PX + (sxq + 1), ps);
+                if (zi >= z0 + 2) {
+                    const T y = jacobi<T, HK>(r2[r], ps, b2[r], cw, om_w0, om, icv);
+                    if (valid[r]) {
+                        const size_t g = gb[r] + plane * (size_t)(zi - 2);
+                        if constexpr (ADD)
+                            a.x64[g] = xo[r] + (double)y;
+                        else
+                            ((T *)a.yout)[g] = y;
+                    }
+                }
+                absorb<T, HK>(r2[r], ps, zi == z0);
+            }
+        }
+        buf = (buf + 1) % 3;
+    };
+
+    fetch(pA, z0 - 2);
+    fetch(pB, z0 - 1);
+    for (int zi = z0 - 2; zi <= z1 + 1; zi += 2) {
+        step(pA, zi);
+        if (zi + 1 <= z1 + 1) step(pB, zi + 1);
+    }
+}
+
+template <typename T, typename KT, int OUT>
+hipError_t go2(const StencilArgs &a, hipStream_t s)
+{
+    const dim3 grid(a.t.blocks()), block(FT);
+    switch (a.t.tx * 10 + a.t.ry) {
+    case 642: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, 64, 2>), grid, block, 0, s, a); break;
+    case 641: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, 64, 1>), grid, block, 0, s, a); break;
+    case 322: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, 32, 2>), grid, block, 0, s, a); break;
+    case 321: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, 32, 1>), grid, block, 0, s, a); break;
+    case 162: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, 16, 2>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool sweep2_supports(int tx, int ry) { return (tx == 64 && ry <= 2) || (tx == 32 && ry <= 2) || (tx == 16 && ry == 2); }
+
+hipError_t launch_sweep2(int T_is_f64, int kt, int out_mode, const StencilArgs &a, hipStream_t s)
+{
+    if (a.t.blocks() <= 0 || (a.t.zc & 1)) return hipErrorInvalidValue;
+    if (a.bmean || !a.ec || !a.b) return hipErrorInvalidValue;
+    if (T_is_f64) {
+        if (out_mode == OUT_STORE) {
+            if (kt == KT_NONE) return go2<double, NoK, OUT_STORE>(a, s);
+            if (kt == KT_F64) return go2<double, double, OUT_STORE>(a, s);
+        }
+        if (out_mode == OUT_ADD64) {
+            if (kt == KT_NONE) return go2<double, NoK, OUT_ADD64>(a, s);
+            if (kt == KT_F64) return go2<double, double, OUT_ADD64>(a, s);
+        }
+        return hipErrorInvalidValue;
+    }
+    if (out_mode == OUT_STORE) {
+        if (kt == KT_NONE) return go2<float, NoK, OUT_STORE>(a, s);
+        if (kt == KT_F32) return go2<float, float, OUT_STORE>(a, s);
+        if (kt == KT_F16) return go2<float, __half, OUT_STORE>(a, s);
+    }
+    if (out_mode == OUT_ADD64) {
+        if (kt == KT_NONE) return go2<float, NoK, OUT_ADD64>(a, s);
+        if (kt == KT_F32) return go2<float, float, OUT_ADD64>(a, s);
+        if (kt == KT_F16) return go2<float, __half, OUT_ADD64>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace nn4mg

@@ -149,6 +149,12 @@ hipError_t launch_fcg_direction(SolveState *st, const double *z, double *p, size
 hipError_t launch_cast_f32(const double *src, float *dst, size_t n, const int *done, hipStream_t s);
 hipError_t launch_zero(double *x, size_t n, const int *done, hipStream_t s);
 
+// ---- both post-smoothing sweeps in one pass (mg_fused.hip) ----
+// Input P e (a.ec, IN_PROLONG semantics), right-hand side a.b (no bmean),
+// coefficient a.k; out_mode OUT_STORE (a.yout) or OUT_ADD64 (a.x64 += e).
+bool sweep2_supports(int tx, int ry);
+hipError_t launch_sweep2(int T_is_f64, int kt, int out_mode, const StencilArgs &a, hipStream_t s);
+
 // ---- coarse end of the cycle in one workgroup (mg_tail.hip) ----
 constexpr int kTailMaxLevels = 8;
 struct TailArgs {

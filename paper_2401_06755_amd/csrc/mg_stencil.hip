@@ -31,6 +31,7 @@
 // Output modes: a weighted-Jacobi sweep y + omega (b - A y) / D stored, or
 // added into an FP64 field; or the residual r = b - A y with the 2x
 // restriction (sum of the 8 children) and a per-block sum of r^2.
+#include "mg_device.h"
 #include "mg_internal.h"
 
 #include <type_traits>
@@ -40,88 +41,6 @@ namespace nn4mg {
 namespace {
 
 constexpr int NT = 256;
-
-struct NoK {};
-
-template <typename KT>
-struct HasK {
-    static constexpr bool value = true;
-};
-template <>
-struct HasK<NoK> {
-    static constexpr bool value = false;
-};
-
-// Storage type of a prefetched coefficient value (the value as loaded).
-template <typename T, typename KT>
-struct KStore {
-    using type = KT;
-};
-template <typename T>
-struct KStore<T, NoK> {
-    using type = T;
-};
-
-template <typename T, typename KT>
-__device__ __forceinline__ T kconv(typename KStore<T, KT>::type v)
-{
-    if constexpr (std::is_same<KT, __half>::value)
-        return (T)__half2float(v);
-    else if constexpr (std::is_same<KT, NoK>::value)
-        return (T)0;
-    else
-        return (T)v;
-}
-
-// 1/d: hardware reciprocal refined by Newton steps (two in FP64).
-__device__ __forceinline__ double recip(double d)
-{
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(fma(-d, r, 1.0), r, r);
-    r = fma(fma(-d, r, 1.0), r, r);
-    return r;
-}
-__device__ __forceinline__ float recip(float d)
-{
-    float r = __builtin_amdgcn_rcpf(d);
-    return fmaf(fmaf(-d, r, 1.0f), r, r);
-}
-
-// Halo index -> interior index, flipping the sign across a Dirichlet-zero
-// wall.  Indices beyond the one-cell halo (ragged tiles) are clamped into
-// range; their values are never used by a valid output.
-__device__ __forceinline__ int fold(int i, int n, int lo, int hi, int &sgn)
-{
-    if (i < 0) {
-        if (lo == BC_P) {
-            i += n;
-            return i < 0 ? 0 : i;
-        }
-        if (lo == BC_D) sgn = -sgn;
-        i = -1 - i;
-        return i < n ? i : n - 1;
-    }
-    if (i >= n) {
-        if (hi == BC_P) {
-            i -= n;
-            return i < n ? i : n - 1;
-        }
-        if (hi == BC_D) sgn = -sgn;
-        i = 2 * n - 1 - i;
-        return i >= 0 ? i : 0;
-    }
-    return i;
-}
-
-// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8).
-// Give each XCD a contiguous range of tiles so neighbouring tiles, which share
-// halo lines, share that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    const int q = nb >> 3, r = nb & 7;
-    const int x = b & 7, k = b >> 3;
-    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
 
 template <int TX, int RY>
 struct Tile {
@@ -420,7 +339,7 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
         }
     };
 
-    double nacc = 0.0, zacc[RP];
+    double nacc = 0.0, zacc[RP > 0 ? RP : 1];
 #pragma unroll
     for (int q = 0; q < RP; ++q) zacc[q] = 0.0;
 
@@ -531,6 +450,14 @@ hipError_t go(const StencilArgs &a, hipStream_t s)
 {
     const dim3 grid(a.t.blocks()), block(NT);
     const int key = a.t.tx * 10 + a.t.ry;
+    if constexpr (OUT != OUT_RESID) {  // one row per thread: sweeps only (the restriction pairs rows)
+        switch (key) {
+        case 641: hipLaunchKernelGGL((stencil_kernel<T, KT, IN, OUT, OT, 64, 1>), grid, block, 0, s, a); return hipGetLastError();
+        case 321: hipLaunchKernelGGL((stencil_kernel<T, KT, IN, OUT, OT, 32, 1>), grid, block, 0, s, a); return hipGetLastError();
+        case 161: hipLaunchKernelGGL((stencil_kernel<T, KT, IN, OUT, OT, 16, 1>), grid, block, 0, s, a); return hipGetLastError();
+        default: break;
+        }
+    }
     switch (key) {
     case 642: hipLaunchKernelGGL((stencil_kernel<T, KT, IN, OUT, OT, 64, 2>), grid, block, 0, s, a); break;
     case 644: hipLaunchKernelGGL((stencil_kernel<T, KT, IN, OUT, OT, 64, 4>), grid, block, 0, s, a); break;
@@ -558,8 +485,8 @@ hipError_t go_in(int in_mode, const StencilArgs &a, hipStream_t s)
 TileShape make_tiles(int nx, int ny, int nz, int zc, int tx, int ry)
 {
     if (tx != 64 && tx != 32 && tx != 16) tx = 64;
-    if (ry != 2 && ry != 4) ry = 2;
-    if (tx == 16) ry = 2;
+    if (ry != 1 && ry != 2 && ry != 4) ry = 2;
+    if (tx == 16 && ry == 4) ry = 2;
     if (zc < 2) zc = 2;
     zc &= ~1;
     TileShape t;
