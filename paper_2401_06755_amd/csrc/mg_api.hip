@@ -990,8 +990,20 @@ int enqueue_fcg_iteration(nn4mg_hier *H, double *x)
     const int *done = &H->st->done;
     int rc;
     H->cur_tag += 1;
-    if ((rc = enqueue_resid(H, v.p, v.zero, nullptr, v.t, nullptr, false, false, done))) return rc;
-    HIP_TRY(launch_fcg_alpha(v.p, v.t, n, H->fcg_part, H->st, s));
+    {   // t = -A p with per-block partials of p.t, then alpha
+        StencilArgs a = base_args(H, 0, NN4MG_KCLASS_FINE_RESID);
+        a.yin = v.p;
+        a.b = v.zero;
+        a.k = H->lv[0].k;
+        a.r = v.t;
+        a.partials = H->partials;
+        a.dot_x = 1;
+        a.done = done;
+        const long pr = prof_begin(H, NN4MG_KCLASS_FINE_RESID);
+        HIP_TRY(launch_stencil(1, H->kt64, IN_PLAIN, OUT_RESID, 0, a, s));
+        prof_end(H, pr);
+        HIP_TRY(launch_fcg_alpha_partials(H->partials, resid_blocks(H), H->st, s));
+    }
     HIP_TRY(launch_fcg_update(H->st, x, v.p, v.r, v.t, H->mixed ? H->lv[0].b32 : nullptr, n, H->partials, s));
     HIP_TRY(launch_finish_norm(H->st, H->partials, fcg_update_blocks(n), s));
     if ((rc = enqueue_precondition(H, v.r, v.z, done))) return rc;

@@ -88,14 +88,14 @@ __global__ __launch_bounds__(256) void pq_kernel(const double *p, const double *
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// mode 0: rho = sum z r (start);  mode 1: alpha = rho / (p.q);
-// mode 2: beta = -(z.q) / (p.q), rho = z.r.
+// mode 0: rho = sum z r (start);  mode 1: alpha = rho / (p.q) from partials of p.q;
+// mode 3: the same from partials of p.t = -p.q;  mode 2: beta = -(z.q) / (p.q), rho = z.r.
 __global__ __launch_bounds__(1024) void scalar_kernel(SolveState *st, const double *partials, int nblk, int mode)
 {
     __shared__ double red[16];
     if (st->done) return;
-    if (mode == 1) {
-        const double pq = reduce_partials(partials, nblk, red);
+    if (mode == 1 || mode == 3) {
+        const double pq = (mode == 3 ? -1.0 : 1.0) * reduce_partials(partials, nblk, red);
         if (threadIdx.x == 0) {
             st->fcg_pq_prev = pq;
             if (!(pq > 0.0) || !isfinite(pq)) {
@@ -187,6 +187,12 @@ hipError_t launch_fcg_alpha(const double *p, const double *t, size_t n, double *
     const int nb = dot_blocks(n);
     hipLaunchKernelGGL(pq_kernel, dim3(nb), dim3(256), 0, s, p, t, n, partials, &st->done);
     hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(1024), 0, s, st, (const double *)partials, nb, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_fcg_alpha_partials(const double *partials, int nblk, SolveState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(1024), 0, s, st, partials, nblk, 3);
     return hipGetLastError();
 }
 

@@ -62,7 +62,8 @@ struct StencilArgs {
     const double *bmean; // subtracted from b if not NULL (projected right-hand side)
     void *r;             // OUT_RESID: full residual (type OT), may be NULL
     void *rc;            // OUT_RESID: restricted residual (type OT), may be NULL
-    double *partials;    // OUT_RESID: one sum of r^2 per block, may be NULL
+    double *partials;    // OUT_RESID: one sum of r^2 per block (x.r with dot_x), may be NULL
+    int dot_x;           // OUT_RESID: partials of x.r instead of r.r
     const int *done;     // skip the launch when *done != 0 (may be NULL)
 };
 
@@ -143,6 +144,8 @@ hipError_t launch_fcg_dots(const double *z, const double *r, const double *t, si
                            SolveState *st, int mode, hipStream_t s);
 hipError_t launch_fcg_alpha(const double *p, const double *t, size_t n, double *partials, SolveState *st,
                             hipStream_t s);
+// alpha from nblk per-block partials of p.t (t = -A p) written by the residual kernel
+hipError_t launch_fcg_alpha_partials(const double *partials, int nblk, SolveState *st, hipStream_t s);
 hipError_t launch_fcg_update(SolveState *st, double *x, const double *p, double *r, const double *t, float *r32,
                              size_t n, double *partials, hipStream_t s);
 hipError_t launch_fcg_direction(SolveState *st, const double *z, double *p, size_t n, hipStream_t s);

@@ -387,7 +387,7 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
                 double rv = 0.0;
                 if (valid[r]) rv = ((double)bcur[r] - bm) - (double)Ay;
                 if (a.r && valid[r]) ((OT *)a.r)[g] = (OT)rv;
-                nacc += rv * rv;
+                nacc += a.dot_x ? (double)y0 * rv : rv * rv;
                 rrow[r] = rv;
             } else if (valid[r]) {
                 if constexpr (OUT == OUT_STORE)
