@@ -239,7 +239,7 @@ struct nn4mg_hier {
     int max_partials = 0;
     double *scal = nullptr;  // device scalars: [0] sum, [1] mean of x, [2..7] spare
     int *flag = nullptr;
-    double *fcg = nullptr;   // FCG vectors r, z, p, t = -A p and a zero vector, level 0, FP64
+    double *fcg = nullptr;   // FCG vectors r, z, p, t = -A p at level 0, FP64
     double *fcg_part = nullptr;  // FCG dot-product partials
     size_t bytes = 0;
     std::vector<void *> allocs;
@@ -317,7 +317,7 @@ size_t bytes_for(const nn4mg_config *c)
     }
     const size_t nc = (size_t)(c->nx >> (L - 1)) * (c->ny >> (L - 1)) * (c->nz >> (L - 1));
     b += 8 * nc * nc + sizeof(SolveState) + 8 * maxblk + 64 + 4;
-    if (c->outer == NN4MG_OUTER_FCG) b += 5 * 8 * (size_t)c->nx * c->ny * c->nz + 8 * (size_t)fcg_partials_needed();
+    if (c->outer == NN4MG_OUTER_FCG) b += 4 * 8 * (size_t)c->nx * c->ny * c->nz + 8 * (size_t)fcg_partials_needed();
     return b;
 }
 
@@ -826,13 +826,8 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
     TRY(dalloc(H, &H->scal, 8));
     TRY(dalloc(H, &H->flag, 1));
     if (cfg->outer == NN4MG_OUTER_FCG) {
-        TRY(dalloc(H, &H->fcg, 5 * H->lv[0].n));
+        TRY(dalloc(H, &H->fcg, 4 * H->lv[0].n));
         TRY(dalloc(H, &H->fcg_part, (size_t)fcg_partials_needed()));
-        if (launch_fill(H->fcg + 4 * H->lv[0].n, H->lv[0].n, 0.0, H->stream) != hipSuccess) {
-            (void)hipGetLastError();
-            nn4mg_destroy(H);
-            return fail(NN4MG_EDEVICE, "zero fill failed");
-        }
     }
     if (hipHostMalloc((void **)&H->st_host, sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -937,14 +932,14 @@ int enqueue_stationary_iteration(nn4mg_hier *H, const double *b, double *x)
 }
 
 // ---- flexible CG outer iteration: one sawtooth cycle from zero is the
-// preconditioner M.  Vectors (level 0, FP64): r, z, p, t = -A p, zero.
+// preconditioner M.  Vectors (level 0, FP64): r, z, p, t = -A p.
 struct FcgVec {
-    double *r, *z, *p, *t, *zero;
+    double *r, *z, *p, *t;
 };
 FcgVec fcg_vec(nn4mg_hier *H)
 {
     const size_t n = H->lv[0].n;
-    return FcgVec{H->fcg, H->fcg + n, H->fcg + 2 * n, H->fcg + 3 * n, H->fcg + 4 * n};
+    return FcgVec{H->fcg, H->fcg + n, H->fcg + 2 * n, H->fcg + 3 * n};
 }
 
 // z = M r.  FP64: the cycle's right-hand side is r itself; mixed: the FP32
@@ -993,7 +988,7 @@ int enqueue_fcg_iteration(nn4mg_hier *H, double *x)
     {   // t = -A p with per-block partials of p.t, then alpha
         StencilArgs a = base_args(H, 0, NN4MG_KCLASS_FINE_RESID);
         a.yin = v.p;
-        a.b = v.zero;
+        a.b = nullptr;  // t = 0 - A p
         a.k = H->lv[0].k;
         a.r = v.t;
         a.partials = H->partials;
@@ -1276,7 +1271,8 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
     constexpr int NT_SHAPES = 8;
     const int txs[NT_SHAPES] = {64, 64, 32, 32, 16, 64, 32, 16};
     const int rys[NT_SHAPES] = {2, 4, 2, 4, 2, 1, 1, 1};
-    const int zcs[5] = {2, 4, 8, 16, 32};
+    constexpr int NZC = 6;
+    const int zcs[NZC] = {2, 4, 8, 16, 32, 64};
     const int reps = 3;
     constexpr int NC = NN4MG_KCLASS_COUNT;
     std::vector<double> best((size_t)L * NC, 1e300);
@@ -1293,7 +1289,7 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
     };
     int rc;
     for (int ti = 0; ti < NT_SHAPES; ++ti)
-        for (int zi = 0; zi < 5; ++zi) {
+        for (int zi = 0; zi < NZC; ++zi) {
             std::vector<bool> used(L, false);
             for (int l = 0; l < L; ++l) {
                 Level &V = H->lv[l];

@@ -55,7 +55,7 @@ struct StencilArgs {
     const void *yin;     // IN_PLAIN input / IN_PROLONG_ADD addend (type T)
     const void *ec;      // coarse correction (type T), dims cnx x cny x cnz
     int cnx, cny, cnz;
-    const void *b;       // right-hand side (type T)
+    const void *b;       // right-hand side (type T); NULL for zero (residual mode)
     const void *k;       // coefficient (KType), NULL for constant
     void *yout;          // OUT_STORE destination (type T)
     double *x64;         // OUT_ADD64 destination

@@ -137,11 +137,11 @@ __device__ __forceinline__ void fetch(Prefetch<T, KT, TX, RY, IN != IN_PLAIN, AD
     using TL = Tile<TX, RY>;
     const size_t plane = (size_t)a.g.nx * a.g.ny;
     if (z - 1 >= z0) {
-        const T *b = (const T *)a.b;
+        const T *b = (const T *)a.b;  // NULL: a zero right-hand side
         const size_t pl = plane * (size_t)(z - 1);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            p.bo[r] = b[gb[r] + pl];
+            p.bo[r] = b ? b[gb[r] + pl] : (T)0;
             if constexpr (ADD) p.xo[r] = a.x64[gb[r] + pl];
         }
     }

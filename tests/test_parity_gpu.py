@@ -91,6 +91,7 @@ VC_CASES = [
     ((48, 48, 48), (N,) * 6, True),
     ((8, 8, 8), (D,) * 6, False),
     ((6, 10, 4), (N, D, N, N, D, N), True),
+    ((64, 32, 48), (P, P, D, N, P, P), True),
 ]
 
 
@@ -118,6 +119,7 @@ def test_one_vcycle_matches_oracle(mg, shape, bc, var):
     ((80, 24, 40), (N, N, N, N, N, D), True, 20),
     ((48, 48, 48), (N,) * 6, True, 12),
     ((40, 40, 80), (N, N, N, N, N, D), True, 10),
+    ((96, 32, 64), (P, P, N, N, D, D), True, 8),
 ])
 def test_fixed_cycle_solve_matches_oracle(mg, shape, bc, var, cycles):
     nx, ny, nz = shape
