@@ -257,3 +257,31 @@ def test_graph_replays_match_direct_launches(mg):
         assert np.array_equal(x2.cpu().numpy(), ref), rep
         assert info2.history() == info1.history()
         del junk
+
+
+@pytest.mark.parametrize("nu", [1, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_other_sweep_counts_match_oracle(mg, nu, prec):
+    """nu_post != 2 takes the one-sweep-per-pass kernels (the two-sweep pass
+    serves nu_post = 2): fixed-cycle solve vs the oracle's cycle with the same
+    sweep count (FP64: 1e-10; FP32 smoothing: the oracle's FP64 residual of the
+    result is driven down at the same rate, checked at 1e-6 of the first)."""
+    shape, bc = (48, 32, 40), (N, N, D, N, N, D)
+    nx, ny, nz = shape
+    h = 1.0 / nx
+    frac = inputs.sphere_fraction(shape, h, (0.5, 0.4, 0.5 * nz / nx), 0.25)
+    k = inputs.two_phase_k(frac, 1000.0, 1.0)
+    b = np.random.default_rng(41).standard_normal((nz, ny, nx))
+    cfg = mg.config_default(*shape, h, bc=bc, coef_mode=1, precision=prec, nu_post=nu)
+    H = mg.Hierarchy(cfg, dev(k))
+    xd = dev(np.zeros_like(b))
+    info = H.solve(dev(b), xd, max_cycles=8, fixed_cycles=True)
+    assert info.status == 0 and info.cycles == 8
+    OH = oracle.Hierarchy(shape, h, bc, k=k, nu_post=nu)
+    xo, hist_o, _ = OH.solve(b, max_cycles=8, fixed=True)
+    got = host(xd, b.shape)
+    if prec == 0:
+        assert np.max(np.abs(got - xo)) <= 1e-10 * np.abs(xo).max()
+        np.testing.assert_allclose(info.history(), hist_o, rtol=1e-10, atol=1e-13)
+    else:
+        assert np.max(np.abs(got - xo)) <= 1e-5 * np.abs(xo).max()
