@@ -134,6 +134,25 @@ __device__ inline double sep(const Nb &n, const V3 &X, const V3 &Y, const V3 &Z)
     return out;
 }
 
+// f(k C; X (x) Y (x) Z) with the products formed on the fly (no third neighbourhood).
+__device__ inline double sepp(const Nb &k, const Nb &n, const V3 &X, const V3 &Y, const V3 &Z)
+{
+    double out = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double pl = 0.0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double *r = &n.v[c * 9 + b * 3];
+            const double *kr = &k.v[c * 9 + b * 3];
+            const double row = X.m * (kr[0] * r[0]) + X.z * (kr[1] * r[1]) + X.p * (kr[2] * r[2]);
+            pl += (b == 0 ? Y.m : (b == 1 ? Y.z : Y.p)) * row;
+        }
+        out += (c == 0 ? Z.m : (c == 1 ? Z.z : Z.p)) * pl;
+    }
+    return out;
+}
+
 struct Filt {
     V3 M, G, K, m;  // m = M / h
     double ml;      // lumped mass h^3
@@ -165,11 +184,17 @@ struct Filt {
 // padded values as the halo of k C.  which: 0..2 = w_dd^PG, 3 = w_lap.
 __device__ inline double fdiff(const Filt &F, const Nb &Cn, const Nb &kn, int which)
 {
-    Nb kc;
-#pragma unroll
-    for (int q = 0; q < 27; ++q) kc.v[q] = kn.v[q] * Cn.v[q];
-    if (which == 3) return 0.5 * (F.lap(kc) + kn.mid() * F.lap(Cn) - Cn.mid() * F.lap(kn));
-    return 0.5 * (F.pg(kc, which) + kn.mid() * F.pg(Cn, which) - Cn.mid() * F.pg(kn, which));
+    double fk;  // f(k C; w)
+    if (which == 3)
+        fk = sepp(kn, Cn, F.K, F.M, F.M) + sepp(kn, Cn, F.M, F.K, F.M) + sepp(kn, Cn, F.M, F.M, F.K);
+    else if (which == 0)
+        fk = sepp(kn, Cn, F.K, F.M, F.M);
+    else if (which == 1)
+        fk = sepp(kn, Cn, F.M, F.K, F.M);
+    else
+        fk = sepp(kn, Cn, F.M, F.M, F.K);
+    if (which == 3) return 0.5 * (fk + kn.mid() * F.lap(Cn) - Cn.mid() * F.lap(kn));
+    return 0.5 * (fk + kn.mid() * F.pg(Cn, which) - Cn.mid() * F.pg(kn, which));
 }
 
 struct Phys {
@@ -317,6 +342,24 @@ __global__ __launch_bounds__(256) void momentum_kernel(Grid g, Phys P, C3 qn, C3
     cell_of(g, [&](size_t id, int i, int j, int k) {
         const Filt F(g.h);
         const double r0 = rho[id];
+        // the pressure gradients and the buoyancy source, each neighbourhood loaded once
+        double ghs[3], gnh[3], buoy;
+        {
+            Nb p;
+            load_phs(p, p_hs, rho, P.g * g.h, g, i, j, k);
+            for (int c = 0; c < 3; ++c) ghs[c] = F.d(p, c);
+        }
+        {
+            Nb p;
+            load(p, p_nh, kOddTop, g, i, j, k);
+            for (int c = 0; c < 3; ++c) gnh[c] = F.d(p, c);
+        }
+        {
+            Nb r;
+            load(r, rho, kEven, g, i, j, k);
+            for (int e = 0; e < 27; ++e) r.v[e] *= -P.g;
+            buoy = F.mass(r);
+        }
         for (int c = 0; c < 3; ++c) {
             double s;
             {
@@ -325,27 +368,14 @@ __global__ __launch_bounds__(256) void momentum_kernel(Grid g, Phys P, C3 qn, C3
                 load(kv, kq.p[c], kEven, g, i, j, k);
                 s = fdiff(F, qv, kv, 3);
             }
-            {
-                Nb p;
-                load_phs(p, p_hs, rho, P.g * g.h, g, i, j, k);
-                s += F.d(p, c);
-            }
-            {
-                Nb p;
-                load(p, p_nh, kOddTop, g, i, j, k);
-                s += F.d(p, c);
-            }
+            s += ghs[c];
+            s += gnh[c];
             {
                 Nb t;
                 load(t, st.p[c], rule_grad(c), g, i, j, k);
                 s -= F.mass(t);
             }
-            if (c == 2) {
-                Nb r;
-                load(r, rho, kEven, g, i, j, k);
-                for (int e = 0; e < 27; ++e) r.v[e] *= -P.g;
-                s -= F.mass(r);
-            }
+            if (c == 2) s -= buoy;
             s += r0 * F.ml * adv.p[c][id];
             const double qnc = qn.p[c][id];
             const double t = (-s / F.ml + r0 * qnc / P.dt) / (r0 / P.dt);
