@@ -64,8 +64,10 @@ enum { NN4MG_COEF_CONST = 0, NN4MG_COEF_NODAL = 1 };
 enum { NN4MG_PREC_FP64 = 0, NN4MG_PREC_FP32_SMOOTH = 1, NN4MG_PREC_FP16_COEF = 2 };
 
 /* Outer iteration: STATIONARY repeats the cycle (x <- x + V(b - A x));
- * FCG runs flexible conjugate gradients in FP64 with one cycle as the
- * preconditioner. */
+ * FCG runs flexible conjugate gradients (FCG(1)) in FP64 with one cycle from
+ * zero as the preconditioner; it needs at least two levels (EINVAL otherwise)
+ * and four extra FP64 fields of the finest size.  With FCG, info->cycles
+ * counts CG iterations (one preconditioning cycle each, plus one at the start). */
 enum { NN4MG_OUTER_STATIONARY = 0, NN4MG_OUTER_FCG = 1 };
 
 typedef struct {
