@@ -15,10 +15,13 @@ Prints one JSON line: value = finest cells x V-cycles / second / 1e9
 (Gcell-updates/s), the roofline figure of the dominant kernel from HIP events
 recorded on the solve stream, and beside it: the FP32-smoothing / FP64-refinement
 solve of the same workload, the flexible-CG outer iteration (time to the same
-tolerance), one two-phase time step on a 128^3 collapsing column split into
-pressure solves and explicit stencils, the served stream of 512 solves of uneven
-sizes (solves/s, p50/p99 latency), and the FP64 oracle timed on the host over a
-bounded sample of V-cycles of the same workload.
+tolerance), the 64^3 constant-coefficient Dirichlet Poisson solve, the
+256 x 256 x 512 rising-bubble solve with the FP16-stored coefficient (and its
+difference from the FP64 solve of the same system), one two-phase time step on
+a 128^3 collapsing column split into pressure solves and explicit stencils, the
+served stream of 512 solves of uneven sizes (solves/s, p50/p99 latency), and
+the FP64 oracle timed on the host over a bounded sample of V-cycles of the same
+workload.
 """
 from __future__ import annotations
 
@@ -45,15 +48,23 @@ BYTES_PER_CELL = {
     "mixed": {"resid": 8 + 8 + 8 + 4 + 0.5,   # x, b, k (FP64); r32, restricted r32
               "sweeps": 0.5 + 4 + 4 + 8 + 8,  # e_1 (FP32, 1/8), r32, k32; x64 read + write
               "sweep": 4 + 4 + 4 + 8 + 8},    # (nu_post != 2 only)
+    "fp16": {"resid": 8 + 8 + 8 + 4 + 0.5,    # as mixed, smoothing with the FP16 copy of k
+             "sweeps": 0.5 + 4 + 2 + 8 + 8,
+             "sweep": 4 + 4 + 2 + 8 + 8},
+    "fp64c": {"resid": 8 + 8 + 8 + 1,         # constant coefficient: no k
+              "sweeps": 1 + 8 + 8 + 8,
+              "sweep": 8 + 8 + 8},
 }
+# bytes per cell of the coefficient on the coarse levels, per mode
+COARSE_K_BYTES = {"fp64": 8, "mixed": 4, "fp16": 2, "fp64c": 0}
 KCLASS = {"resid": 0, "sweeps": 1, "sweep": 2}
 
 # HBM bytes per finest-level launch (256^3, FP64, nodal k) from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for
 # a plain 256 MiB device copy (fetch x2.0, write x1.0); the commands and raw
-# counts are in profiles/dense_sphere_256_fp64_fine_kernels.md.  Valid for the
-# stencil kernel as profiled; set to None when the kernel changes.
-MEASURED_TRAFFIC_FP64_256 = {"resid": 570.8e6, "sweeps": 578.9e6}
+# counts are in profiles/dense_sphere_256_fp64_fine_kernels.md.  Valid for each
+# kernel as profiled; a kernel changed since then has no entry (traffic null).
+MEASURED_TRAFFIC_FP64_256 = {"resid": 570.8e6}
 
 
 def log(msg):
@@ -64,22 +75,26 @@ def cycle_model_bytes(levels, mode):
     """Algorithmic bytes of one V(0,2) cycle over all levels (finest kernels as
     above; coarse level l: restriction w + w/8 B, both sweeps in one pass
     reading e_{l+1} (w/8), b, k and writing e (3w); FP32 on coarse levels in
-    mixed mode)."""
-    w = 8 if mode == "fp64" else 4
+    mixed mode; no k with a constant coefficient)."""
+    w = 8 if mode in ("fp64", "fp64c") else 4
+    kb = COARSE_K_BYTES[mode]
     n0 = levels[0][0] * levels[0][1] * levels[0][2]
     tot = n0 * (BYTES_PER_CELL[mode]["resid"] + BYTES_PER_CELL[mode]["sweeps"])
     for l in range(1, len(levels) - 1):
         n = levels[l][0] * levels[l][1] * levels[l][2]
-        tot += n * ((w + w / 8) + (w / 8 + 3 * w))
+        tot += n * ((w + w / 8) + (w / 8 + 2 * w + kb))
     return tot
 
 
-def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol, autotune=True, outer=0, profile=True):
+def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol, autotune=True, outer=0, profile=True,
+               keep_x=False):
     nx, ny, nz = work["shape"]
     n = nx * ny * nz
-    cfg = nn4mg.config_default(nx, ny, nz, work["h"], bc=work["bc"], coef_mode=nn4mg.COEF_NODAL,
+    nodal = work["k"] is not None
+    cfg = nn4mg.config_default(nx, ny, nz, work["h"], bc=work["bc"],
+                               coef_mode=nn4mg.COEF_NODAL if nodal else nn4mg.COEF_CONST,
                                precision=precision, outer=outer)
-    kd = torch.from_numpy(work["k"].reshape(-1)).cuda()
+    kd = torch.from_numpy(work["k"].reshape(-1)).cuda() if nodal else None
     bd = torch.from_numpy(work["b"].reshape(-1)).cuda()
     xd = torch.zeros_like(bd)
     torch.cuda.synchronize()
@@ -87,10 +102,12 @@ def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol, autotune=True
     H = nn4mg.Hierarchy(cfg, kd)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
-    t0 = time.perf_counter()
-    H.update_coef(kd)
-    torch.cuda.synchronize()
-    update_ms = (time.perf_counter() - t0) * 1e3
+    update_ms = None
+    if nodal:
+        t0 = time.perf_counter()
+        H.update_coef(kd)
+        torch.cuda.synchronize()
+        update_ms = (time.perf_counter() - t0) * 1e3
     tiles, tune_ms = None, 0.0
     if autotune:
         t0 = time.perf_counter()
@@ -134,8 +151,12 @@ def run_solver(nn4mg, torch, work, precision, steps, warmup, rtol, autotune=True
             cnt, ms = H.profile_read(cls)
             kern[name] = (cnt, ms)
     levels = H.levels()
+    if keep_x:
+        xd.zero_()
+        H.solve(bd, xd, rtol=rtol, max_cycles=2000)
     H.close()
     return dict(n=n, dt=dt, dt_prof=dt_prof, cycles=cycles, info=infos[-1], kern=kern, levels=levels,
+                x=xd if keep_x else None,
                 setup_ms=setup_ms,
                 update_ms=update_ms, tiles=tiles, tune_ms=tune_ms,
                 all_converged=all(i.status == 0 for i in infos))
@@ -283,6 +304,53 @@ def step_bench(nn4mg, torch, n, steps):
                               "note": "Eq. speed coefficients: seconds per node (times polynomial order p; here p = 1)"}}
 
 
+def poisson64_bench(nn4mg, torch, inputs, steps, warmup, rtol):
+    """64^3 constant-coefficient Poisson on the unit cube, zero Dirichlet walls,
+    sine mode plus 1e-3 uniform noise, FP64 V(0,2) to rtol.  The grid (2 MiB per
+    field) runs from the on-die caches, so this is a latency figure."""
+    work = inputs.poisson_sine_noise(64, seed=1)
+    r = run_solver(nn4mg, torch, work, nn4mg.PREC_FP64, steps, warmup, rtol)
+    best, roof, pk = roofline(r, "fp64c")
+    hist = r["info"].history()
+    return {"workload": "64^3 constant-coefficient Poisson, zero Dirichlet, sin(pi x)sin(pi y)sin(pi z) "
+                        "+ 1e-3 U[-1,1), FP64 V(0,2) to rtol 1e-8, 5 levels to 4^3",
+            "value": round(r["n"] * r["cycles"] / r["dt"] / 1e9, 3), "unit": "Gcell-updates/s",
+            "ms_per_solve": round(r["dt"] / steps * 1e3, 3), "cycles_per_solve": r["info"].cycles,
+            "relres": r["info"].relres,
+            "reduction_per_cycle": round((r["info"].relres / r["info"].relres0) ** (1.0 / r["info"].cycles), 4),
+            "relres_history_first": [float(f"{v:.3e}") for v in hist[:6]],
+            "all_converged": r["all_converged"], "fine_kernels": pk,
+            "note": "all fields fit the 256 MB on-die cache; launch/latency-bound"}
+
+
+def bubble_bench(nn4mg, torch, inputs, steps, rtol):
+    """256 x 256 x 512 rising-bubble solve with the FP16-stored coefficient,
+    FP32 smoothing and FP64 residual/refinement, autotuned tiles per level;
+    its solution against the FP64 solve of the same system on the GPU."""
+    work = inputs.rising_bubble(256, seed=5)
+    r16 = run_solver(nn4mg, torch, work, nn4mg.PREC_FP16_COEF, steps, 1, rtol, keep_x=True)
+    r64 = run_solver(nn4mg, torch, work, nn4mg.PREC_FP64, 1, 0, rtol, profile=False, keep_x=True)
+    rf = run_solver(nn4mg, torch, work, nn4mg.PREC_FP16_COEF, 1, 1, rtol, outer=nn4mg.OUTER_FCG, profile=False)
+    x16, x64 = r16["x"], r64["x"]
+    err = float(torch.linalg.vector_norm(x16 - x64) / torch.linalg.vector_norm(x64))
+    best, roof, pk = roofline(r16, "fp16")
+    model = cycle_model_bytes(r16["levels"], "fp16")
+    return {"workload": "rising bubble 256x256x512 on a 1x1x2 box, air sphere r=0.25 at (0.5,0.5,0.5) in water "
+                        "(rho 1/1000), zero pressure on top, Neumann elsewhere, Gaussian RHS",
+            "dtype": "f16-stored k, f32 smoothing, f64 residual/coarsest/refinement",
+            "value": round(r16["n"] * r16["cycles"] / r16["dt"] / 1e9, 3), "unit": "Gcell-updates/s",
+            "ms_per_solve": round(r16["dt"] / steps * 1e3, 3), "cycles_per_solve": r16["info"].cycles,
+            "relres": r16["info"].relres, "all_converged": r16["all_converged"],
+            "fp64_solve_ms": round(r64["dt"] * 1e3, 3), "fp64_cycles": r64["info"].cycles,
+            "rel_diff_vs_fp64_solution": float(f"{err:.3e}"),
+            "fcg": {"ms_per_solve": round(rf["dt"] * 1e3, 3), "iterations": rf["info"].cycles,
+                    "relres": rf["info"].relres, "all_converged": rf["all_converged"]},
+            "roofline": roof, "roofline_kernel": best, "fine_kernels": pk,
+            "hbm_model_GBps": round(model * r16["cycles"] / r16["dt"] / 1e9, 1),
+            "model_bytes_per_cell_cycle": round(model / r16["n"], 2),
+            "tiles_per_level": r16["tiles"]}
+
+
 def cpu_baseline(work, min_seconds=10.0, max_cycles=12):
     """FP64 V-cycles of the same workload in the oracle (single-threaded C),
     repeated until about ten seconds of host time (a bounded sample)."""
@@ -322,6 +390,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--step-n", type=int, default=128, help="time-step grid edge (0: skip)")
     ap.add_argument("--step-steps", type=int, default=3)
+    ap.add_argument("--no-poisson64", action="store_true", help="skip the 64^3 constant-coefficient leg")
+    ap.add_argument("--no-bubble", action="store_true", help="skip the 256x256x512 FP16-coefficient leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -382,7 +452,7 @@ def main():
         "setup_ms": round(r64["setup_ms"], 2),
         "autotune_ms": round(r64["tune_ms"], 1),
         "tiles_per_level": r64["tiles"],
-        "update_coef_ms": round(r64["update_ms"], 2),
+        "update_coef_ms": round(r64["update_ms"], 2) if r64["update_ms"] is not None else None,
         "paper_context": {"metric": "1/H_s node-cycles/s (Eq. speed)", "value_G": 9.09,
                           "hardware": "NVIDIA A10", "precision": "not stated"},
     }
@@ -410,6 +480,12 @@ def main():
                          "relres": rf["info"].relres, "all_converged": rf["all_converged"],
                          "speedup_vs_stationary_fp64": round(r64["dt"] / rf["dt"], 3)}
         out["fcg"] = fcg
+    if not args.no_poisson64:
+        log("64^3 constant-coefficient Poisson, zero Dirichlet walls, FP64")
+        out["poisson64"] = poisson64_bench(nn4mg, torch, inputs, args.steps, args.warmup, args.rtol)
+    if not args.no_bubble:
+        log("rising bubble 256x256x512, FP16-stored coefficient")
+        out["bubble"] = bubble_bench(nn4mg, torch, inputs, min(args.steps, 3), args.rtol)
     if args.serve_requests > 0:
         log(f"served stream: {args.serve_requests} requests")
         out["serving"] = serving_bench(nn4mg, torch, args.serve_requests, args.serve_budget_gib, args.serve_slots)

@@ -21,6 +21,10 @@
 // exactly x <- S S (x + P e), since the Jacobi sweep is affine.  Output: the
 // correction stored (coarse levels, preconditioner z) or added into an FP64
 // field (finest level).
+// Each thread of the first sweep walks a vertical strip of cells and the
+// second sweep its RY output rows: every row of the 3-wide neighbourhood is
+// read from LDS once and reduced to the pair sum of its side cells and its
+// centre, which the two or three cells of the strip that reach it share.
 // Operator and sweep are those of the single-sweep kernel: with the plane
 // sums D (corners) and X (crosses) of the 3x3 neighbourhood,
 //   S = 2 D(z) + 2 (X(z-1) + X(z+1)) + D(z-1) + D(z+1),
@@ -35,6 +39,14 @@ namespace {
 
 constexpr int FT = 256;
 
+// Smallest strip height whose strips over a QX x QY region fit one per thread.
+constexpr int strip_rows(int qx, int qy)
+{
+    int r = 1;
+    while (((qy + r - 1) / r) * qx > FT) ++r;
+    return r;
+}
+
 template <int TX, int RY>
 struct FTile {
     static constexpr int TYT = FT / TX;                             // thread rows
@@ -42,7 +54,10 @@ struct FTile {
     static constexpr int QX = TX + 2, QY = TY + 2, QN = QX * QY;    // first-sweep region
     static constexpr int PX = TX + 4, PY = TY + 4, PN = PX * PY;    // input region
     static constexpr int NPRE = (PN + FT - 1) / FT;                 // input slots per thread
-    static constexpr int NS1 = (QN + FT - 1) / FT;                  // first-sweep slots per thread
+    // first sweep: one vertical strip of R1 cells per thread, NST strips per column
+    static constexpr int R1 = strip_rows(QX, QY);
+    static constexpr int NST = (QY + R1 - 1) / R1;
+    static constexpr int NT1 = NST * QX;                            // threads with a strip
     static constexpr int CX = TX / 2 + 4, CY = TY / 2 + 4, CN = CX * CY;  // coarse footprint
     static constexpr int NPREC = (CN + FT - 1) / FT;
 };
@@ -55,8 +70,8 @@ struct FGeo {
     int tap[TL::NPRE];    // prolongation: LDS tap | x-neighbour bit << 16 | y-neighbour bit << 17
     int coff[TL::NPREC];  // folded in-plane offset of each coarse slot
     bool cneg[TL::NPREC];
-    int boff[TL::NS1];    // folded in-plane offset of each first-sweep slot (right-hand side)
-    bool bneg[TL::NS1];
+    int boff[TL::R1];     // folded in-plane offset of each first-sweep strip cell (right-hand side)
+    bool bneg[TL::R1];
 };
 
 template <int TX, int RY>
@@ -85,10 +100,11 @@ __device__ __forceinline__ void make_fgeo(FGeo<TX, RY> &G, const StencilArgs &a,
         G.coff[q] = fI + a.cnx * fJ;
         G.cneg[q] = s < 0;
     }
+    const int t1 = min((int)threadIdx.x, TL::NT1 - 1);
+    const int sq = t1 / TL::QX, qx = t1 - sq * TL::QX;
 #pragma unroll
-    for (int q = 0; q < TL::NS1; ++q) {
-        const int idx = min((int)threadIdx.x + q * FT, TL::QN - 1);
-        const int qy = idx / TL::QX, qx = idx - qy * TL::QX;
+    for (int q = 0; q < TL::R1; ++q) {
+        const int qy = min(sq * TL::R1 + q, TL::QY - 1);  // rows past the region: any valid cell
         int s = 1;
         const int fi = fold(i0 + qx - 1, a.g.nx, a.g.bc[0], a.g.bc[1], s);
         const int fj = fold(j0 + qy - 1, a.g.ny, a.g.bc[2], a.g.bc[3], s);
@@ -105,7 +121,7 @@ struct FPre {
     using TL = FTile<TX, RY>;
     typename KStore<T, KT>::type k[HasK<KT>::value ? TL::NPRE : 1];
     T c1[TL::NPREC], c2[TL::NPREC];
-    T b1[TL::NS1];
+    T b1[TL::R1];
     T b2[RY];
     double xo[ADD ? RY : 1];
 };
@@ -120,32 +136,52 @@ struct Run {
     T qx, ox, qk, ok, qp, op, xc, kc;
 };
 
-// Plane sums at one position of a plane with row stride W (field v, coefficient k).
-template <typename T, bool HK, int W, int WK>
-__device__ __forceinline__ void sums_at(const T *v, int c, const T *k, int ck, PS<T> &o)
+// One row of a 3-wide neighbourhood: the pair sum of its two side cells and
+// its centre, for the field v, the coefficient k and the product k v.
+template <typename T>
+struct Row {
+    T h, m, kh, km, ph, pm;
+};
+
+template <typename T, bool HK>
+__device__ __forceinline__ Row<T> row_at(const T *v, int c, const T *k, int ck)
 {
-    const T v00 = v[c - W - 1], v01 = v[c - W], v02 = v[c - W + 1];
-    const T v10 = v[c - 1], v11 = v[c], v12 = v[c + 1];
-    const T v20 = v[c + W - 1], v21 = v[c + W], v22 = v[c + W + 1];
-    const T D = (v00 + v02) + (v20 + v22);
-    const T X = (v01 + v21) + (v10 + v12);
-    o.xc = v11;
+    Row<T> o;
+    const T vl = v[c - 1], vm = v[c], vr = v[c + 1];
+    o.h = vl + vr;
+    o.m = vm;
+    if constexpr (HK) {
+        const T kl = k[ck - 1], km = k[ck], kr = k[ck + 1];
+        o.kh = kl + kr;
+        o.km = km;
+        o.ph = kl * vl + kr * vr;
+        o.pm = km * vm;
+    }
+    return o;
+}
+
+// Plane sums of the centre row b of three consecutive rows a, b, c.
+template <typename T, bool HK>
+__device__ __forceinline__ PS<T> col_sums(const Row<T> &a, const Row<T> &b, const Row<T> &c)
+{
+    PS<T> o;
+    const T D = a.h + c.h;
+    const T X = (a.m + c.m) + b.h;
+    o.xc = b.m;
     o.xa = D + D;
     o.xo = fma((T)2, X, D);
     if constexpr (HK) {
-        const T k00 = k[ck - WK - 1], k01 = k[ck - WK], k02 = k[ck - WK + 1];
-        const T k10 = k[ck - 1], k11 = k[ck], k12 = k[ck + 1];
-        const T k20 = k[ck + WK - 1], k21 = k[ck + WK], k22 = k[ck + WK + 1];
-        const T Dk = (k00 + k02) + (k20 + k22);
-        const T Xk = (k01 + k21) + (k10 + k12);
-        const T Dp = (k00 * v00 + k02 * v02) + (k20 * v20 + k22 * v22);
-        const T Xp = (k01 * v01 + k21 * v21) + (k10 * v10 + k12 * v12);
-        o.kc = k11;
+        const T Dk = a.kh + c.kh;
+        const T Xk = (a.km + c.km) + b.kh;
+        const T Dp = a.ph + c.ph;
+        const T Xp = (a.pm + c.pm) + b.ph;
+        o.kc = b.km;
         o.ka = Dk + Dk;
         o.ko = fma((T)2, Xk, Dk);
         o.pa = Dp + Dp;
         o.po = fma((T)2, Xp, Dp);
     }
+    return o;
 }
 
 template <typename T, bool HK>
@@ -220,7 +256,10 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
     FGeo<TX, RY> G;
     make_fgeo<TX, RY>(G, a, i0, j0);
     FPre<T, KT, TX, RY, ADD> pA, pB;
-    Run<T> r1[TL::NS1], r2[RY];
+    Run<T> r1[TL::R1], r2[RY];
+    const bool act1 = (int)threadIdx.x < TL::NT1;
+    const int s1q = min((int)threadIdx.x, TL::NT1 - 1) / TL::QX;   // strip of this thread
+    const int s1x = min((int)threadIdx.x, TL::NT1 - 1) - s1q * TL::QX;
 
     const T *bp = (const T *)a.b;
     const T *ep = (const T *)a.ec;
@@ -246,7 +285,7 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
             int sb = 1;
             const size_t pb = plane * (size_t)fold(zi - 1, nz, a.g.bc[4], a.g.bc[5], sb);
 #pragma unroll
-            for (int q = 0; q < TL::NS1; ++q) p.b1[q] = bp[pb + (size_t)G.boff[q]];
+            for (int q = 0; q < TL::R1; ++q) p.b1[q] = bp[pb + (size_t)G.boff[q]];
         }
         if (zi - 2 >= z0 && zi - 2 < z1) {
             const size_t pl = plane * (size_t)(zi - 2);
@@ -292,7 +331,7 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
     int buf = 0;  // sx/sk buffer of the plane being committed (rotates through 3)
     auto step = [&](FPre<T, KT, TX, RY, ADD> &p, int zi) {
         commit(p, zi, buf);
-        T b1[TL::NS1], b2[RY];
+        T b1[TL::R1], b2[RY];
         double xo[ADD ? RY : 1];
         bool bzneg = false;
         {
@@ -301,7 +340,7 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
             bzneg = sb < 0;
         }
 #pragma unroll
-        for (int q = 0; q < TL::NS1; ++q) b1[q] = (G.bneg[q] != bzneg) ? -p.b1[q] : p.b1[q];
+        for (int q = 0; q < TL::R1; ++q) b1[q] = (G.bneg[q] != bzneg) ? -p.b1[q] : p.b1[q];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             b2[r] = p.b2[r];
@@ -309,18 +348,26 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
         }
         if (zi + 2 <= z1 + 1) fetch(p, zi + 2);
 
-        // first sweep: absorb plane zi at every ring slot, completing y1(zi - 1)
+        // first sweep: absorb plane zi down the thread's strip, completing y1(zi - 1)
         const int yb = (zi - 1) & 1;
+        if (act1) {
+            // window rows j = 0 .. R1 + 1 of the input plane (region rows
+            // s1q R1 - 1 .. s1q R1 + R1), clamped into the staged plane
+            auto wrow = [&](int j) {
+                const int py = min(s1q * TL::R1 + j, TL::PY - 1);
+                const int c = py * TL::PX + (s1x + 1);
+                return row_at<T, HK>(sx[buf], c, sk[buf], c);
+            };
+            Row<T> w0 = wrow(0), w1 = wrow(1);
 #pragma unroll
-        for (int q = 0; q < TL::NS1; ++q) {
-            const int idx = q * FT + threadIdx.x;
-            if (idx < TL::QN) {
-                const int qy = idx / TL::QX, qx = idx - qy * TL::QX;
-                const int c = (qy + 1) * TL::PX + (qx + 1);
-                PS<T> ps;
-                sums_at<T, HK, TL::PX, TL::PX>(sx[buf], c, sk[buf], c, ps);
-                if (zi >= z0) sy[yb][idx] = jacobi<T, HK>(r1[q], ps, b1[q], cw, om_w0, om, icv);
+            for (int q = 0; q < TL::R1; ++q) {
+                const Row<T> w2 = wrow(q + 2);
+                const PS<T> ps = col_sums<T, HK>(w0, w1, w2);
+                const int qy = s1q * TL::R1 + q;
+                if (zi >= z0 && qy < TL::QY) sy[yb][qy * TL::QX + s1x] = jacobi<T, HK>(r1[q], ps, b1[q], cw, om_w0, om, icv);
                 absorb<T, HK>(r1[q], ps, zi == z0 - 2);
+                w0 = w1;
+                w1 = w2;
             }
         }
         if (zi >= z0) {
@@ -328,11 +375,19 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
             // second sweep: absorb y1(zi - 1) with the coefficient plane zi - 1,
             // completing the output plane zi - 2
             const int kb = (buf + 2) % 3;
+            // window rows j = 0 .. RY + 1 of the first-sweep plane (rows RY ly + j),
+            // coefficient one row and column further in the input region
+            auto wrow = [&](int j) {
+                const int yy = RY * ly + j;
+                return row_at<T, HK>(sy[yb], yy * TL::QX + (lx + 1), sk[kb], (yy + 1) * TL::PX + (lx + 2));
+            };
+            Row<T> w0 = wrow(0), w1 = wrow(1);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
-                const int sxq = lx + 1, syq = RY * ly + r + 1;
-                PS<T> ps;
-                sums_at<T, HK, TL::QX, TL::PX>(sy[yb], syq * TL::QX + sxq, sk[kb], (syq + 1) * TL::PX + (sxq + 1), ps);
+                const Row<T> w2 = wrow(r + 2);
+                const PS<T> ps = col_sums<T, HK>(w0, w1, w2);
+                w0 = w1;
+                w1 = w2;
                 if (zi >= z0 + 2) {
                     const T y = jacobi<T, HK>(r2[r], ps, b2[r], cw, om_w0, om, icv);
                     if (valid[r]) {
