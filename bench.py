@@ -18,7 +18,8 @@ solve of the same workload, the flexible-CG outer iteration (time to the same
 tolerance), the 64^3 constant-coefficient Dirichlet Poisson solve, the
 256 x 256 x 512 rising-bubble solve with the FP16-stored coefficient (and its
 difference from the FP64 solve of the same system), one two-phase time step on
-a 128^3 collapsing column split into pressure solves and explicit stencils, the
+a 128^3 collapsing column split into pressure solves and explicit stencils (and
+the same step at 64^3 .. 256^3 with M_s and H_s of Eq. speed fitted), the
 served stream of 512 solves of uneven sizes (solves/s, p50/p99 latency), and
 the FP64 oracle timed on the host over a bounded sample of V-cycles of the same
 workload.
@@ -304,6 +305,40 @@ def step_bench(nn4mg, torch, n, steps):
                               "note": "Eq. speed coefficients: seconds per node (times polynomial order p; here p = 1)"}}
 
 
+def eq_speed_fit(nn4mg, torch, sizes=(64, 96, 128, 192, 256), steps=2):
+    """Eq. speed on this GPU: the collapsing-column step timed at several grid
+    sizes, then M_s and H_s fitted by least squares through the origin
+    (explicit time = N M_s, pressure-solve time = N (N_h + N_I N_nh) H_s, p = 1),
+    with each size's deviation from the fitted model."""
+    import numpy as np
+
+    pts = []
+    for n in sizes:
+        r = step_bench(nn4mg, torch, n, steps)
+        pts.append((n, n ** 3, r["ms_per_step"], r["ms_pressure_solves"], r["ms_explicit"]))
+        log(f"  step {n}^3: {r['ms_per_step']:.3f} ms ({r['ms_pressure_solves']:.3f} ms in the solves)")
+    p = nn4mg.step_params()
+    cycles = p.mg_cycles * (1 + p.n_corr)
+    N = np.array([q[1] for q in pts], dtype=np.float64)
+    mg = np.array([q[3] for q in pts]) * 1e-3
+    ex = np.array([q[4] for q in pts]) * 1e-3
+    Ms = float(np.dot(N, ex) / np.dot(N, N))
+    Hs = float(np.dot(N * cycles, mg) / np.dot(N * cycles, N * cycles))
+    model = N * (Ms + cycles * Hs)
+    meas = mg + ex
+    # affine fits: a fixed per-step cost (launch-bound coarse levels, small grids) plus the per-node slope
+    A = np.stack([np.ones_like(N), N], axis=1)
+    (ex0, Ms_a), (mg0, mgs) = np.linalg.lstsq(A, ex, rcond=None)[0], np.linalg.lstsq(A, mg, rcond=None)[0]
+    return {"sizes": [q[0] for q in pts], "ms_per_step": [q[2] for q in pts],
+            "ms_pressure_solves": [q[3] for q in pts], "ms_explicit": [q[4] for q in pts],
+            "cycles_per_step": cycles, "M_s": Ms, "H_s": Hs,
+            "model_rel_error": [round(float(v), 3) for v in (model - meas) / meas],
+            "fit": "least squares through the origin over the sizes listed, p = 1",
+            "affine": {"M_s": float(Ms_a), "H_s": float(mgs / cycles), "explicit_fixed_ms": round(float(ex0) * 1e3, 3),
+                       "solves_fixed_ms": round(float(mg0) * 1e3, 3)},
+            "paper_context": {"A10": {"M_s": 1.2e-8, "H_s": 1.1e-10}, "RTX A5000": {"M_s": 1.37e-8, "H_s": 1.3e-10}}}
+
+
 def poisson64_bench(nn4mg, torch, inputs, steps, warmup, rtol):
     """64^3 constant-coefficient Poisson on the unit cube, zero Dirichlet walls,
     sine mode plus 1e-3 uniform noise, FP64 V(0,2) to rtol.  The grid (2 MiB per
@@ -392,6 +427,7 @@ def main():
     ap.add_argument("--step-steps", type=int, default=3)
     ap.add_argument("--no-poisson64", action="store_true", help="skip the 64^3 constant-coefficient leg")
     ap.add_argument("--no-bubble", action="store_true", help="skip the 256x256x512 FP16-coefficient leg")
+    ap.add_argument("--no-eq-speed", action="store_true", help="skip the multi-size time-step fit of Eq. speed")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -492,6 +528,9 @@ def main():
     if args.step_n > 0:
         log(f"time step: {args.step_n}^3 collapsing column")
         out["step"] = step_bench(nn4mg, torch, args.step_n, args.step_steps)
+    if not args.no_eq_speed:
+        log("Eq. speed fit: time step at 64^3 .. 256^3")
+        out["eq_speed"] = eq_speed_fit(nn4mg, torch)
     if not args.no_cpu_baseline:
         log("CPU baseline: oracle, one V-cycle")
         out["cpu_baseline"] = cpu_baseline(work)

@@ -169,18 +169,24 @@ int nn4mg_profile_read_level(nn4mg_t h, int level, int kclass, int *launches, do
 
 /* Launch shape of one stencil kernel class (NN4MG_KCLASS_*; -1 = all classes
  * for set) of one level: tile width tx (64, 32 or 16 cells along x), ry cell
- * rows per thread (2 or 4; 2 when tx == 16; the tile is tx x ry*256/tx cells
- * in x-y) and the number of z-planes zc (even, >= 2) each workgroup marches.
- * Any shape gives the same results; only the speed differs.  EINVAL for a bad
- * level, class or shape. */
+ * rows per thread (1, 2 or 4; 2 or 1 when tx == 16; 2 or 4 for the residual
+ * class; the tile is tx x ry*256/tx cells in x-y) and the number of z-planes
+ * zc (even, >= 2) each workgroup marches.  With the default two post-sweeps
+ * the first-sweep class also accepts (8, 8, 8): both sweeps of the level run
+ * as independent 8^3 blocks (one round of loads per block instead of a march
+ * over z; for small levels); any other shape of that class switches it back.
+ * Any shape gives the same results up to rounding; only the speed differs.
+ * EINVAL for a bad level, class or shape, or (8, 8, 8) on a level without the
+ * two-sweep kernel (nu_post != 2, or a dimension below 4). */
 int nn4mg_set_tiles(nn4mg_t h, int level, int kclass, int tx, int ry, int zc);
 int nn4mg_get_tiles(nn4mg_t h, int level, int kclass, int *tx, int *ry, int *zc);
 
 /* Autotuner: time the candidate launch shapes (tile width, rows per thread,
- * z-chunk) on a few cycles with b_dev and x_dev as input (x_dev is
- * overwritten), keep the fastest shape per level and kernel class, and return
- * them in tiles_out (9 ints per level: tx, ry, zc for each of the 3 classes;
- * may be NULL).  Synchronous. */
+ * z-chunk, and the 8^3 block form of the two sweeps) on a few cycles with
+ * b_dev and x_dev as input (x_dev is overwritten), keep the fastest shape per
+ * level and kernel class, and return them in tiles_out (9 ints per level: tx,
+ * ry, zc for each of the 3 classes; (8, 8, 8) for the block form; may be
+ * NULL).  Synchronous. */
 int nn4mg_autotune(nn4mg_t h, const double *b_dev, double *x_dev, int *tiles_out, int max_levels);
 
 /* ---- Continuous-batching solve server ------------------------------------

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnn4mg.so")
-SOURCES = ["mg_stencil.hip", "mg_kernels.hip", "mg_api.hip", "mg_server.hip", "mg_step.hip", "mg_fcg.hip", "mg_tail.hip", "mg_fused.hip"]
+SOURCES = ["mg_stencil.hip", "mg_kernels.hip", "mg_api.hip", "mg_server.hip", "mg_step.hip", "mg_fcg.hip", "mg_tail.hip", "mg_fused.hip", "mg_block.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

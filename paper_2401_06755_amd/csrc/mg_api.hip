@@ -50,6 +50,7 @@ struct Level {
     float *b32 = nullptr, *e32 = nullptr, *t32 = nullptr, *t32b = nullptr;  // FP32 cycle buffers
     void *ks = nullptr;                               // FP32 / FP16 smoothing coefficient
     TileShape tiles[3]{};  // launch shape per kernel class (NN4MG_KCLASS_*)
+    bool block2 = false;   // both sweeps as 8^3 blocks instead of the z-marching kernel
 };
 
 // Default launch shape of a level: the tile width that pads the x-y plane
@@ -488,10 +489,16 @@ int enqueue_sweep2(nn4mg_hier *H, int l, const void *b, void *y, double *x64, in
     a.x64 = x64;
     a.done = done;
     const long pr = prof_begin(H, NN4MG_KCLASS_FINE_SWEEP_PROLONG, l);
-    HIP_TRY(launch_sweep2(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, out_mode, a, H->stream));
+    if (H->lv[l].block2)
+        HIP_TRY(launch_sweep2_block(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, out_mode, a, H->stream));
+    else
+        HIP_TRY(launch_sweep2(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, out_mode, a, H->stream));
     prof_end(H, pr);
     return NN4MG_OK;
 }
+
+// Largest coarse level that defaults to the 8^3 block form of the two sweeps.
+constexpr size_t kBlock2MaxCells = 64 * 64 * 64;
 
 bool level_fusable(const nn4mg_hier *H, int l)
 {
@@ -819,6 +826,9 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
     H->nc = (int)C.n;
     H->tail = choose_tail(H);
     H->fused = cfg->nu_post == 2 && H->L >= 2;
+    // coarse levels of up to 64^3 cells: the block form of the two sweeps is
+    // shorter than a march over z (the autotuner re-decides per level)
+    for (int l = 1; l < H->L; ++l) H->lv[l].block2 = level_fusable(H, l) && H->lv[l].n <= kBlock2MaxCells;
     TRY(dalloc(H, &H->ainv, (size_t)H->nc * H->nc));
     TRY(dalloc(H, &H->st, 1));
     TRY(dalloc(H, &H->partials, (size_t)maxblk));
@@ -1234,6 +1244,17 @@ int nn4mg_set_tiles(nn4mg_t H, int level, int kclass, int tx, int ry, int zc)
     if (!H) return fail(NN4MG_EINVAL, "handle is NULL");
     if (level < 0 || level >= H->L) return fail(NN4MG_EINVAL, "bad level");
     if (kclass < -1 || kclass >= NN4MG_KCLASS_COUNT) return fail(NN4MG_EINVAL, "bad kernel class");
+    if (tx == 8) {
+        // both post-sweeps as 8^3 blocks: a shape of the first-sweep class of a fused level only
+        if (kclass != NN4MG_KCLASS_FINE_SWEEP_PROLONG || ry != 8 || zc != 8)
+            return fail(NN4MG_EINVAL, "the 8^3 block shape is (8, 8, 8) for the first-sweep class only");
+        if (!level_fusable(H, level))
+            return fail(NN4MG_EINVAL, "the 8^3 block shape needs nu_post == 2 and a level of at least 4^3");
+        HIP_TRY(hipStreamSynchronize(H->stream));
+        H->lv[level].block2 = true;
+        H->tiles_epoch++;
+        return NN4MG_OK;
+    }
     if ((tx != 64 && tx != 32 && tx != 16) || (ry != 1 && ry != 2 && ry != 4) || (tx == 16 && ry == 4) || zc < 2 ||
         (zc & 1))
         return fail(NN4MG_EINVAL, "bad tile shape");
@@ -1248,6 +1269,7 @@ int nn4mg_set_tiles(nn4mg_t H, int level, int kclass, int tx, int ry, int zc)
         if (ry == 1 && c == NN4MG_KCLASS_FINE_RESID) continue;  // kclass -1: sweeps only
         if (kclass < 0 || kclass == c) V.tiles[c] = t;
     }
+    if (kclass < 0 || kclass == NN4MG_KCLASS_FINE_SWEEP_PROLONG) V.block2 = false;
     H->tiles_epoch++;
     return NN4MG_OK;
 }
@@ -1258,9 +1280,10 @@ int nn4mg_get_tiles(nn4mg_t H, int level, int kclass, int *tx, int *ry, int *zc)
     if (level < 0 || level >= H->L) return fail(NN4MG_EINVAL, "bad level");
     if (kclass < 0 || kclass >= NN4MG_KCLASS_COUNT) return fail(NN4MG_EINVAL, "bad kernel class");
     const TileShape &t = H->lv[level].tiles[kclass];
-    if (tx) *tx = t.tx;
-    if (ry) *ry = t.ry;
-    if (zc) *zc = t.zc;
+    const bool blk = kclass == NN4MG_KCLASS_FINE_SWEEP_PROLONG && H->lv[level].block2;
+    if (tx) *tx = blk ? 8 : t.tx;
+    if (ry) *ry = blk ? 8 : t.ry;
+    if (zc) *zc = blk ? 8 : t.zc;
     return NN4MG_OK;
 }
 
@@ -1279,6 +1302,7 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
     std::vector<TileShape> best_t((size_t)L * NC);
     for (int l = 0; l < L; ++l)
         for (int c = 0; c < NC; ++c) best_t[(size_t)l * NC + c] = H->lv[l].tiles[c];
+    for (int l = 0; l < L; ++l) H->lv[l].block2 = false;  // the marching shapes are timed first
     const bool saved_on = H->prof_on;
     auto clear = [&]() {
         H->prof_cls.clear();
@@ -1334,6 +1358,39 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
         }
     for (int l = 0; l < L; ++l)
         for (int c = 0; c < NC; ++c) H->lv[l].tiles[c] = best_t[(size_t)l * NC + c];
+    // the 8^3 block kernel against the best marching shape, per fused level
+    {
+        constexpr int C1 = NN4MG_KCLASS_FINE_SWEEP_PROLONG;
+        std::vector<bool> cand(L, false);
+        bool any = false;
+        for (int l = 0; l < L; ++l) {
+            H->lv[l].block2 = false;
+            if (level_fusable(H, l)) cand[l] = any = true;
+        }
+        if (any) {
+            for (int l = 0; l < L; ++l) H->lv[l].block2 = cand[l];
+            HIP_TRY(hipStreamSynchronize(H->stream));
+            H->prof_on = true;
+            clear();
+            H->cur_tag = 0;
+            for (int r = 0; r < reps + 1; ++r) {
+                if (r == 1) {
+                    HIP_TRY(hipStreamSynchronize(H->stream));
+                    clear();
+                }
+                if ((rc = enqueue_resid_for_cycle(H, b, x, nullptr, false, nullptr))) return rc;
+                if ((rc = enqueue_body(H, b, nullptr, x, nullptr))) return rc;
+            }
+            H->prof_on = false;
+            for (int l = 0; l < L; ++l) {
+                if (!cand[l]) continue;
+                double ms = 0.0;
+                int n = 0;
+                if ((rc = nn4mg_profile_read_level(H, l, C1, &n, &ms))) return rc;
+                H->lv[l].block2 = n > 0 && ms < best[(size_t)l * NC + C1];
+            }
+        }
+    }
     H->tiles_epoch++;
     H->prof_on = saved_on;
     clear();
@@ -1341,9 +1398,10 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
         for (int l = 0; l < L && l < max_levels; ++l)
             for (int c = 0; c < NC; ++c) {
                 const TileShape &t = best_t[(size_t)l * NC + c];
-                tiles_out[9 * l + 3 * c] = t.tx;
-                tiles_out[9 * l + 3 * c + 1] = t.ry;
-                tiles_out[9 * l + 3 * c + 2] = t.zc;
+                const bool blk = c == NN4MG_KCLASS_FINE_SWEEP_PROLONG && H->lv[l].block2;
+                tiles_out[9 * l + 3 * c] = blk ? 8 : t.tx;
+                tiles_out[9 * l + 3 * c + 1] = blk ? 8 : t.ry;
+                tiles_out[9 * l + 3 * c + 2] = blk ? 8 : t.zc;
             }
     return NN4MG_OK;
 }

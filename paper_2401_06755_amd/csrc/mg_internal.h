@@ -158,6 +158,13 @@ hipError_t launch_zero(double *x, size_t n, const int *done, hipStream_t s);
 bool sweep2_supports(int tx, int ry);
 hipError_t launch_sweep2(int T_is_f64, int kt, int out_mode, const StencilArgs &a, hipStream_t s);
 
+// ---- the same two sweeps as independent 8^3 blocks (mg_block.hip) ----
+// Same arguments and result as launch_sweep2 (a.t is not used); one
+// workgroup per 8^3 block of the level, for levels whose marching chain of
+// planes, not their bytes, sets the time.
+int block2_blocks(int nx, int ny, int nz);
+hipError_t launch_sweep2_block(int T_is_f64, int kt, int out_mode, const StencilArgs &a, hipStream_t s);
+
 // ---- coarse end of the cycle in one workgroup (mg_tail.hip) ----
 constexpr int kTailMaxLevels = 8;
 struct TailArgs {
