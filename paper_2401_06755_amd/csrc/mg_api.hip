@@ -227,6 +227,7 @@ struct nn4mg_hier {
     int L = 0;
     Level lv[kMaxLevels];
     int tail = 0;           // first level of the one-workgroup coarse end (0: none)
+    void *ktail = nullptr;  // padded coefficients of the tail levels (nodal; FP64, or FP32 when mixed)
     bool fused = false;     // both post-sweeps of a level in one pass (nu_post == 2)
     int singular = 0;
     int mixed = 0;
@@ -308,6 +309,8 @@ size_t bytes_for(const nn4mg_config *c)
             if ((size_t)t.blocks() > maxblk) maxblk = t.blocks();
         }
         if (nodal) b += 8 * n;
+        // padded coefficient copy of a possible tail level
+        if (nodal && n <= 1024) b += 8 * (size_t)((c->nx >> l) + 2) * ((c->ny >> l) + 2) * ((c->nz >> l) + 2);
         if (!mixed) {
             b += (l == 0) ? 8 * n : 24 * n;
         } else {
@@ -333,14 +336,25 @@ int choose_tail(const nn4mg_hier *H)
 {
     if (H->L < 2) return 0;
     const size_t elt = H->mixed ? 4 : 8;
-    const size_t fields = H->cfg.coef_mode == NN4MG_COEF_NODAL ? 4 : 3;
+    const int nodal = H->cfg.coef_mode == NN4MG_COEF_NODAL;
+    const Level &C = H->lv[H->L - 1];
+    if ((size_t)(C.nx + 2) * (C.ny + 2) * (C.nz + 2) > 2 * kTailMaxCells) return 0;  // no tail
     for (int T = 1; T < H->L; ++T) {
         if (H->L - T > kTailMaxLevels) continue;
-        size_t n = 0;
-        for (int l = T; l < H->L; ++l) n += H->lv[l].n;
-        if (fields * n * elt + 48 * 1024 <= kTailLdsBudget && H->lv[T].n <= kTailMaxCells) return T;
+        int nx[kTailMaxLevels], ny[kTailMaxLevels], nz[kTailMaxLevels];
+        bool fits = true;
+        for (int l = T; l < H->L; ++l) {
+            nx[l - T] = H->lv[l].nx;
+            ny[l - T] = H->lv[l].ny;
+            nz[l - T] = H->lv[l].nz;
+            // the workgroup covers at most two padded cells per thread
+            fits = fits && (size_t)(nx[l - T] + 2) * (ny[l - T] + 2) * (nz[l - T] + 2) <= 2 * kTailMaxCells;
+        }
+        if (!fits) continue;
+        const size_t cells = tail_field_cells(nx, ny, nz, H->L - T, nodal);
+        if (cells * elt + 48 * 1024 <= kTailLdsBudget && H->lv[T].n <= kTailMaxCells) return T;
     }
-    return H->L - 1;
+    return H->lv[H->L - 1].n <= kTailMaxCells ? H->L - 1 : 0;
 }
 
 int rebuild_coefficients(nn4mg_hier *H)
@@ -354,6 +368,17 @@ int rebuild_coefficients(nn4mg_hier *H)
                                      c.coarse_avg, s));
         if (H->mixed)
             for (int l = 0; l < H->L; ++l) HIP_TRY(launch_cast_k(H->lv[l].k, H->lv[l].ks, H->lv[l].n, H->kts, s));
+        if (H->ktail) {
+            size_t off = 0;
+            const size_t elt = H->mixed ? sizeof(float) : sizeof(double);
+            for (int l = H->tail; l < H->L; ++l) {
+                const Level &V = H->lv[l];
+                HIP_TRY(launch_tail_kpad(H->mixed ? 0 : 1, H->mixed ? H->kts : KT_F64,
+                                         H->mixed ? V.ks : (const void *)V.k, V.nx, V.ny, V.nz, c.bc,
+                                         (char *)H->ktail + off * elt, s));
+                off += (size_t)(V.nx + 2) * (V.ny + 2) * (V.nz + 2);
+            }
+        }
     }
     const Level &C = H->lv[H->L - 1];
     std::vector<double> hk;
@@ -644,8 +669,8 @@ int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, doub
             ta.ny[l - T] = V.ny;
             ta.nz[l - T] = V.nz;
             ta.h[l - T] = V.h;
-            ta.k[l - T] = f64 ? (const void *)V.k : V.ks;
         }
+        ta.kpad = H->ktail;
         if (T >= 2)
             ta.b_above = f64 ? (const void *)H->lv[T - 1].b : (const void *)H->lv[T - 1].b32;
         else
@@ -829,6 +854,20 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
     // coarse levels of up to 64^3 cells: the block form of the two sweeps is
     // shorter than a march over z (the autotuner re-decides per level)
     for (int l = 1; l < H->L; ++l) H->lv[l].block2 = level_fusable(H, l) && H->lv[l].n <= kBlock2MaxCells;
+    if (nodal && H->tail > 0) {
+        size_t cells = 0;
+        for (int l = H->tail; l < H->L; ++l)
+            cells += (size_t)(H->lv[l].nx + 2) * (H->lv[l].ny + 2) * (H->lv[l].nz + 2);
+        if (H->mixed) {
+            float *p;
+            TRY(dalloc(H, &p, cells));
+            H->ktail = p;
+        } else {
+            double *p;
+            TRY(dalloc(H, &p, cells));
+            H->ktail = p;
+        }
+    }
     TRY(dalloc(H, &H->ainv, (size_t)H->nc * H->nc));
     TRY(dalloc(H, &H->st, 1));
     TRY(dalloc(H, &H->partials, (size_t)maxblk));

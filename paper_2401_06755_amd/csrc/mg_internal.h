@@ -171,7 +171,8 @@ struct TailArgs {
     int levels;                         // tail levels, finest first; the last is the coarsest
     int nx[kTailMaxLevels], ny[kTailMaxLevels], nz[kTailMaxLevels];
     double h[kTailMaxLevels];
-    const void *k[kTailMaxLevels];      // coefficient per level (storage type of the launch), NULL if constant
+    const void *kpad;                   // coefficient of every tail level on its padded cells (type T), finest
+                                        // first, built by launch_tail_kpad; NULL if constant
     const void *b_above;                // right-hand side of the level above the first tail level, or NULL
     const void *b_first;                // right-hand side of the first tail level (when b_above is NULL)
     void *e_first;                      // out: correction of the first tail level
@@ -183,7 +184,14 @@ struct TailArgs {
     int nu;
     const int *done;                    // skip when *done != 0 (may be NULL)
 };
+// LDS elements of the tail levels' fields: right-hand side, two iterates and
+// (nodal) the coefficient per level, the last three with a one-cell halo.
+size_t tail_field_cells(const int *nx, const int *ny, const int *nz, int levels, int nodal);
 size_t tail_lds_bytes(const TailArgs &a, int t_is_f64, int nodal);
+// Padded copy (one-cell halo by the +mirror rule) of a level's coefficient k
+// (storage type kt) as type T (double if T_is_f64, else float), for the tail.
+hipError_t launch_tail_kpad(int T_is_f64, int kt, const void *k, int nx, int ny, int nz, const int *bc, void *out,
+                            hipStream_t s);
 hipError_t launch_tail(int T_is_f64, int kt, const TailArgs &a, hipStream_t s);
 
 // Record the message returned by nn4mg_last_error() on this thread; returns code.

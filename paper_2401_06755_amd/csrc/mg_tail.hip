@@ -47,6 +47,10 @@ __device__ __forceinline__ int tfold(int i, int n, int lo, int hi, int &sgn)
     return i;
 }
 
+struct Bc6 {
+    int v[6];
+};
+
 template <typename T, typename KT>
 __device__ __forceinline__ T kval(const KT *k, int g)
 {
@@ -57,16 +61,94 @@ __device__ __forceinline__ T kval(const KT *k, int g)
 }
 
 // One tail level: dims, spacing and the offsets of its LDS fields (elements
-// of the shared array): right-hand side, two iterates and the coefficient.
+// of the shared array).  The right-hand side is stored without a halo; the two
+// iterates and the coefficient carry a one-cell halo (padded dims px = nx + 2,
+// ...), so stencils read fixed offsets.
 struct Lv {
     int nx, ny, nz, n;
+    int px, pxy, pn;   // padded row, plane and cell counts
+    double rpx, rpxy;  // their reciprocals
     double h;
     int ob, oya, oyb, ok;
 };
 
-// out = y + omega (b - A y) / D over the level; every field in LDS.
+// The padded cells of a level a thread owns (p = thread + r * 1024, r < 2):
+// the interior cell each holds (the folded one for a halo cell), its padded
+// index and the sign of the boundary rule across the fold.  Computed once per
+// level and shared by the prolongation and the sweeps.
+struct PCell {
+    int c, q, i, j, k, sg;  // c < 0: no cell
+};
+
+__device__ __forceinline__ void padded_cells(const Lv &V, const int *bc, PCell (&pc)[2])
+{
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int p = (int)threadIdx.x + r * TT;
+        if (p < V.pn) {
+            // p / px and p / pxy through a double reciprocal: exact for these small indices
+            const int pk = (int)(((double)p + 0.5) * V.rpxy);
+            const int rem = p - pk * V.pxy;
+            const int pj = (int)(((double)rem + 0.5) * V.rpx);
+            const int pi = rem - pj * V.px;
+            int sg = 1;
+            const int i = tfold(pi - 1, V.nx, bc[0], bc[1], sg);
+            const int j = tfold(pj - 1, V.ny, bc[2], bc[3], sg);
+            const int k = tfold(pk - 1, V.nz, bc[4], bc[5], sg);
+            pc[r] = {i + V.nx * (j + V.ny * k), (k + 1) * V.pxy + (j + 1) * V.px + (i + 1), i, j, k, sg};
+        } else {
+            pc[r] = {-1, 0, 0, 0, 0, 1};
+        }
+    }
+}
+
+__device__ __forceinline__ int padded_of(const Lv &V, int c)
+{
+    const int i = c % V.nx, t = c / V.nx;
+    const int j = t % V.ny, k = t / V.ny;
+    return (k + 1) * V.pxy + (j + 1) * V.px + (i + 1);
+}
+
+__device__ __forceinline__ double trecip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return fma(fma(-d, r, 1.0), r, r);
+}
+__device__ __forceinline__ float trecip(float d)
+{
+    const float r = __builtin_amdgcn_rcpf(d);
+    return fmaf(fmaf(-d, r, 1.0f), r, r);
+}
+
+// Corner (D) and cross (X) sums of the 3x3 neighbourhood of o in a plane of row stride W.
+template <typename T>
+__device__ __forceinline__ T dsum(const T *v, int o, int W)
+{
+    return (v[o - W - 1] + v[o - W + 1]) + (v[o + W - 1] + v[o + W + 1]);
+}
+template <typename T>
+__device__ __forceinline__ T xsum(const T *v, int o, int W)
+{
+    return (v[o - W] + v[o + W]) + (v[o - 1] + v[o + 1]);
+}
+template <typename T>
+__device__ __forceinline__ T dprod(const T *v, const T *k, int o, int W)
+{
+    return (k[o - W - 1] * v[o - W - 1] + k[o - W + 1] * v[o - W + 1]) +
+           (k[o + W - 1] * v[o + W - 1] + k[o + W + 1] * v[o + W + 1]);
+}
+template <typename T>
+__device__ __forceinline__ T xprod(const T *v, const T *k, int o, int W)
+{
+    return (k[o - W] * v[o - W] + k[o + W] * v[o + W]) + (k[o - 1] * v[o - 1] + k[o + 1] * v[o + 1]);
+}
+
+// out = y + omega (b - A y) / D at every padded cell (halo cells take the
+// signed value of the interior cell they mirror, so out is halo-complete):
+// S = 2 D(z) + 2 (X(z-1) + X(z+1)) + D(z-1) + D(z+1) for y, k and k y.
 template <typename T, bool HK>
-__device__ __forceinline__ void sweep(T *sm, const Lv &L, int oy, int oo, const int *bc, T omega)
+__device__ __forceinline__ void sweep(T *sm, const Lv &L, const PCell (&pc)[2], int oy, int oo, T omega)
 {
     const T h = (T)L.h;
     const T cw = -h / (T)12, icv = (T)24 / h;
@@ -75,88 +157,55 @@ __device__ __forceinline__ void sweep(T *sm, const Lv &L, int oy, int oo, const 
     const T *kk = sm + L.ok;
     const T *b = sm + L.ob;
     T *out = sm + oo;
-    for (int c = threadIdx.x; c < L.n; c += TT) {
-        const int i = c % L.nx, t = c / L.nx;
-        const int j = t % L.ny, kz = t / L.ny;
-        T Sy = 0, Sk = 0, Sp = 0;
-        const T y0 = y[c];
+    const int W = L.px, WP = L.pxy;
 #pragma unroll
-        for (int dz = -1; dz <= 1; ++dz) {
-            int sz = 1;
-            const int fz = tfold(kz + dz, L.nz, bc[4], bc[5], sz);
-#pragma unroll
-            for (int dy = -1; dy <= 1; ++dy) {
-                int sy = sz;
-                const int fy = tfold(j + dy, L.ny, bc[2], bc[3], sy);
-#pragma unroll
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int nzc = (dx != 0) + (dy != 0) + (dz != 0);
-                    if (nzc < 2) continue;  // centre and faces carry no weight
-                    int s = sy;
-                    const int fx = tfold(i + dx, L.nx, bc[0], bc[1], s);
-                    const int g = fx + L.nx * (fy + L.ny * fz);
-                    const T w = (nzc == 2) ? (T)2 : (T)1;
-                    const T v = (s < 0) ? -y[g] : y[g];
-                    Sy += w * v;
-                    if constexpr (HK) {
-                        const T kv = kk[g];
-                        Sk += w * kv;
-                        Sp += w * kv * v;
-                    }
-                }
-            }
-        }
-        T r;
+    for (int r = 0; r < 2; ++r) {
+        if (pc[r].c < 0) continue;
+        const int c = pc[r].c, q = pc[r].q;
+        const T y0 = y[q];
+        const T Dz = dsum(y, q, W);
+        const T Sy = (Dz + Dz + fma((T)2, xsum(y, q - WP, W), dsum(y, q - WP, W))) +
+                     fma((T)2, xsum(y, q + WP, W), dsum(y, q + WP, W));
+        T v;
         if constexpr (!HK) {
-            r = y0 + om_w0 * (b[c] - cw * (Sy - (T)32 * y0));
+            v = y0 + om_w0 * (b[c] - cw * (Sy - (T)32 * y0));
         } else {
-            const T k0 = kk[c];
-            const T Dg = (T)32 * k0 + Sk;
+            const T Dk = dsum(kk, q, W);
+            const T Sk = (Dk + Dk + fma((T)2, xsum(kk, q - WP, W), dsum(kk, q - WP, W))) +
+                         fma((T)2, xsum(kk, q + WP, W), dsum(kk, q + WP, W));
+            const T Dp = dprod(y, kk, q, W);
+            const T Sp = (Dp + Dp + fma((T)2, xprod(y, kk, q - WP, W), dprod(y, kk, q - WP, W))) +
+                         fma((T)2, xprod(y, kk, q + WP, W), dprod(y, kk, q + WP, W));
+            const T k0 = kk[q];
+            const T Dg = fma((T)32, k0, Sk);
             const T Ays = Dg * y0 - k0 * Sy - Sp;
-            r = y0 + omega * (b[c] * icv - Ays) / Dg;
+            v = y0 + omega * (b[c] * icv - Ays) * trecip(Dg);
         }
-        out[c] = r;
+        out[(int)threadIdx.x + r * TT] = pc[r].sg < 0 ? -v : v;
     }
 }
 
-// y = P e of the coarser level (cell-centred trilinear, coarse halos by the
-// boundary rules), interior cells; both fields in LDS.
+// y = P e of the coarser level at every padded cell of F (cell-centred
+// trilinear; the coarse field is halo-complete, so no folding is needed).
 template <typename T>
-__device__ __forceinline__ void prolong(T *sm, const Lv &F, int oy, const Lv &C, int oe, const int *bc)
+__device__ __forceinline__ void prolong(T *sm, const PCell (&pc)[2], int oy, const Lv &C, int oe)
 {
     const T *ec = sm + oe;
     T *y = sm + oy;
-    const int cx = C.nx, cy = C.ny, cz = C.nz;
-    for (int c = threadIdx.x; c < F.n; c += TT) {
-        const int i = c % F.nx, t = c / F.nx;
-        const int j = t % F.ny, kz = t / F.ny;
-        int I[2], J[2], K[2];
-        int sI[2] = {1, 1}, sJ[2] = {1, 1}, sK[2] = {1, 1};
-        I[0] = tfold(i >> 1, cx, bc[0], bc[1], sI[0]);
-        I[1] = tfold((i >> 1) + ((i & 1) ? 1 : -1), cx, bc[0], bc[1], sI[1]);
-        J[0] = tfold(j >> 1, cy, bc[2], bc[3], sJ[0]);
-        J[1] = tfold((j >> 1) + ((j & 1) ? 1 : -1), cy, bc[2], bc[3], sJ[1]);
-        K[0] = tfold(kz >> 1, cz, bc[4], bc[5], sK[0]);
-        K[1] = tfold((kz >> 1) + ((kz & 1) ? 1 : -1), cz, bc[4], bc[5], sK[1]);
-        const T w[2] = {(T)0.75, (T)0.25};
-        T acc = 0;
+    const int CW = C.px, CP = C.pxy;
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            T pl = 0;
-#pragma unroll
-            for (int b2 = 0; b2 < 2; ++b2) {
-                T row = 0;
-#pragma unroll
-                for (int d = 0; d < 2; ++d) {
-                    const int s = sI[d] * sJ[b2] * sK[a];
-                    const T v = ec[I[d] + cx * (J[b2] + cy * K[a])];
-                    row += w[d] * (s < 0 ? -v : v);
-                }
-                pl += w[b2] * row;
-            }
-            acc += w[a] * pl;
-        }
-        y[c] = acc;
+    for (int r = 0; r < 2; ++r) {
+        if (pc[r].c < 0) continue;
+        const int i = pc[r].i, j = pc[r].j, kz = pc[r].k;
+        const int q = ((kz >> 1) + 1) * CP + ((j >> 1) + 1) * CW + ((i >> 1) + 1);
+        const int dI = (i & 1) ? 1 : -1, dJ = (j & 1) ? CW : -CW, dK = (kz & 1) ? CP : -CP;
+        const T w3 = (T)0.75, wq = (T)0.25;
+        const T z00 = w3 * ec[q] + wq * ec[q + dK];
+        const T z01 = w3 * ec[q + dI] + wq * ec[q + dI + dK];
+        const T z10 = w3 * ec[q + dJ] + wq * ec[q + dJ + dK];
+        const T z11 = w3 * ec[q + dJ + dI] + wq * ec[q + dJ + dI + dK];
+        const T v = w3 * (w3 * z00 + wq * z01) + wq * (w3 * z10 + wq * z11);
+        y[(int)threadIdx.x + r * TT] = pc[r].sg < 0 ? -v : v;
     }
 }
 
@@ -176,10 +225,13 @@ __device__ __forceinline__ void restrict_to(const S *in, int cx, int cy, int cz,
     }
 }
 
+// Padded coefficient cells and coarsest-inverse entries a thread stages with its first loads.
+constexpr int kTailKRegs = 3;
+constexpr int kTailARegs = 4;
+
 template <typename T, typename KT>
 __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
 {
-    if (a.done && *a.done) return;
     constexpr bool HK = !std::is_same<KT, NoK>::value;
     extern __shared__ __align__(16) unsigned char smem[];
     T *sm = (T *)smem;
@@ -187,77 +239,174 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
     __shared__ Lv lv[kTailMaxLevels];
     __shared__ int s_total;
     const int nl = a.levels;
+    // the stopping flag is read with the first loads and tested before any write
+    const int stop = a.done ? *a.done : 0;
     if (threadIdx.x == 0) {
         int off = 0;
 #pragma unroll
         for (int l = 0; l < kTailMaxLevels; ++l) {
             if (l < nl) {
                 const int n = a.nx[l] * a.ny[l] * a.nz[l];
+                const int pn = (a.nx[l] + 2) * (a.ny[l] + 2) * (a.nz[l] + 2);
                 lv[l].nx = a.nx[l];
                 lv[l].ny = a.ny[l];
                 lv[l].nz = a.nz[l];
                 lv[l].n = n;
+                lv[l].px = a.nx[l] + 2;
+                lv[l].pxy = (a.nx[l] + 2) * (a.ny[l] + 2);
+                lv[l].pn = pn;
+                lv[l].rpx = 1.0 / (double)(a.nx[l] + 2);
+                lv[l].rpxy = 1.0 / (double)((a.nx[l] + 2) * (a.ny[l] + 2));
                 lv[l].h = a.h[l];
                 lv[l].ob = off;
                 lv[l].oya = off + n;
-                lv[l].oyb = off + 2 * n;
-                lv[l].ok = HK ? off + 3 * n : 0;
-                off += (HK ? 4 : 3) * n;
+                lv[l].oyb = off + n + pn;
+                off += n + 2 * pn;
             }
         }
-        s_total = off;
+        // the padded coefficients of all levels follow, contiguous as in kpad
+        int ko = off;
+#pragma unroll
+        for (int l = 0; l < kTailMaxLevels; ++l) {
+            if (l < nl) {
+                lv[l].ok = HK ? ko : 0;
+                if (HK) ko += lv[l].pn;
+            }
+        }
+        s_total = ko;
     }
-    __syncthreads();
+
+    // every HBM read up front, all in flight together: the first level's
+    // right-hand side (restricted from the level above if given), the
+    // coefficient of every tail level on its padded cells (the halo by the
+    // +mirror rule) and the coarsest inverse
+    const int n0 = a.nx[0] * a.ny[0] * a.nz[0];
+    T rb = (T)0;
+    if ((int)threadIdx.x < n0) {
+        const int c = threadIdx.x;
+        if (a.b_above) {
+            const int cx = a.nx[0], cy = a.ny[0];
+            const int I = c % cx, t = c / cx;
+            const int J = t % cy, K = t / cy;
+            const int fx = 2 * cx, fy = 2 * cy, sy = fx, sz = fx * fy;
+            const T *in = (const T *)a.b_above;
+            const int g = 2 * I + fx * (2 * J + fy * 2 * K);
+            const T v0 = in[g], v1 = in[g + 1], v2 = in[g + sy], v3 = in[g + sy + 1];
+            const T v4 = in[g + sz], v5 = in[g + sz + 1], v6 = in[g + sz + sy], v7 = in[g + sz + sy + 1];
+            rb = ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7));
+        } else {
+            rb = ((const T *)a.b_first)[c];
+        }
+    }
+    // padded coefficients (contiguous) and the coarsest inverse, first parts in registers
+    int ktot = 0, kbase = 0;
+#pragma unroll
+    for (int l = 0; l < kTailMaxLevels; ++l) {
+        if (l < nl) {
+            kbase += a.nx[l] * a.ny[l] * a.nz[l] + 2 * (a.nx[l] + 2) * (a.ny[l] + 2) * (a.nz[l] + 2);
+            if (HK) ktot += (a.nx[l] + 2) * (a.ny[l] + 2) * (a.nz[l] + 2);
+        }
+    }
+    T kr[HK ? kTailKRegs : 1];
+    if constexpr (HK) {
+#pragma unroll
+        for (int q = 0; q < kTailKRegs; ++q) {
+            const int f = (int)threadIdx.x + q * TT;
+            kr[q] = f < ktot ? ((const T *)a.kpad)[f] : (T)0;
+        }
+    }
+    const int ncl = a.nx[nl - 1] * a.ny[nl - 1] * a.nz[nl - 1];
+    double ar[kTailARegs];
+#pragma unroll
+    for (int q = 0; q < kTailARegs; ++q) {
+        const int f = (int)threadIdx.x + q * TT;
+        ar[q] = (a.ainv_in_lds && f < ncl * ncl) ? a.ainv[f] : 0.0;
+    }
+    if (stop) return;  // uniform over the workgroup
+    __syncthreads();   // level table
+
     const T om = (T)a.omega;
     const Lv &C = lv[nl - 1];
     const int nc = C.n;
     // FP64 inverse in LDS after the fields when it fits (8-byte aligned)
     double *ainv_s = (double *)(smem + (((size_t)s_total * sizeof(T) + 7) & ~(size_t)7));
-
-    // every HBM read up front, all in flight together: the first level's
-    // right-hand side (restricted from the level above if given), the
-    // coefficient of every tail level and the coarsest inverse
-    if (a.b_above)
-        restrict_to<T, T>((const T *)a.b_above, lv[0].nx, lv[0].ny, lv[0].nz, sm + lv[0].ob);
-    else
-        for (int c = threadIdx.x; c < lv[0].n; c += TT) sm[lv[0].ob + c] = ((const T *)a.b_first)[c];
+    if ((int)threadIdx.x < n0) sm[lv[0].ob + threadIdx.x] = rb;
     if constexpr (HK) {
-        for (int l = 0; l < nl; ++l) {
-            const KT *kp = (const KT *)a.k[l];
-            for (int c = threadIdx.x; c < lv[l].n; c += TT) sm[lv[l].ok + c] = kval<T, KT>(kp, c);
+#pragma unroll
+        for (int q = 0; q < kTailKRegs; ++q) {
+            const int f = (int)threadIdx.x + q * TT;
+            if (f < ktot) sm[kbase + f] = kr[q];
         }
+        for (int f = threadIdx.x + kTailKRegs * TT; f < ktot; f += TT) sm[kbase + f] = ((const T *)a.kpad)[f];
     }
-    if (a.ainv_in_lds)
-        for (int c = threadIdx.x; c < nc * nc; c += TT) ainv_s[c] = a.ainv[c];
+    if (a.ainv_in_lds) {
+#pragma unroll
+        for (int q = 0; q < kTailARegs; ++q) {
+            const int f = (int)threadIdx.x + q * TT;
+            if (f < nc * nc) ainv_s[f] = ar[q];
+        }
+        for (int c = threadIdx.x + kTailARegs * TT; c < nc * nc; c += TT) ainv_s[c] = a.ainv[c];
+    }
     __syncthreads();
     for (int l = 0; l + 1 < nl; ++l) {
         restrict_to<T, T>(sm + lv[l].ob, lv[l + 1].nx, lv[l + 1].ny, lv[l + 1].nz, sm + lv[l + 1].ob);
         __syncthreads();
     }
 
-    // coarsest: e = A_c^{-1} b (symmetric inverse), mean removed if singular
+    // coarsest: e = A_c^{-1} b (symmetric inverse), mean removed if singular,
+    // at every padded cell (halo cells from the cell they mirror; at most two
+    // padded cells per thread)
     {
         const T *bc = sm + C.ob;
-        const int i = threadIdx.x;
-        double e = 0.0;
-        if (i < nc) {
-            if (a.ainv_in_lds) {
-                for (int j = 0; j < nc; ++j) e += ainv_s[j * nc + i] * (double)bc[j];
-            } else {
-#pragma unroll 8
-                for (int j = 0; j < nc; ++j) e += a.ainv[(size_t)j * nc + i] * (double)bc[j];
+        double e[2] = {0.0, 0.0};
+        int sg[2] = {1, 1};
+        double part = 0.0;
+        PCell pc[2];
+        padded_cells(C, a.bc, pc);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int p = threadIdx.x + r * TT;
+            if (pc[r].c >= 0) {
+                const int i = pc[r].c;
+                sg[r] = pc[r].sg;
+                // four interleaved partial sums keep the loads in flight
+                double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+                const double *col = a.ainv_in_lds ? (const double *)ainv_s : a.ainv;
+                int j = 0;
+                if (a.ainv_in_lds) {
+                    for (; j + 3 < nc; j += 4) {
+                        acc0 += ainv_s[j * nc + i] * (double)bc[j];
+                        acc1 += ainv_s[(j + 1) * nc + i] * (double)bc[j + 1];
+                        acc2 += ainv_s[(j + 2) * nc + i] * (double)bc[j + 2];
+                        acc3 += ainv_s[(j + 3) * nc + i] * (double)bc[j + 3];
+                    }
+                } else {
+                    for (; j + 3 < nc; j += 4) {
+                        acc0 += col[(size_t)j * nc + i] * (double)bc[j];
+                        acc1 += col[(size_t)(j + 1) * nc + i] * (double)bc[j + 1];
+                        acc2 += col[(size_t)(j + 2) * nc + i] * (double)bc[j + 2];
+                        acc3 += col[(size_t)(j + 3) * nc + i] * (double)bc[j + 3];
+                    }
+                }
+                for (; j < nc; ++j) acc0 += col[(size_t)j * nc + i] * (double)bc[j];
+                e[r] = (acc0 + acc1) + (acc2 + acc3);
+                if (pc[r].q == p) part += e[r];
             }
         }
         if (a.singular) {
-            double part = (i < nc) ? e : 0.0;
             for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off);
             if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
             __syncthreads();
             double sum = 0.0;
             for (int w = 0; w < TT / 64; ++w) sum += red[w];
-            e -= sum / (double)nc;
+            e[0] -= sum / (double)nc;
+            e[1] -= sum / (double)nc;
         }
-        if (i < nc) sm[C.oya + i] = (T)e;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int p = threadIdx.x + r * TT;
+            if (p < C.pn) sm[C.oya + p] = (T)(sg[r] < 0 ? -e[r] : e[r]);
+        }
         __syncthreads();
     }
 
@@ -265,12 +414,14 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
     // buffer that makes the last sweep land in ya
     for (int l = nl - 2; l >= 0; --l) {
         const Lv &V = lv[l];
+        PCell pc[2];
+        padded_cells(V, a.bc, pc);
         int src = (a.nu % 2 == 0) ? V.oya : V.oyb;
-        prolong<T>(sm, V, src, lv[l + 1], lv[l + 1].oya, a.bc);
+        prolong<T>(sm, pc, src, lv[l + 1], lv[l + 1].oya);
         __syncthreads();
         for (int s = 0; s < a.nu; ++s) {
             const int o = (src == V.oya) ? V.oyb : V.oya;
-            sweep<T, HK>(sm, V, src, o, a.bc, om);
+            sweep<T, HK>(sm, V, pc, src, o, om);
             __syncthreads();
             src = o;
         }
@@ -278,16 +429,24 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
 
     // the first tail level's correction back to HBM
     T *e_out = (T *)a.e_first;
-    for (int c = threadIdx.x; c < lv[0].n; c += TT) e_out[c] = sm[lv[0].oya + c];
+    for (int c = threadIdx.x; c < lv[0].n; c += TT) e_out[c] = sm[lv[0].oya + padded_of(lv[0], c)];
 }
 
 }  // namespace
 
-size_t tail_lds_bytes(const TailArgs &a, int t_is_f64, int nodal)
+size_t tail_field_cells(const int *nx, const int *ny, const int *nz, int levels, int nodal)
 {
     size_t n = 0;
-    for (int l = 0; l < a.levels; ++l) n += (size_t)a.nx[l] * a.ny[l] * a.nz[l];
-    size_t b = (nodal ? 4 : 3) * n * (t_is_f64 ? 8 : 4);
+    for (int l = 0; l < levels; ++l) {
+        const size_t pn = (size_t)(nx[l] + 2) * (ny[l] + 2) * (nz[l] + 2);
+        n += (size_t)nx[l] * ny[l] * nz[l] + (nodal ? 3 : 2) * pn;
+    }
+    return n;
+}
+
+size_t tail_lds_bytes(const TailArgs &a, int t_is_f64, int nodal)
+{
+    size_t b = tail_field_cells(a.nx, a.ny, a.nz, a.levels, nodal) * (t_is_f64 ? 8 : 4);
     b = (b + 7) & ~(size_t)7;
     if (a.ainv_in_lds) {
         const int l = a.levels - 1;
@@ -297,9 +456,55 @@ size_t tail_lds_bytes(const TailArgs &a, int t_is_f64, int nodal)
     return b;
 }
 
+namespace {
+
+template <typename T, typename KT>
+__global__ __launch_bounds__(256) void kpad_kernel(const KT *k, int nx, int ny, int nz, Bc6 bc, T *out)
+{
+    const int pn = (nx + 2) * (ny + 2) * (nz + 2);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= pn) return;
+    const int px = nx + 2, pi = p % px, t = p / px;
+    const int pj = t % (ny + 2), pk = t / (ny + 2);
+    int sg = 1;
+    const int i = tfold(pi - 1, nx, bc.v[0], bc.v[1], sg);
+    const int j = tfold(pj - 1, ny, bc.v[2], bc.v[3], sg);
+    const int kk = tfold(pk - 1, nz, bc.v[4], bc.v[5], sg);
+    out[p] = kval<T, KT>(k, i + nx * (j + ny * kk));  // the coefficient's halo is +mirror
+}
+
+}  // namespace
+
+hipError_t launch_tail_kpad(int T_is_f64, int kt, const void *k, int nx, int ny, int nz, const int *bc, void *out,
+                            hipStream_t s)
+{
+    Bc6 b;
+    for (int f = 0; f < 6; ++f) b.v[f] = bc[f];
+    const int pn = (nx + 2) * (ny + 2) * (nz + 2);
+    const dim3 grid((pn + 255) / 256), block(256);
+    if (T_is_f64) {
+        if (kt != KT_F64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((kpad_kernel<double, double>), grid, block, 0, s, (const double *)k, nx, ny, nz, b,
+                           (double *)out);
+    } else if (kt == KT_F32) {
+        hipLaunchKernelGGL((kpad_kernel<float, float>), grid, block, 0, s, (const float *)k, nx, ny, nz, b,
+                           (float *)out);
+    } else if (kt == KT_F16) {
+        hipLaunchKernelGGL((kpad_kernel<float, __half>), grid, block, 0, s, (const __half *)k, nx, ny, nz, b,
+                           (float *)out);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_tail(int T_is_f64, int kt, const TailArgs &a, hipStream_t s)
 {
     if (a.levels < 1 || a.levels > kTailMaxLevels) return hipErrorInvalidValue;
+    if (a.nx[0] * a.ny[0] * a.nz[0] > TT) return hipErrorInvalidValue;
+    for (int l = 0; l < a.levels; ++l)
+        if ((a.nx[l] + 2) * (a.ny[l] + 2) * (a.nz[l] + 2) > 2 * TT) return hipErrorInvalidValue;
+    if (kt != KT_NONE && !a.kpad) return hipErrorInvalidValue;
     const size_t lds = tail_lds_bytes(a, T_is_f64, kt != KT_NONE);
     auto go = [&](auto kernel) -> hipError_t {
         hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
