@@ -10,7 +10,8 @@
 //     K = [-1, 2, -1] / h (stiffness),
 // so each is evaluated separably on a 27-value neighbourhood held in
 // registers.  One thread owns one cell; the neighbourhoods of adjacent threads
-// overlap in L1/L2, which carries the re-reads.  This explicit part moves
+// overlap in L1/L2, which carries the re-reads (the momentum predictor, with
+// twelve fields the heaviest, stages its planes in LDS instead).  This explicit part moves
 // about a kilobyte per cell per step; the three pressure solves, run by the
 // multigrid hierarchy of this library with a fixed cycle count, dominate.
 //
@@ -335,54 +336,143 @@ __global__ __launch_bounds__(256) void pg_velocity_kernel(Grid g, C3 q, C3 adv, 
 // s_c = rho m_l adv_c + f_lap(q_c, k_c) + f(p_hs + p_nh; w_c) - f(s_t,c; w_m)
 // [- f(-g rho; w_m) for c = z] gives q~_c = (-s_c / m_l + rho q^n_c / dt) / (rho / dt),
 // and the next iterate is (q^n + q~) / 2.
-__global__ __launch_bounds__(256) void momentum_kernel(Grid g, Phys P, C3 qn, C3 q, C3 kq, C3 adv,
-                                                       const double *p_hs, const double *p_nh, C3 st,
-                                                       const double *rho, F3 qt, F3 qnext)
+// Its twelve input fields are staged in LDS: one workgroup owns an MT_X x MT_Y
+// column of cells and marches MT_Z planes; each plane of every field is loaded
+// once, with its halo rule (and the lifted bottom halo of p_hs), into a
+// three-plane rotation, and each cell's 27-value neighbourhoods are gathered
+// from LDS in the order load() builds them (the same arithmetic as the
+// per-cell form).  The neighbourhood re-reads that would go through L1/L2
+// (324 loads per cell) become LDS reads.
+constexpr int MT_X = 16, MT_Y = 8, MT_Z = 16;
+constexpr int MP_X = MT_X + 2, MP_N = (MT_X + 2) * (MT_Y + 2);
+constexpr int M_NF = 12;  // p_hs, p_nh, rho, q0..2, kq0..2, st0..2
+
+struct MomIn {
+    const double *u[M_NF];
+};
+
+__device__ inline unsigned mom_rule(int f)
 {
-    cell_of(g, [&](size_t id, int i, int j, int k) {
-        const Filt F(g.h);
-        const double r0 = rho[id];
-        // the pressure gradients and the buoyancy source, each neighbourhood loaded once
-        double ghs[3], gnh[3], buoy;
-        {
-            Nb p;
-            load_phs(p, p_hs, rho, P.g * g.h, g, i, j, k);
-            for (int c = 0; c < 3; ++c) ghs[c] = F.d(p, c);
+    return f <= 1 ? kOddTop : (f == 2 ? kEven : (f <= 5 ? rule_vel(f - 3) : (f <= 8 ? kEven : rule_grad(f - 9))));
+}
+
+__device__ inline void gather(Nb &n, const double *sf, const int (&slot)[3], int li, int lj)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double *pl = sf + slot[c] * MP_N;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) n.v[c * 9 + b * 3 + a] = pl[(lj + b) * MP_X + (li + a)];
+    }
+}
+
+__global__ __launch_bounds__(MT_X * MT_Y) void momentum_lds_kernel(Grid g, Phys P, C3 qn, MomIn in, C3 adv,
+                                                                   F3 qt, F3 qnext)
+{
+    __shared__ double sm[M_NF][3][MP_N];
+    const int tx = (g.nx + MT_X - 1) / MT_X, ty = (g.ny + MT_Y - 1) / MT_Y;
+    const int bx = blockIdx.x % tx, rest = blockIdx.x / tx;
+    const int by = rest % ty, bz = rest / ty;
+    const int i0 = bx * MT_X, j0 = by * MT_Y, z0 = bz * MT_Z;
+    const int z1 = min(z0 + MT_Z, g.nz);
+    const int li = threadIdx.x % MT_X, lj = threadIdx.x / MT_X;
+    const int i = i0 + li, j = j0 + lj;
+    const bool valid = i < g.nx && j < g.ny;
+    const double gh = P.g * g.h;
+
+    // plane z of every field into slot (z + 3) % 3: clamped addresses and the
+    // faces crossed first, then every load in flight, then the signs of each
+    // field's rule (the product over the crossed faces, as tap() forms it)
+    constexpr int NR = (MP_N + MT_X * MT_Y - 1) / (MT_X * MT_Y);
+    auto stage = [&](int z) {
+        const int sl = (z + 3) % 3;
+        const int zc = z < 0 ? 0 : (z >= g.nz ? g.nz - 1 : z);
+        const unsigned zbit = z < 0 ? 16u : (z >= g.nz ? 32u : 0u);
+        size_t off[NR];
+        unsigned bits[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int c = min((int)threadIdx.x + r * MT_X * MT_Y, MP_N - 1);
+            const int py = c / MP_X, px = c - py * MP_X;
+            const int gi = i0 + px - 1, gj = j0 + py - 1;
+            const int ci = gi < 0 ? 0 : (gi >= g.nx ? g.nx - 1 : gi);
+            const int cj = gj < 0 ? 0 : (gj >= g.ny ? g.ny - 1 : gj);
+            bits[r] = zbit | (gi < 0 ? 1u : (gi >= g.nx ? 2u : 0u)) | (gj < 0 ? 4u : (gj >= g.ny ? 8u : 0u));
+            off[r] = at(g, ci, cj, zc);
         }
-        {
-            Nb p;
-            load(p, p_nh, kOddTop, g, i, j, k);
-            for (int c = 0; c < 3; ++c) gnh[c] = F.d(p, c);
-        }
-        {
-            Nb r;
-            load(r, rho, kEven, g, i, j, k);
-            for (int e = 0; e < 27; ++e) r.v[e] *= -P.g;
-            buoy = F.mass(r);
-        }
-        for (int c = 0; c < 3; ++c) {
-            double s;
-            {
-                Nb qv, kv;
-                load(qv, q.p[c], rule_vel(c), g, i, j, k);
-                load(kv, kq.p[c], kEven, g, i, j, k);
-                s = fdiff(F, qv, kv, 3);
+        double v[M_NF][NR];
+#pragma unroll
+        for (int f = 0; f < M_NF; ++f)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) v[f][r] = in.u[f][off[r]];
+#pragma unroll
+        for (int f = 0; f < M_NF; ++f) {
+            const unsigned rule = mom_rule(f);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int c = (int)threadIdx.x + r * MT_X * MT_Y;
+                if (c < MP_N) {
+                    double x = (__popc(bits[r] & rule) & 1) ? -v[f][r] : v[f][r];
+                    if (f == 0 && z == -1) x += gh * v[2][r];  // lifted bottom halo of p_hs (rho +mirror)
+                    sm[f][sl][c] = x;
+                }
             }
-            s += ghs[c];
-            s += gnh[c];
-            {
-                Nb t;
-                load(t, st.p[c], rule_grad(c), g, i, j, k);
-                s -= F.mass(t);
-            }
-            if (c == 2) s -= buoy;
-            s += r0 * F.ml * adv.p[c][id];
-            const double qnc = qn.p[c][id];
-            const double t = (-s / F.ml + r0 * qnc / P.dt) / (r0 / P.dt);
-            qt.p[c][id] = t;
-            qnext.p[c][id] = 0.5 * (qnc + t);
         }
-    });
+    };
+    stage(z0 - 1);
+    stage(z0);
+    for (int k = z0; k < z1; ++k) {
+        stage(k + 1);
+        __syncthreads();
+        const int slot[3] = {(k + 2) % 3, k % 3, (k + 1) % 3};  // planes k - 1, k, k + 1
+        if (valid) {
+            const size_t id = at(g, i, j, k);
+            const Filt F(g.h);
+            const double r0 = in.u[2][id];
+            double ghs[3], gnh[3], buoy;
+            {
+                Nb p;
+                gather(p, &sm[0][0][0], slot, li, lj);
+                for (int c = 0; c < 3; ++c) ghs[c] = F.d(p, c);
+            }
+            {
+                Nb p;
+                gather(p, &sm[1][0][0], slot, li, lj);
+                for (int c = 0; c < 3; ++c) gnh[c] = F.d(p, c);
+            }
+            {
+                Nb r;
+                gather(r, &sm[2][0][0], slot, li, lj);
+                for (int e = 0; e < 27; ++e) r.v[e] *= -P.g;
+                buoy = F.mass(r);
+            }
+            for (int c = 0; c < 3; ++c) {
+                double s;
+                {
+                    Nb qv, kv;
+                    gather(qv, &sm[3 + c][0][0], slot, li, lj);
+                    gather(kv, &sm[6 + c][0][0], slot, li, lj);
+                    s = fdiff(F, qv, kv, 3);
+                }
+                s += ghs[c];
+                s += gnh[c];
+                {
+                    Nb t;
+                    gather(t, &sm[9 + c][0][0], slot, li, lj);
+                    s -= F.mass(t);
+                }
+                if (c == 2) s -= buoy;
+                s += r0 * F.ml * adv.p[c][id];
+                const double qnc = qn.p[c][id];
+                const double t = (-s / F.ml + r0 * qnc / P.dt) / (r0 / P.dt);
+                qt.p[c][id] = t;
+                qnext.p[c][id] = 0.5 * (qnc + t);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // Right-hand side of Eq. ph_disc2 for the pressure increment:
@@ -525,6 +615,10 @@ int hip_fail(hipError_t e, const char *what)
     } while (0)
 
 dim3 cells_grid(const Grid &g) { return dim3((unsigned)((g.n + 255) / 256)); }
+dim3 mom_grid(const Grid &g)
+{
+    return dim3((unsigned)(((g.nx + MT_X - 1) / MT_X) * ((g.ny + MT_Y - 1) / MT_Y) * ((g.nz + MT_Z - 1) / MT_Z)));
+}
 
 // Fixed-cycle solve of A x = b on the pressure hierarchy; the work pair
 // (b, px) is the same for every solve, so a captured cycle stays valid.
@@ -684,9 +778,19 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
         hipLaunchKernelGGL(advection_kernel, grid, blk, 0, s, g, c3(cur), f3(S->adv));
         hipLaunchKernelGGL(pg_velocity_kernel, grid, blk, 0, s, g, c3(cur), c3(S->adv), (const double *)S->rho,
                            (const double *)S->mu, f3(S->kq));
-        hipLaunchKernelGGL(momentum_kernel, grid, blk, 0, s, g, P, c3(q), c3(cur), c3(S->kq), c3(S->adv),
-                           (const double *)p_hs, (const double *)p_nh, c3(S->st), (const double *)S->rho,
-                           f3(S->qt), f3(nxt));
+        {
+            MomIn in;
+            in.u[0] = p_hs;
+            in.u[1] = p_nh;
+            in.u[2] = S->rho;
+            for (int c = 0; c < 3; ++c) {
+                in.u[3 + c] = cur[c];
+                in.u[6 + c] = S->kq[c];
+                in.u[9 + c] = S->st[c];
+            }
+            hipLaunchKernelGGL(momentum_lds_kernel, mom_grid(g), dim3(MT_X * MT_Y), 0, s, g, P, c3(q), in,
+                               c3(S->adv), f3(S->qt), f3(nxt));
+        }
         double **t = cur;
         cur = nxt;
         nxt = t;
