@@ -92,6 +92,11 @@ VC_CASES = [
     ((8, 8, 8), (D,) * 6, False),
     ((6, 10, 4), (N, D, N, N, D, N), True),
     ((64, 32, 48), (P, P, D, N, P, P), True),
+    # coarsest 4 x 8 x 16: its halo-padded region (1080 cells) exceeds the coarse-end workgroup
+    ((32, 64, 128), (N, N, N, N, N, D), True),
+    ((32, 64, 128), (D, N, P, P, N, N), False),
+    # a five-level chain ending at 3 x 6 x 3 (odd coarsest dims, three coarse-end levels)
+    ((48, 96, 48), (N,) * 6, True),
 ]
 
 
