@@ -101,18 +101,6 @@ __device__ inline void load(Nb &n, const double *u, unsigned odd, const Grid &g,
             for (int a = 0; a < 3; ++a) n.v[c * 9 + b * 3 + a] = tap(u, odd, g, i + a - 1, j + b - 1, k + c - 1);
 }
 
-// p_hs with its bottom halo p(-1) = p(0) + g h rho(0) (rho +mirror elsewhere).
-__device__ inline void load_phs(Nb &n, const double *p, const double *rho, double gh, const Grid &g, int i, int j,
-                                int k)
-{
-    load(n, p, kOddTop, g, i, j, k);
-    if (k == 0)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) n.v[b * 3 + a] += gh * tap(rho, kEven, g, i + a - 1, j + b - 1, 0);
-}
-
 struct V3 {
     double m, z, p;  // weights at offsets -1, 0, +1
 };
