@@ -55,7 +55,8 @@ struct Level {
 
 // Default launch shape of a level: the tile width that pads the x-y plane
 // least (ties: the wider tile, for longer coalesced rows), and the longest
-// z-chunk that still gives >= 1024 workgroups.
+// z-chunk that still gives >= 1024 workgroups.  (Used for the single-sweep
+// classes; the shapes below are what the autotuner picks on large levels.)
 TileShape default_tiles(int nx, int ny, int nz)
 {
     int best_tx = 64;
@@ -71,6 +72,31 @@ TileShape default_tiles(int nx, int ny, int nz)
     int zc = kDefaultZc;
     while (zc > 2 && (double)nx * ny * nz / (512.0 * zc) < 1024.0) zc /= 2;
     return make_tiles(nx, ny, nz, zc, best_tx);
+}
+
+// Longest z-chunk (power of two, at most 64) that keeps >= 512 workgroups
+// (two per compute unit) for a tile of tx x ty cells.
+int zchunk_for(int nx, int ny, int nz, int tx, int ty)
+{
+    const long tiles = (long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
+    int zc = 64;
+    while (zc > 2 && tiles * ((nz + zc - 1) / zc) < 512) zc /= 2;
+    return zc;
+}
+
+// Default shape per kernel class: the residual in 64-wide tiles of 2 rows per
+// thread; with the two-sweep pass (nu_post == 2) the first-sweep class in
+// 32-wide tiles, 2 rows per thread in FP64 and 1 with FP32 smoothing (the FP64
+// run state of 64-wide tiles leaves one wave per SIMD).
+TileShape default_tiles_for(int nx, int ny, int nz, int kclass, bool mixed, bool fused)
+{
+    if (kclass == NN4MG_KCLASS_FINE_RESID && nx >= 64)
+        return make_tiles(nx, ny, nz, zchunk_for(nx, ny, nz, 64, 8), 64, 2);
+    if (kclass == NN4MG_KCLASS_FINE_SWEEP_PROLONG && fused && nx >= 32) {
+        const int ry = mixed ? 1 : 2;
+        return make_tiles(nx, ny, nz, zchunk_for(nx, ny, nz, 32, 8 * ry), 32, ry);
+    }
+    return default_tiles(nx, ny, nz);
 }
 
 int count_levels(int nx, int ny, int nz, int min_coarse)
@@ -814,7 +840,8 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
         V.nz = cfg->nz >> l;
         V.h = cfg->h * (double)(1 << l);
         V.n = (size_t)V.nx * V.ny * V.nz;
-        for (int c = 0; c < 3; ++c) V.tiles[c] = default_tiles(V.nx, V.ny, V.nz);
+        for (int c = 0; c < 3; ++c)
+            V.tiles[c] = default_tiles_for(V.nx, V.ny, V.nz, c, H->mixed, cfg->nu_post == 2 && H->L >= 2);
         if (V.tiles[0].blocks() > maxblk) maxblk = V.tiles[0].blocks();
         if (nodal) TRY(dalloc(H, &V.k, V.n));
         const bool single = (H->L == 1);

@@ -730,6 +730,17 @@ int nn4mg_step_create(int nx, int ny, int nz, double h, const nn4mg_step_params 
             nn4mg_step_destroy(S);
             return hip_fail(e, "hipEventCreate");
         }
+    // launch shapes of the pressure hierarchy, tuned once for this grid on the
+    // stepper's own (zeroed) solve pair; every solve of the stepper uses them
+    if ((e = launch_fill(S->b, n, 0.0, (hipStream_t)hip_stream)) != hipSuccess ||
+        (e = launch_fill(S->px, n, 0.0, (hipStream_t)hip_stream)) != hipSuccess) {
+        nn4mg_step_destroy(S);
+        return hip_fail(e, "fill");
+    }
+    if ((rc = nn4mg_autotune(S->P, S->b, S->px, nullptr, 0))) {
+        nn4mg_step_destroy(S);
+        return rc;
+    }
     *out = S;
     return NN4MG_OK;
 }
