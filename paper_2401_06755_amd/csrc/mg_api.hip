@@ -680,11 +680,16 @@ int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, doub
     int rc;
     if (H->tail > 0) {
         const int T = H->tail;
-        for (int l = 1; l + 1 < T; ++l) {
+        // right-hand sides of levels 2 .. T - 1, up to three levels per launch
+        for (int l = 1; l + 1 < T; l += 3) {
+            const int depth = std::min(3, T - 1 - l);
             Level &V = H->lv[l];
-            HIP_TRY(launch_restrict(f64 ? 1 : 0, f64 ? (void *)V.b : (void *)V.b32,
-                                    f64 ? (void *)H->lv[l + 1].b : (void *)H->lv[l + 1].b32, V.nx, V.ny, V.nz, done,
-                                    s));
+            auto bof = [&](int m) -> void * {
+                if (m > l + depth) return nullptr;
+                return f64 ? (void *)H->lv[m].b : (void *)H->lv[m].b32;
+            };
+            HIP_TRY(launch_restrict_chain(f64 ? 1 : 0, f64 ? (void *)V.b : (void *)V.b32, bof(l + 1), bof(l + 2),
+                                          bof(l + 3), V.nx, V.ny, V.nz, depth, done, s));
         }
         TailArgs ta;
         std::memset(&ta, 0, sizeof(ta));

@@ -93,6 +93,9 @@ struct SolveState {
 hipError_t launch_stencil(int T_is_f64, int kt, int in_mode, int out_mode, int out_f32, const StencilArgs &a,
                           hipStream_t s);
 
+// depth (1..3) successive restrictions from the level of dims nx x ny x nz into c1, c2, c3 (one launch).
+hipError_t launch_restrict_chain(int T_is_f64, const void *fine, void *c1, void *c2, void *c3, int nx, int ny, int nz,
+                                 int depth, const int *done, hipStream_t s);
 hipError_t launch_restrict(int T_is_f64, const void *fine, void *coarse, int nx, int ny, int nz, const int *done,
                            hipStream_t s);
 hipError_t launch_coarsen_k(const double *kf, double *kc, int nx, int ny, int nz, int harmonic, hipStream_t s);

@@ -26,6 +26,63 @@ __global__ __launch_bounds__(256) void restrict_kernel(const T *f, T *c, int nx,
     }
 }
 
+// Up to three successive restrictions (sum of the 8 children) in one launch:
+// each workgroup owns a 16^3 block of the input level and writes the 8^3, 4^3
+// and 2^3 blocks of the next levels under it.  A coarse cell depends only on
+// its own children, so no workgroup waits for another.  Sums in the order of
+// restrict_kernel (x pairs, then y, then z), so the results are the same.
+template <typename T>
+__global__ __launch_bounds__(512) void restrict_chain_kernel(const T *f, T *c1, T *c2, T *c3, int nx, int ny, int nz,
+                                                             int depth, const int *done)
+{
+    if (done && *done) return;
+    __shared__ T s1[512];  // the 8^3 block of the first coarse level
+    __shared__ T s2[64];   // the 4^3 block of the second
+    const int bxn = (nx + 15) / 16, byn = (ny + 15) / 16;
+    const int bx = blockIdx.x % bxn, rest = blockIdx.x / bxn;
+    const int by = rest % byn, bz = rest / byn;
+    const int t = threadIdx.x;
+    const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
+    {
+        const int I = bx * 8 + (t & 7), J = by * 8 + ((t >> 3) & 7), K = bz * 8 + (t >> 6);
+        T v = (T)0;
+        if (I < cx && J < cy && K < cz) {
+            const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+            const size_t g = 2 * (size_t)I + sy * 2 * (size_t)J + sz * 2 * (size_t)K;
+            v = ((f[g] + f[g + 1]) + (f[g + sy] + f[g + sy + 1])) +
+                ((f[g + sz] + f[g + sz + 1]) + (f[g + sz + sy] + f[g + sz + sy + 1]));
+            c1[(size_t)I + (size_t)cx * ((size_t)J + (size_t)cy * (size_t)K)] = v;
+        }
+        s1[t] = v;
+    }
+    if (depth < 2) return;  // uniform
+    __syncthreads();
+    const int dx = cx >> 1, dy = cy >> 1, dz = cz >> 1;
+    if (t < 64) {
+        const int mi = t & 3, mj = (t >> 2) & 3, mk = t >> 4;
+        const int I = bx * 4 + mi, J = by * 4 + mj, K = bz * 4 + mk;
+        T v = (T)0;
+        if (I < dx && J < dy && K < dz) {
+            const int o = 2 * mi + 16 * mj + 128 * mk;
+            v = ((s1[o] + s1[o + 1]) + (s1[o + 8] + s1[o + 9])) + ((s1[o + 64] + s1[o + 65]) + (s1[o + 72] + s1[o + 73]));
+            c2[(size_t)I + (size_t)dx * ((size_t)J + (size_t)dy * (size_t)K)] = v;
+        }
+        s2[t] = v;
+    }
+    if (depth < 3) return;
+    __syncthreads();
+    const int ex = dx >> 1, ey = dy >> 1, ez = dz >> 1;
+    if (t < 8) {
+        const int ni = t & 1, nj = (t >> 1) & 1, nk = t >> 2;
+        const int I = bx * 2 + ni, J = by * 2 + nj, K = bz * 2 + nk;
+        if (I < ex && J < ey && K < ez) {
+            const int o = 2 * ni + 8 * nj + 32 * nk;
+            c3[(size_t)I + (size_t)ex * ((size_t)J + (size_t)ey * (size_t)K)] =
+                ((s2[o] + s2[o + 1]) + (s2[o + 4] + s2[o + 5])) + ((s2[o + 16] + s2[o + 17]) + (s2[o + 20] + s2[o + 21]));
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void coarsen_k_kernel(const double *f, double *c, int nx, int ny, int nz,
                                                         int harmonic)
 {
@@ -242,6 +299,20 @@ hipError_t launch_restrict(int T_is_f64, const void *fine, void *coarse, int nx,
     else
         hipLaunchKernelGGL(restrict_kernel<float>, dim3(stream_blocks(nc)), dim3(256), 0, s, (const float *)fine,
                            (float *)coarse, nx, ny, nz, done);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_chain(int T_is_f64, const void *fine, void *c1, void *c2, void *c3, int nx, int ny, int nz,
+                                 int depth, const int *done, hipStream_t s)
+{
+    if (depth < 1 || depth > 3) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(((nx + 15) / 16) * ((ny + 15) / 16) * ((nz + 15) / 16)));
+    if (T_is_f64)
+        hipLaunchKernelGGL(restrict_chain_kernel<double>, grid, dim3(512), 0, s, (const double *)fine, (double *)c1,
+                           (double *)c2, (double *)c3, nx, ny, nz, depth, done);
+    else
+        hipLaunchKernelGGL(restrict_chain_kernel<float>, grid, dim3(512), 0, s, (const float *)fine, (float *)c1,
+                           (float *)c2, (float *)c3, nx, ny, nz, depth, done);
     return hipGetLastError();
 }
 
