@@ -119,6 +119,28 @@ def test_one_vcycle_matches_oracle(mg, shape, bc, var):
     assert np.max(np.abs(got - want)) <= 1e-12 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("shape,bc", [((48, 48, 48), (N,) * 6), ((64, 32, 48), (P, P, D, N, P, P)),
+                                      ((40, 12, 24), (N, N, D, N, N, N))])
+def test_harmonic_coarsening_one_vcycle_matches_oracle(mg, shape, bc):
+    """Coarse coefficients by the harmonic mean of the 8 children (the option
+    of the coarsening), one cycle against the oracle's."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(23)
+    x0 = rng.standard_normal((nz, ny, nx))
+    b = rng.standard_normal((nz, ny, nx))
+    if all(v != D for v in bc):
+        b -= b.mean()
+    k = rand_k((nz, ny, nx), 24)
+    h = 1.0 / nx
+    H = make(mg, shape, h, bc, k, coarse_avg=1)
+    OH = oracle.Hierarchy(shape, h, bc, k=k, harmonic=True)
+    xd = dev(x0)
+    H.vcycle(dev(b), xd)
+    got = host(xd, x0.shape)
+    want = OH.vcycle(x0, b)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.abs(want).max()
+
+
 @pytest.mark.parametrize("shape,bc,var,cycles", [
     ((64, 64, 64), (D,) * 6, False, 20),
     ((80, 24, 40), (N, N, N, N, N, D), True, 20),
