@@ -141,6 +141,29 @@ def test_harmonic_coarsening_one_vcycle_matches_oracle(mg, shape, bc):
     assert np.max(np.abs(got - want)) <= 1e-12 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("omega,min_coarse", [(0.8, 4), (0.5, 8), (2.0 / 3.0, 8)])
+@pytest.mark.parametrize("var", [False, True])
+def test_other_weights_and_coarsest_sizes_one_vcycle(mg, omega, min_coarse, var):
+    """A Jacobi weight other than 2/3 (it enters the two-sweep, block and
+    coarse-end kernels) and a larger coarsest level (fewer levels, another
+    coarse-end split), one cycle against the oracle's."""
+    shape, bc = (32, 32, 32), (N, N, D, N, P, P)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(29)
+    x0 = rng.standard_normal((nz, ny, nx))
+    b = rng.standard_normal((nz, ny, nx))
+    k = rand_k((nz, ny, nx), 30) if var else None
+    h = 1.0 / nx
+    H = make(mg, shape, h, bc, k, omega=omega, min_coarse=min_coarse)
+    OH = oracle.Hierarchy(shape, h, bc, k=k, omega=omega, min_coarse=min_coarse)
+    assert len(H.levels()) == OH.levels
+    xd = dev(x0)
+    H.vcycle(dev(b), xd)
+    got = host(xd, x0.shape)
+    want = OH.vcycle(x0, b)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.abs(want).max()
+
+
 @pytest.mark.parametrize("shape,bc,var,cycles", [
     ((64, 64, 64), (D,) * 6, False, 20),
     ((80, 24, 40), (N, N, N, N, N, D), True, 20),
