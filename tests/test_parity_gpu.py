@@ -164,6 +164,34 @@ def test_other_weights_and_coarsest_sizes_one_vcycle(mg, omega, min_coarse, var)
     assert np.max(np.abs(got - want)) <= 1e-12 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_update_coef_equals_fresh_setup(mg, precision):
+    """nn4mg_update_coef rebuilds everything derived from k (coarse levels,
+    smoothing copies, the padded coarse-end copy, the coarsest inverse): a
+    hierarchy built with k1 and updated to k2 runs the same cycle, bit for bit,
+    as one built with k2, and (FP64) matches the oracle's cycle with k2."""
+    shape, bc = (48, 48, 48), (N, N, N, N, N, D)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(41)
+    x0 = rng.standard_normal((nz, ny, nx))
+    b = rng.standard_normal((nz, ny, nx))
+    k1, k2 = rand_k((nz, ny, nx), 42), rand_k((nz, ny, nx), 43)
+    h = 1.0 / nx
+    Hu = make(mg, shape, h, bc, k1, precision=precision)
+    Hu.update_coef(dev(k2))
+    Hf = make(mg, shape, h, bc, k2, precision=precision)
+    outs = []
+    for H in (Hu, Hf):
+        xd = dev(x0)
+        H.vcycle(dev(b), xd)
+        outs.append(host(xd, x0.shape))
+        H.close()
+    assert np.array_equal(outs[0], outs[1])
+    if precision == 0:
+        want = oracle.Hierarchy(shape, h, bc, k=k2).vcycle(x0, b)
+        assert np.max(np.abs(outs[0] - want)) <= 1e-12 * np.abs(want).max()
+
+
 @pytest.mark.parametrize("shape,bc,var,cycles", [
     ((64, 64, 64), (D,) * 6, False, 20),
     ((80, 24, 40), (N, N, N, N, N, D), True, 20),
