@@ -7,7 +7,16 @@ checked by the oracle's FP64 residual of the returned x over the whole field.
 The bar is the solve tolerance itself: ||b - A x||_2 <= 1e-8 ||b||_2 with A the
 oracle's FP64 operator (Eq. k-T), with 5% slack for the different summation
 order of the two residual evaluations.
+
+At the same sizes and tiles, one V-cycle from a random iterate and the residual
+kernel are also compared element by element with the oracle (its cycle takes a
+few seconds on the host at these sizes): FP64 to 1e-12 of the largest entry
+(residual 1e-13), as the small-size parity tests; the mixed forms on the
+correction x - x0 to the bars of the mixed-precision tests (2e-5 with FP32
+smoothing, 2e-2 with the FP16-stored coefficient).
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -69,3 +78,58 @@ def test_rising_bubble_256x256x512_fp16_coefficient(mg):
     info, x = run(mg, work, 2)
     assert info.status == 0 and info.relres <= 1e-8
     assert oracle_relres(work, x) <= 1.05e-8
+
+
+WORKLOADS = {
+    "dense_sphere_256": lambda: inputs.dense_sphere(256, seed=2),
+    "rising_bubble_256x256x512": lambda: inputs.rising_bubble(256, seed=5),
+}
+
+
+@functools.lru_cache(maxsize=1)
+def cycle_case(name):
+    """Workload, a seeded random iterate, the zero-mean right-hand side where no
+    face is Dirichlet, and the oracle's cycle and residual from that iterate."""
+    work = WORKLOADS[name]()
+    x0 = np.random.default_rng(41).standard_normal(work["b"].shape)
+    b = work["b"]
+    if all(v != 0 for v in work["bc"]):
+        b = b - b.mean()
+    want = oracle.Hierarchy(work["shape"], work["h"], work["bc"], k=work["k"]).vcycle(x0, b)
+    res = oracle.residual(b, x0, work["h"], work["bc"], work["k"])
+    return work, x0, b, want, res
+
+
+@pytest.mark.parametrize("name,precision,tol", [
+    ("dense_sphere_256", 0, 1e-12),
+    ("dense_sphere_256", 1, 2e-5),
+    ("rising_bubble_256x256x512", 0, 1e-12),
+    ("rising_bubble_256x256x512", 2, 2e-2),
+])
+def test_full_size_one_cycle_and_residual_elementwise(mg, name, precision, tol):
+    import torch
+
+    work, x0, b, want, res = cycle_case(name)
+    nx, ny, nz = work["shape"]
+    cfg = mg.config_default(nx, ny, nz, work["h"], bc=work["bc"], coef_mode=1, precision=precision)
+    kd = torch.from_numpy(work["k"].reshape(-1)).cuda()
+    bd = torch.from_numpy(np.ascontiguousarray(b).reshape(-1)).cuda()
+    H = mg.Hierarchy(cfg, kd)
+    xd = torch.zeros_like(bd)
+    H.autotune(bd, xd)
+    x0d = torch.from_numpy(x0.reshape(-1)).cuda()
+    if precision == 0:
+        r = torch.empty_like(bd)
+        nrm = H.residual(x0d, bd, r)
+        got_r = r.cpu().numpy().reshape(res.shape)
+        assert np.max(np.abs(got_r - res)) <= 1e-13 * np.abs(res).max()
+        assert abs(nrm - np.linalg.norm(res)) <= 1e-12 * np.linalg.norm(res)
+    xd.copy_(x0d)
+    H.vcycle(bd, xd)
+    got = xd.cpu().numpy().reshape(x0.shape)
+    H.close()
+    if precision == 0:
+        assert np.max(np.abs(got - want)) <= tol * np.abs(want).max()
+    else:
+        corr = want - x0
+        assert np.max(np.abs((got - x0) - corr)) <= tol * np.abs(corr).max()
