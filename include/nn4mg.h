@@ -156,8 +156,9 @@ size_t nn4mg_bytes_held(nn4mg_t h);
  * enable = 1 resets and starts recording, 0 stops.  Recording is capped at
  * 4096 launches per class. */
 enum { NN4MG_KCLASS_FINE_RESID = 0,        /* residual + restriction + norm partials */
-       NN4MG_KCLASS_FINE_SWEEP_PROLONG = 1, /* first sweep, reads x + P e_1 */
-       NN4MG_KCLASS_FINE_SWEEP = 2,         /* later sweeps */
+       NN4MG_KCLASS_FINE_SWEEP_PROLONG = 1, /* first sweep after the prolongation, reads P e of the level
+                                               below; with nu_post == 2 both sweeps run in this one pass */
+       NN4MG_KCLASS_FINE_SWEEP = 2,         /* later sweeps (nu_post != 2 only) */
        NN4MG_KCLASS_COUNT = 3 };
 int nn4mg_profile(nn4mg_t h, int enable);
 /* Launch count and summed duration (ms) of one class at the finest level
