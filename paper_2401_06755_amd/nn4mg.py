@@ -315,7 +315,11 @@ class Server:
         kp = _field(k, n, "k") if k is not None else None
         _check(lib().nn4mg_server_submit(self._h, ctypes.byref(cfg), kp, _field(b, n, "b"), _field(x, n, "x"),
                                          float(rtol), int(max_cycles), int(tag)))
-        self._keep[int(tag)] = (cfg, b, x, k)
+        # tags need not be unique: per tag, the count of requests in flight and
+        # the tensors of all of them
+        held = self._keep.setdefault(int(tag), [0, []])
+        held[0] += 1
+        held[1].append((cfg, b, x, k))
 
     def poll(self, cap: int = 256):
         out = (Result * cap)()
@@ -323,7 +327,14 @@ class Server:
         _check(lib().nn4mg_server_poll(self._h, out, cap, ctypes.byref(nd)))
         res = [out[i] for i in range(nd.value)]
         for r in res:
-            self._keep.pop(int(r.tag), None)
+            tag = int(r.tag)
+            held = self._keep.get(tag)
+            if held is not None:
+                # a result names only its tag, so the tensors of a tag are
+                # released together once every request with that tag is done
+                held[0] -= 1
+                if held[0] <= 0:
+                    del self._keep[tag]
         return res
 
     def drain(self, timeout_ms: float = -1.0):

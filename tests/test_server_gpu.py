@@ -97,3 +97,39 @@ def test_oversize_request_rejected(mg):
     with pytest.raises(mg.Nn4mgError):
         srv.submit(cfg, b, x, tag=1)
     srv.close()
+
+
+def test_shared_tag_keeps_every_request_alive(mg):
+    """Tags need not be unique.  The binding keeps each request's tensors alive
+    until every request with its tag has finished, although the caller drops
+    its own references to b and k right after submitting: blocks freed too
+    early would be handed to the filler tensors allocated below and overwritten
+    while the solves still read them."""
+    import torch
+
+    srv = mg.Server(8 << 30, 4)
+    works, xs = [], []
+    for i in range(3):
+        w = inputs.served_request(i, base_seed=4100, edges=(48,))
+        n = w["edge"]
+        cfg = mg.config_default(n, n, n, w["h"], bc=w["bc"], coef_mode=1, precision=1)
+        b = torch.from_numpy(w["b"].reshape(-1)).cuda()
+        k = torch.from_numpy(w["k"].reshape(-1)).cuda()
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        srv.submit(cfg, b, x, k=k, rtol=1e-8, max_cycles=2000, tag=5)
+        del b, k
+        works.append(w)
+        xs.append(x)
+    filler = [torch.full((48 ** 3,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(8)]
+    srv.drain()
+    res = srv.poll()
+    assert len(res) == 3 and all(r.tag == 5 and r.info.status == 0 for r in res)
+    assert 5 not in srv._keep
+    srv.close()
+    del filler
+    for w, xd in zip(works, xs):
+        x = xd.cpu().numpy().reshape(w["b"].shape)
+        bb = w["b"] - w["b"].mean()
+        r = bb - oracle.apply(x, w["h"], w["bc"], w["k"])
+        assert np.linalg.norm(r) <= 1.05e-8 * np.linalg.norm(bb)
