@@ -139,8 +139,8 @@ int acquire_resident(nn4mg_server *S, Slot &sl, int *err)
         Resident &R = S->residents[i];
         if (!R.busy && same_config(R.cfg, q.cfg)) {
             R.busy = true;
-            if ((*err = hier_set_stream(R.H, sl.stream))) return -2;
-            if (q.cfg.coef_mode == NN4MG_COEF_NODAL && (*err = nn4mg_update_coef(R.H, q.k))) {
+            if ((*err = hier_set_stream(R.H, sl.stream)) ||
+                (q.cfg.coef_mode == NN4MG_COEF_NODAL && (*err = nn4mg_update_coef(R.H, q.k)))) {
                 R.busy = false;
                 return -2;
             }
@@ -262,14 +262,15 @@ extern "C" {
 
 int nn4mg_server_create(size_t budget, int max_slots, nn4mg_srv_t *out)
 {
-    if (!out || max_slots < 1 || max_slots > 64 || budget == 0) return NN4MG_EINVAL;
+    if (!out || max_slots < 1 || max_slots > 64 || budget == 0)
+        return set_error(NN4MG_EINVAL, "server: NULL out, zero budget, or max_slots outside 1..64");
     *out = nullptr;
     nn4mg_server *S = new nn4mg_server();
     S->budget = budget;
     S->t0 = std::chrono::steady_clock::now();
     if (hipGetDevice(&S->device) != hipSuccess) {
         delete S;
-        return NN4MG_EDEVICE;
+        return set_error(NN4MG_EDEVICE, "server: hipGetDevice failed");
     }
     S->slots.resize(max_slots);
     for (Slot &sl : S->slots) {
@@ -281,7 +282,7 @@ int nn4mg_server_create(size_t budget, int max_slots, nn4mg_srv_t *out)
                 if (t.ev) (void)hipEventDestroy(t.ev);
             }
             delete S;
-            return NN4MG_EDEVICE;
+            return set_error(NN4MG_EDEVICE, "server: creating a slot stream or event failed");
         }
     }
     S->worker = std::thread(worker_main, S);
@@ -292,11 +293,12 @@ int nn4mg_server_create(size_t budget, int max_slots, nn4mg_srv_t *out)
 int nn4mg_server_submit(nn4mg_srv_t S, const nn4mg_config *cfg, const double *k, const double *b, double *x,
                         double rtol, int max_cycles, unsigned long long tag)
 {
-    if (!S || !cfg || !b || !x || max_cycles < 0 || !(rtol >= 0.0)) return NN4MG_EINVAL;
-    if (cfg->coef_mode == NN4MG_COEF_NODAL && !k) return NN4MG_EINVAL;
+    if (!S || !cfg || !b || !x || max_cycles < 0 || !(rtol >= 0.0))
+        return set_error(NN4MG_EINVAL, "server submit: NULL argument, max_cycles < 0 or rtol < 0");
+    if (cfg->coef_mode == NN4MG_COEF_NODAL && !k) return set_error(NN4MG_EINVAL, "server submit: NULL k for NODAL");
     const size_t need = nn4mg_bytes_required(cfg);
-    if (need == 0) return NN4MG_EINVAL;
-    if (request_bytes(*cfg) > S->budget) return NN4MG_EBUSY;
+    if (need == 0) return set_error(NN4MG_EINVAL, "server submit: invalid configuration");
+    if (request_bytes(*cfg) > S->budget) return set_error(NN4MG_EBUSY, "server submit: request exceeds the whole budget");
     Request q;
     q.tag = tag;
     q.cfg = *cfg;
@@ -308,7 +310,7 @@ int nn4mg_server_submit(nn4mg_srv_t S, const nn4mg_config *cfg, const double *k,
     q.n = (size_t)cfg->nx * cfg->ny * cfg->nz;
     {
         std::lock_guard<std::mutex> lk(S->mu);
-        if (S->stop.load()) return NN4MG_EINVAL;
+        if (S->stop.load()) return set_error(NN4MG_EINVAL, "server submit: server is stopping");
         q.t_submit = S->now_ms();
         S->queue.push_back(q);
         S->outstanding++;
@@ -318,7 +320,7 @@ int nn4mg_server_submit(nn4mg_srv_t S, const nn4mg_config *cfg, const double *k,
 
 int nn4mg_server_poll(nn4mg_srv_t S, nn4mg_result *out, int cap, int *n_done)
 {
-    if (!S || (!out && cap > 0)) return NN4MG_EINVAL;
+    if (!S || (!out && cap > 0)) return set_error(NN4MG_EINVAL, "server poll: NULL argument");
     std::lock_guard<std::mutex> lk(S->mu);
     int n = 0;
     while (n < cap && !S->results.empty()) {
@@ -331,20 +333,20 @@ int nn4mg_server_poll(nn4mg_srv_t S, nn4mg_result *out, int cap, int *n_done)
 
 int nn4mg_server_drain(nn4mg_srv_t S, double timeout_ms)
 {
-    if (!S) return NN4MG_EINVAL;
+    if (!S) return set_error(NN4MG_EINVAL, "server: NULL handle");
     std::unique_lock<std::mutex> lk(S->mu);
     auto pred = [&] { return S->outstanding == 0; };
     if (timeout_ms < 0) {
         S->cv.wait(lk, pred);
         return NN4MG_OK;
     }
-    return S->cv.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), pred) ? NN4MG_OK
-                                                                                           : NN4MG_EBUSY;
+    if (S->cv.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), pred)) return NN4MG_OK;
+    return set_error(NN4MG_EBUSY, "server drain: timed out with requests outstanding");
 }
 
 int nn4mg_server_stats(nn4mg_srv_t S, size_t *in_use, size_t *peak, int *active, int *queued)
 {
-    if (!S) return NN4MG_EINVAL;
+    if (!S) return set_error(NN4MG_EINVAL, "server: NULL handle");
     std::lock_guard<std::mutex> lk(S->mu);
     if (in_use) *in_use = S->in_use;
     if (peak) *peak = S->peak;

@@ -94,8 +94,10 @@ def test_oversize_request_rejected(mg):
     cfg = mg.config_default(64, 64, 64, 1 / 64)
     b = torch.zeros(64 ** 3, dtype=torch.float64, device="cuda")
     x = torch.zeros_like(b)
-    with pytest.raises(mg.Nn4mgError):
+    with pytest.raises(mg.Nn4mgError, match="budget"):
         srv.submit(cfg, b, x, tag=1)
+    with pytest.raises(mg.Nn4mgError, match="rtol"):
+        srv.submit(cfg, b, x, rtol=-1.0, tag=2)
     srv.close()
 
 
