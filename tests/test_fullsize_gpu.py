@@ -133,3 +133,36 @@ def test_full_size_one_cycle_and_residual_elementwise(mg, name, precision, tol):
     else:
         corr = want - x0
         assert np.max(np.abs((got - x0) - corr)) <= tol * np.abs(corr).max()
+
+
+def test_dense_sphere_512_residual_and_solve(mg):
+    """Beyond the benchmark's sizes: 512^3 cells (134 M, 1 GiB per FP64 field,
+    byte offsets past 2^31), default launch shapes, 8 levels.  The residual
+    kernel element by element against the oracle (1e-13 of the largest entry),
+    then the solve to 1e-8 checked by the oracle's FP64 residual.  The oracle's
+    cycle is too slow on the host at this size for an element-wise cycle."""
+    import torch
+
+    work = inputs.dense_sphere(512, seed=2)
+    nx, ny, nz = work["shape"]
+    b0 = work["b"] - work["b"].mean()
+    x0 = np.random.default_rng(41).standard_normal(b0.shape)
+    cfg = mg.config_default(nx, ny, nz, work["h"], bc=work["bc"], coef_mode=1)
+    kd = torch.from_numpy(work["k"].reshape(-1)).cuda()
+    bd = torch.from_numpy(b0.reshape(-1)).cuda()
+    H = mg.Hierarchy(cfg, kd)
+    assert len(H.levels()) == 8
+    r = torch.empty_like(bd)
+    nrm = H.residual(torch.from_numpy(x0.reshape(-1)).cuda(), bd, r)
+    want = oracle.residual(b0, x0, work["h"], work["bc"], work["k"])
+    got = r.cpu().numpy().reshape(want.shape)
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.abs(want).max()
+    assert abs(nrm - np.linalg.norm(want)) <= 1e-12 * np.linalg.norm(want)
+    del r, got, want
+    xd = torch.zeros_like(bd)
+    info = H.solve(bd, xd, rtol=1e-8, max_cycles=2000)
+    x = xd.cpu().numpy().reshape(b0.shape)
+    H.close()
+    assert info.status == 0 and info.relres <= 1e-8
+    assert oracle_relres(work, x) <= 1.05e-8
+    assert abs(x.mean()) <= 1e-12 * np.abs(x).max()
