@@ -1,7 +1,8 @@
 """Full-size solves in the benchmark's launch configuration (autotuned tiles),
 checked by the oracle's FP64 residual of the returned x over the whole field.
 
-* 256^3 dense sphere (rho 1000/1, k = 1/rho, Neumann), FP64 and FP32-smoothing.
+* 256^3 dense sphere (rho 1000/1, k = 1/rho, Neumann), FP64 and FP32-smoothing,
+  stationary and flexible-CG outer iteration.
 * 256 x 256 x 512 rising bubble (air in water, zero pressure on top), FP16-stored
   coefficient + FP32 smoothing + FP64 residual/refinement.
 The bar is the solve tolerance itself: ||b - A x||_2 <= 1e-8 ||b||_2 with A the
@@ -38,11 +39,11 @@ def mg():
     return nn4mg
 
 
-def run(mg, work, precision):
+def run(mg, work, precision, outer=0):
     import torch
 
     nx, ny, nz = work["shape"]
-    cfg = mg.config_default(nx, ny, nz, work["h"], bc=work["bc"], coef_mode=1, precision=precision)
+    cfg = mg.config_default(nx, ny, nz, work["h"], bc=work["bc"], coef_mode=1, precision=precision, outer=outer)
     kd = torch.from_numpy(work["k"].reshape(-1)).cuda()
     bd = torch.from_numpy(work["b"].reshape(-1)).cuda()
     xd = torch.zeros_like(bd)
@@ -71,6 +72,19 @@ def test_dense_sphere_256(mg, precision):
     assert oracle_relres(work, x) <= 1.05e-8
     if all(v != 0 for v in work["bc"]):
         assert abs(x.mean()) <= 1e-12 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_dense_sphere_256_fcg(mg, precision):
+    """The flexible-CG outer iteration the benchmark times beside the
+    stationary cycle: converged to 1e-8 by the oracle's residual, in fewer
+    iterations than the stationary cycle's 99."""
+    work = inputs.dense_sphere(256, seed=2)
+    info, x = run(mg, work, precision, outer=1)
+    assert info.status == 0 and info.relres <= 1e-8
+    assert info.cycles < 60
+    assert oracle_relres(work, x) <= 1.05e-8
+    assert abs(x.mean()) <= 1e-12 * np.abs(x).max()
 
 
 def test_rising_bubble_256x256x512_fp16_coefficient(mg):
