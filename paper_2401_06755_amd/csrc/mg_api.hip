@@ -668,11 +668,13 @@ int enqueue_fine_sweeps(nn4mg_hier *H, const double *b, const double *bmean, dou
     return NN4MG_OK;
 }
 
+int resid_blocks(const nn4mg_hier *H) { return H->lv[0].tiles[NN4MG_KCLASS_FINE_RESID].blocks(); }
+
 // Everything of one cycle after the finest residual has been restricted to
 // level 1 (FP64: lv[1].b; mixed: lv[1].b32 and the FP32 finest residual in
 // lv[0].b32).
 int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done,
-                       bool x_zero = false)
+                       bool x_zero = false, bool stop_in_chain = false)
 {
     const bool f64 = !H->mixed;
     const int L = H->L;
@@ -688,8 +690,12 @@ int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, doub
                 if (m > l + depth) return nullptr;
                 return f64 ? (void *)H->lv[m].b : (void *)H->lv[m].b32;
             };
+            // the first launch also runs the stopping rule of the residual
+            // the previous cycle ended with (stationary solves)
+            const bool stop_here = stop_in_chain && l == 1;
             HIP_TRY(launch_restrict_chain(f64 ? 1 : 0, f64 ? (void *)V.b : (void *)V.b32, bof(l + 1), bof(l + 2),
-                                          bof(l + 3), V.nx, V.ny, V.nz, depth, done, s));
+                                          bof(l + 3), V.nx, V.ny, V.nz, depth, done, s, stop_here ? H->st : nullptr,
+                                          stop_here ? H->partials : nullptr, stop_here ? resid_blocks(H) : 0));
         }
         TailArgs ta;
         std::memset(&ta, 0, sizeof(ta));
@@ -762,13 +768,17 @@ int enqueue_single_level_body(nn4mg_hier *H, double *x, const int *done)
     return NN4MG_OK;
 }
 
-int enqueue_body(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done)
+// The stationary solve's stopping rule runs inside the cycle's first
+// restriction-chain launch when there is one (levels between the finest and
+// the coarse end); otherwise as its own launch after each residual.
+bool stop_in_chain(const nn4mg_hier *H) { return H->L > 1 && H->tail > 2; }
+
+int enqueue_body(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done,
+                 bool with_stop = false)
 {
     if (H->L == 1) return enqueue_single_level_body(H, x, done);
-    return enqueue_cycle_body(H, b, bmean, x, done);
+    return enqueue_cycle_body(H, b, bmean, x, done, false, with_stop && stop_in_chain(H));
 }
-
-int resid_blocks(const nn4mg_hier *H) { return H->lv[0].tiles[NN4MG_KCLASS_FINE_RESID].blocks(); }
 
 }  // namespace
 
@@ -1006,9 +1016,11 @@ int enqueue_stationary_iteration(nn4mg_hier *H, const double *b, double *x)
     int rc;
     H->cur_tag += 1;
     const int *done = &H->st->done;
-    if ((rc = enqueue_body(H, b, H->singular ? &H->st->bmean : nullptr, x, done))) return rc;
+    if ((rc = enqueue_body(H, b, H->singular ? &H->st->bmean : nullptr, x, done, true))) return rc;
     if ((rc = enqueue_resid_for_cycle(H, b, x, H->singular ? &H->st->bmean : nullptr, true, done))) return rc;
-    HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), H->stream));
+    // with the rule in the next cycle's chain, the residual is judged there
+    // (or by the stand-alone launch that ends each batch)
+    if (!stop_in_chain(H)) HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), H->stream));
     return NN4MG_OK;
 }
 
@@ -1191,7 +1203,7 @@ int solve_begin(nn4mg_hier *H, const double *b, double *x, double rtol, int max_
     if ((rc = enqueue_b_norm(H, b))) return rc;
     if (H->cfg.outer == NN4MG_OUTER_FCG) return enqueue_fcg_start(H, b, x);
     if ((rc = enqueue_resid_for_cycle(H, b, x, H->singular ? &H->st->bmean : nullptr, true, &H->st->done))) return rc;
-    HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), s));
+    HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), s, stop_in_chain(H) ? 1 : 0));
     return NN4MG_OK;
 }
 
@@ -1208,6 +1220,9 @@ int solve_enqueue_next(nn4mg_hier *H, const double *b, double *x)
         for (int c = 0; c < n; ++c)
             if ((rc = enqueue_iteration(H, b, x))) return rc;
     }
+    // the last residual of the batch is judged before the host reads the state
+    if (H->cfg.outer != NN4MG_OUTER_FCG && stop_in_chain(H))
+        HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), H->stream, 1));
     H->solve_enqueued += n;
     return NN4MG_OK;
 }

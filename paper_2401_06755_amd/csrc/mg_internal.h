@@ -77,7 +77,7 @@ struct SolveState {
     int nres;        // residual norms recorded
     int done;        // 1 once the stopping rule fired
     int status;      // 0, -4 (max cycles), -5 (non-finite)
-    int pad_;
+    int taken;       // 1: a stand-alone stopping-rule launch already took the latest residual
     double last;     // last relative residual
     double hist[512];
     // flexible CG scalars
@@ -94,8 +94,11 @@ hipError_t launch_stencil(int T_is_f64, int kt, int in_mode, int out_mode, int o
                           hipStream_t s);
 
 // depth (1..3) successive restrictions from the level of dims nx x ny x nz into c1, c2, c3 (one launch).
+// With st, one extra workgroup applies the stopping rule to the np residual
+// partials (skipped when a stand-alone launch marked them taken).
 hipError_t launch_restrict_chain(int T_is_f64, const void *fine, void *c1, void *c2, void *c3, int nx, int ny, int nz,
-                                 int depth, const int *done, hipStream_t s);
+                                 int depth, const int *done, hipStream_t s, SolveState *st = nullptr,
+                                 const double *partials = nullptr, int np = 0);
 hipError_t launch_restrict(int T_is_f64, const void *fine, void *coarse, int nx, int ny, int nz, const int *done,
                            hipStream_t s);
 hipError_t launch_coarsen_k(const double *kf, double *kc, int nx, int ny, int nz, int harmonic, hipStream_t s);
@@ -113,7 +116,9 @@ hipError_t launch_reduce(const double *partials, int n, double scale, double *ou
 hipError_t launch_init_state(SolveState *st, double rtol, int max_cycles, int fixed, hipStream_t s);
 hipError_t launch_set_nb(SolveState *st, const double *sumsq, hipStream_t s);
 // Stopping rule after a residual: consumes partials of r^2.
-hipError_t launch_finish_norm(SolveState *st, const double *partials, int n, hipStream_t s);
+// Stopping rule on the residual partials; mark_taken = 1 tells the stopping
+// workgroup of the next restriction chain that this residual is done.
+hipError_t launch_finish_norm(SolveState *st, const double *partials, int n, hipStream_t s, int mark_taken = 0);
 
 hipError_t launch_coarse_solve(int T_is_f64, const void *bc, void *ec, const double *ainv, int n, int singular,
                                const int *done, hipStream_t s);

@@ -31,15 +31,65 @@ __global__ __launch_bounds__(256) void restrict_kernel(const T *f, T *c, int nx,
 // and 2^3 blocks of the next levels under it.  A coarse cell depends only on
 // its own children, so no workgroup waits for another.  Sums in the order of
 // restrict_kernel (x pairs, then y, then z), so the results are the same.
+// The stopping rule on the latest residual norm (thread 0 of one workgroup):
+// record the relative residual and set done / status.
+__device__ void stop_rule(SolveState *st, double sumsq)
+{
+    const double rel = sqrt(sumsq) / st->nb;
+    const int idx = st->nres;
+    if (idx < 512) st->hist[idx] = rel;
+    st->last = rel;
+    st->nres = idx + 1;
+    if (!isfinite(rel)) {
+        st->done = 1;
+        st->status = -5;
+    } else if (!st->fixed && rel <= st->rtol) {
+        st->done = 1;
+        st->status = 0;
+    } else if (idx >= st->max_cycles) {
+        st->done = 1;
+        st->status = st->fixed ? 0 : -4;
+    }
+}
+
+// Sum of n partials by a 512-thread workgroup, fixed order; thread 0 holds it.
+__device__ double reduce_512(const double *p, int n, double *red)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 512) acc += p[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < 8; ++w) s += red[w];
+    return s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(512) void restrict_chain_kernel(const T *f, T *c1, T *c2, T *c3, int nx, int ny, int nz,
-                                                             int depth, const int *done)
+                                                             int depth, const int *done, SolveState *st,
+                                                             const double *partials, int np)
 {
     if (done && *done) return;
+    if (st && blockIdx.x == 0) {
+        // the extra first workgroup (dispatched first, so its reduction is off
+        // the chain's critical path): stopping rule of the residual the
+        // previous cycle ended with, unless a stand-alone launch already took it
+        __shared__ double red[8];
+        if (st->taken) {
+            if (threadIdx.x == 0) st->taken = 0;
+            return;
+        }
+        const double s = reduce_512(partials, np, red);
+        if (threadIdx.x == 0) stop_rule(st, s);
+        return;
+    }
     __shared__ T s1[512];  // the 8^3 block of the first coarse level
     __shared__ T s2[64];   // the 4^3 block of the second
     const int bxn = (nx + 15) / 16, byn = (ny + 15) / 16;
-    const int bx = blockIdx.x % bxn, rest = blockIdx.x / bxn;
+    const int bid = st ? (int)blockIdx.x - 1 : (int)blockIdx.x;
+    const int bx = bid % bxn, rest = bid / bxn;
     const int by = rest % byn, bz = rest / byn;
     const int t = threadIdx.x;
     const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
@@ -171,27 +221,14 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double *p, int n, do
     if (threadIdx.x == 0) out[0] = scale * s;
 }
 
-__global__ __launch_bounds__(1024) void finish_norm_kernel(SolveState *st, const double *p, int n)
+__global__ __launch_bounds__(1024) void finish_norm_kernel(SolveState *st, const double *p, int n, int mark)
 {
     __shared__ double red[16];
     if (st->done) return;
     const double s = reduce_1024(p, n, red);
     if (threadIdx.x == 0) {
-        const double rel = sqrt(s) / st->nb;
-        const int idx = st->nres;
-        if (idx < 512) st->hist[idx] = rel;
-        st->last = rel;
-        st->nres = idx + 1;
-        if (!isfinite(rel)) {
-            st->done = 1;
-            st->status = -5;
-        } else if (!st->fixed && rel <= st->rtol) {
-            st->done = 1;
-            st->status = 0;
-        } else if (idx >= st->max_cycles) {
-            st->done = 1;
-            st->status = st->fixed ? 0 : -4;
-        }
+        stop_rule(st, s);
+        if (mark) st->taken = 1;
     }
 }
 
@@ -205,6 +242,7 @@ __global__ void init_state_kernel(SolveState *st, double rtol, int max_cycles, i
     st->nres = 0;
     st->done = 0;
     st->status = 0;
+    st->taken = 0;
     st->last = 0.0;
     st->fcg_rho = st->fcg_alpha = st->fcg_beta = st->fcg_pq_prev = 0.0;
 }
@@ -303,16 +341,19 @@ hipError_t launch_restrict(int T_is_f64, const void *fine, void *coarse, int nx,
 }
 
 hipError_t launch_restrict_chain(int T_is_f64, const void *fine, void *c1, void *c2, void *c3, int nx, int ny, int nz,
-                                 int depth, const int *done, hipStream_t s)
+                                 int depth, const int *done, hipStream_t s, SolveState *st, const double *partials,
+                                 int np)
 {
     if (depth < 1 || depth > 3) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(((nx + 15) / 16) * ((ny + 15) / 16) * ((nz + 15) / 16)));
+    if (st && (!partials || np < 1)) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)(((nx + 15) / 16) * ((ny + 15) / 16) * ((nz + 15) / 16));
+    const dim3 grid(st ? nb + 1 : nb);
     if (T_is_f64)
         hipLaunchKernelGGL(restrict_chain_kernel<double>, grid, dim3(512), 0, s, (const double *)fine, (double *)c1,
-                           (double *)c2, (double *)c3, nx, ny, nz, depth, done);
+                           (double *)c2, (double *)c3, nx, ny, nz, depth, done, st, partials, np);
     else
         hipLaunchKernelGGL(restrict_chain_kernel<float>, grid, dim3(512), 0, s, (const float *)fine, (float *)c1,
-                           (float *)c2, (float *)c3, nx, ny, nz, depth, done);
+                           (float *)c2, (float *)c3, nx, ny, nz, depth, done, st, partials, np);
     return hipGetLastError();
 }
 
@@ -373,9 +414,9 @@ hipError_t launch_set_nb(SolveState *st, const double *sumsq, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_finish_norm(SolveState *st, const double *partials, int n, hipStream_t s)
+hipError_t launch_finish_norm(SolveState *st, const double *partials, int n, hipStream_t s, int mark_taken)
 {
-    hipLaunchKernelGGL(finish_norm_kernel, dim3(1), dim3(1024), 0, s, st, partials, n);
+    hipLaunchKernelGGL(finish_norm_kernel, dim3(1), dim3(1024), 0, s, st, partials, n, mark_taken);
     return hipGetLastError();
 }
 
