@@ -240,6 +240,32 @@ def test_config1_poisson_64_to_1e8(mg):
     assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(w["b"])
 
 
+@pytest.mark.parametrize("shape,bc", [((64, 64, 64), (N, N, N, N, N, D)), ((96, 32, 64), (P, P, N, N, D, D))])
+def test_tolerance_solve_history_matches_oracle(mg, shape, bc):
+    """A solve to 1e-8 runs as several planned batches of cycles; the stopping
+    rule of each cycle's residual runs inside the next cycle's first launch and
+    in a stand-alone launch at the end of each batch.  Every entry of the
+    history (the relative residual before each cycle and the final one) equals
+    the oracle's to 1e-10 relative, so each residual is judged exactly once,
+    and the solve stops at the oracle's cycle."""
+    nx, ny, nz = shape
+    b = np.random.default_rng(33).standard_normal((nz, ny, nx))
+    frac = inputs.sphere_fraction(shape, 1.0 / nx, (0.5, 0.5, 0.5 * nz / nx), 0.3)
+    k = inputs.two_phase_k(frac, 1000.0, 1.0)
+    h = 1.0 / nx
+    H = make(mg, shape, h, bc, k)
+    xd = dev(np.zeros_like(b))
+    info = H.solve(dev(b), xd, rtol=1e-8, max_cycles=500)
+    xo, hist_o, st = oracle.Hierarchy(shape, h, bc, k=k).solve(b, rtol=1e-8, max_cycles=500)
+    H.close()
+    assert info.status == 0 and st == 0
+    assert info.cycles == len(hist_o) - 1 > 8  # more than the first planned batch of 4
+    hist_g = np.array(info.history())
+    assert len(hist_g) == len(hist_o)
+    assert np.all(np.abs(hist_g - hist_o) <= 1e-10 * hist_o + 1e-13)
+    assert np.max(np.abs(host(xd, b.shape) - xo)) <= 1e-10 * np.abs(xo).max()
+
+
 def test_singular_neumann_zero_mean_and_projection(mg):
     """All-Neumann: b projected to zero mean, x returned with zero mean; same
     cycle count and x as the oracle (which projects x after every cycle)."""
