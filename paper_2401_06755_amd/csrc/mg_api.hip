@@ -673,8 +673,10 @@ int resid_blocks(const nn4mg_hier *H) { return H->lv[0].tiles[NN4MG_KCLASS_FINE_
 // Everything of one cycle after the finest residual has been restricted to
 // level 1 (FP64: lv[1].b; mixed: lv[1].b32 and the FP32 finest residual in
 // lv[0].b32).
+// stop_np > 0: the first restriction-chain launch also applies the stopping
+// rule to the stop_np norm partials in H->partials.
 int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done,
-                       bool x_zero = false, bool stop_in_chain = false)
+                       bool x_zero = false, int stop_np = 0)
 {
     const bool f64 = !H->mixed;
     const int L = H->L;
@@ -690,12 +692,12 @@ int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, doub
                 if (m > l + depth) return nullptr;
                 return f64 ? (void *)H->lv[m].b : (void *)H->lv[m].b32;
             };
-            // the first launch also runs the stopping rule of the residual
-            // the previous cycle ended with (stationary solves)
-            const bool stop_here = stop_in_chain && l == 1;
+            // the first launch may also run the stopping rule (on the residual
+            // the previous stationary cycle ended with, or on FCG's updated r)
+            const bool stop_here = stop_np > 0 && l == 1;
             HIP_TRY(launch_restrict_chain(f64 ? 1 : 0, f64 ? (void *)V.b : (void *)V.b32, bof(l + 1), bof(l + 2),
                                           bof(l + 3), V.nx, V.ny, V.nz, depth, done, s, stop_here ? H->st : nullptr,
-                                          stop_here ? H->partials : nullptr, stop_here ? resid_blocks(H) : 0));
+                                          stop_here ? H->partials : nullptr, stop_here ? stop_np : 0));
         }
         TailArgs ta;
         std::memset(&ta, 0, sizeof(ta));
@@ -777,7 +779,7 @@ int enqueue_body(nn4mg_hier *H, const double *b, const double *bmean, double *x,
                  bool with_stop = false)
 {
     if (H->L == 1) return enqueue_single_level_body(H, x, done);
-    return enqueue_cycle_body(H, b, bmean, x, done, false, with_stop && stop_in_chain(H));
+    return enqueue_cycle_body(H, b, bmean, x, done, false, with_stop && stop_in_chain(H) ? resid_blocks(H) : 0);
 }
 
 }  // namespace
@@ -1037,17 +1039,19 @@ FcgVec fcg_vec(nn4mg_hier *H)
 
 // z = M r.  FP64: the cycle's right-hand side is r itself; mixed: the FP32
 // copy of r already sits in lv[0].b32 and the cycle adds its correction to z.
-int enqueue_precondition(nn4mg_hier *H, const double *r, double *z, const int *done)
+// stop_np > 0: the cycle's first restriction-chain launch applies the
+// stopping rule to that many norm partials (the caller checked stop_in_chain).
+int enqueue_precondition(nn4mg_hier *H, const double *r, double *z, const int *done, int stop_np = 0)
 {
     Level &F = H->lv[0];
     hipStream_t s = H->stream;
     if (!H->mixed) {
         HIP_TRY(launch_restrict(1, r, H->lv[1].b, F.nx, F.ny, F.nz, done, s));
-        return enqueue_cycle_body(H, r, nullptr, z, done, true);
+        return enqueue_cycle_body(H, r, nullptr, z, done, true, stop_np);
     }
     HIP_TRY(launch_restrict(0, F.b32, H->lv[1].b32, F.nx, F.ny, F.nz, done, s));
     HIP_TRY(launch_zero(z, F.n, done, s));
-    return enqueue_cycle_body(H, nullptr, nullptr, z, done);
+    return enqueue_cycle_body(H, nullptr, nullptr, z, done, false, stop_np);
 }
 
 // Start: r = (b - mean) - A x, its norm (stopping rule), z = M r, rho = z.r, p = z.
@@ -1093,8 +1097,11 @@ int enqueue_fcg_iteration(nn4mg_hier *H, double *x)
         HIP_TRY(launch_fcg_alpha_partials(H->partials, resid_blocks(H), H->st, s));
     }
     HIP_TRY(launch_fcg_update(H->st, x, v.p, v.r, v.t, H->mixed ? H->lv[0].b32 : nullptr, n, H->partials, s));
-    HIP_TRY(launch_finish_norm(H->st, H->partials, fcg_update_blocks(n), s));
-    if ((rc = enqueue_precondition(H, v.r, v.z, done))) return rc;
+    // the stopping rule on ||r|| runs in the preconditioning cycle's first
+    // chain launch when it has one (the restriction before it runs regardless)
+    const bool fold = stop_in_chain(H);
+    if (!fold) HIP_TRY(launch_finish_norm(H->st, H->partials, fcg_update_blocks(n), s));
+    if ((rc = enqueue_precondition(H, v.r, v.z, done, fold ? fcg_update_blocks(n) : 0))) return rc;
     HIP_TRY(launch_fcg_dots(v.z, v.r, v.t, n, H->fcg_part, H->st, 2, s));
     HIP_TRY(launch_fcg_direction(H->st, v.z, v.p, n, s));
     return NN4MG_OK;
