@@ -70,6 +70,7 @@ def lib():
             "or_level_k": (None, [vp, i, dp]),
             "or_vcycle": (None, [vp, dp, dp]),
             "or_solve": (i, [vp, dp, dp, d, i, i, dp, ip]),
+            "or_fcg": (i, [vp, dp, dp, d, i, i, i, dp, ip]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -100,6 +101,20 @@ def _declare_step(L):
                           dp, dp, dp, dp, dp, dp, ctypes.POINTER(StepInfo)]
     L.or_step_filters.restype = None
     L.or_step_filters.argtypes = [ctypes.c_double, dp, dp, dp, dp]
+    i, d = ctypes.c_int, ctypes.c_double
+    L.or_step_set_periodic.restype = None
+    L.or_step_set_periodic.argtypes = [i]
+    L.or_step_surface.restype = None
+    L.or_step_surface.argtypes = [i, i, i, d, d, dp, dp, dp, dp, dp, dp, dp, dp]
+    L.or_step_pg_velocity.restype = None
+    L.or_step_pg_velocity.argtypes = [i, i, i, d, i, dp, dp, dp, dp, dp, dp, dp]
+    L.or_step_vof_coefs.restype = None
+    L.or_step_vof_coefs.argtypes = [i, i, i, d, d, dp, dp, dp, dp, dp, dp, dp, dp]
+    L.or_step_vof.restype = None
+    L.or_step_vof.argtypes = [i, i, i, d, d, dp, dp, dp, dp]
+    L.or_step_correct.restype = ctypes.c_int
+    L.or_step_correct.argtypes = [i, i, i, d, ctypes.POINTER(StepParams), dp, dp, dp, dp, dp,
+                                  ctypes.POINTER(StepInfo)]
 
 
 def step_params(rho_l=1000.0, rho_g=1.0, mu_l=1e-3, mu_g=1.8e-5, g=9.81, sigma_t=0.07, dt=1e-4, mg_cycles=20,
@@ -120,6 +135,68 @@ def step(state, h, params=None):
     if rc != 0:
         raise RuntimeError("oracle step failed")
     return [info.relres[i] for i in range(info.solves)]
+
+
+class periodic_step:
+    """Context manager: inside it the step oracle uses the test-only periodic
+    box (every halo wraps, periodic pressure solves) instead of the tank."""
+
+    def __enter__(self):
+        lib().or_step_set_periodic(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib().or_step_set_periodic(0)
+        return False
+
+
+def step_surface(C, h, sigma_t):
+    """grad C (derivative units), curvature and surface-tension vectors of C."""
+    C = _f64(C)
+    nx, ny, nz = _shape(C)
+    out = [np.empty_like(C) for _ in range(7)]
+    lib().or_step_surface(nx, ny, nz, float(h), float(sigma_t), _d(C), *[_d(a) for a in out])
+    return dict(Cx=out[0], Cy=out[1], Cz=out[2], kappa=out[3], st=(out[4], out[5], out[6]))
+
+
+def step_pg_velocity(comp, u, v, w, rho, mu, h):
+    """Advection residual a and diffusivity k of velocity component comp."""
+    u, v, w, rho, mu = (_f64(a) for a in (u, v, w, rho, mu))
+    nx, ny, nz = _shape(u)
+    a, k = np.empty_like(u), np.empty_like(u)
+    lib().or_step_pg_velocity(nx, ny, nz, float(h), int(comp), _d(u), _d(v), _d(w), _d(rho), _d(mu), _d(a), _d(k))
+    return a, k
+
+
+def step_vof_coefs(C, u, v, w, h, dt):
+    """Stage-4 diffusivities (kx, ky, kz) and the advection residual of C."""
+    C, u, v, w = (_f64(a) for a in (C, u, v, w))
+    nx, ny, nz = _shape(C)
+    out = [np.empty_like(C) for _ in range(4)]
+    lib().or_step_vof_coefs(nx, ny, nz, float(h), float(dt), _d(C), _d(u), _d(v), _d(w), *[_d(a) for a in out])
+    return out[0], out[1], out[2], out[3]
+
+
+def step_vof(C, u, v, w, h, dt):
+    """Stage 4 alone: returns C^{n+1}."""
+    C = _f64(C).copy()
+    u, v, w = (_f64(a) for a in (u, v, w))
+    nx, ny, nz = _shape(C)
+    lib().or_step_vof(nx, ny, nz, float(h), float(dt), _d(C), _d(u), _d(v), _d(w))
+    return C
+
+
+def step_correct(C, u, v, w, p_nh, h, params):
+    """Stage 3 alone on copies: returns (u, v, w, p_nh, relres list)."""
+    C = _f64(C)
+    u, v, w, p_nh = (_f64(a).copy() for a in (u, v, w, p_nh))
+    nx, ny, nz = _shape(C)
+    info = StepInfo()
+    rc = lib().or_step_correct(nx, ny, nz, float(h), ctypes.byref(params), _d(C), _d(u), _d(v), _d(w), _d(p_nh),
+                               ctypes.byref(info))
+    if rc != 0:
+        raise RuntimeError("oracle correction failed")
+    return u, v, w, p_nh, [info.relres[i] for i in range(info.solves)]
 
 
 def step_filters(h):
@@ -293,6 +370,17 @@ class Hierarchy:
         st = lib().or_solve(self._ptr, _d(b), _d(x), float(rtol), int(max_cycles), int(fixed), _d(hist),
                             ctypes.byref(cyc))
         return x, hist[: cyc.value + 1].copy(), st
+
+    def fcg(self, b, x0=None, rtol=1e-8, max_iter=100, fixed=False, precond=True):
+        """FCG(1) around one cycle from zero (precond) or plain CG; returns
+        (x, history of ||r|| / ||b||, status)."""
+        b = _f64(b)
+        x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+        hist = np.zeros(max_iter + 1)
+        it = ctypes.c_int(0)
+        st = lib().or_fcg(self._ptr, _d(b), _d(x), float(rtol), int(max_iter), int(fixed), int(precond), _d(hist),
+                          ctypes.byref(it))
+        return x, hist[: it.value + 1].copy(), st
 
     def __del__(self):
         p = getattr(self, "_ptr", None)

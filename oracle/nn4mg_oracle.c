@@ -525,3 +525,81 @@ int or_solve(or_hier *H, const double *b_in, double *x, double rtol, int max_cyc
     free(b); free(r);
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Flexible conjugate gradients around the cycle                             */
+/* ------------------------------------------------------------------------ */
+
+static double dot(size_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (size_t p = 0; p < n; ++p) s += a[p] * b[p];
+    return s;
+}
+
+/* FCG(1), flexible conjugate gradients with one direction kept (Notay,
+ * SIAM J. Sci. Comput. 22, 2000), preconditioned by one sawtooth cycle from a
+ * zero guess (precond = 1) or by the identity (precond = 0, plain CG).  The
+ * paper repeats the cycle on its own; this outer iteration is the library's
+ * addition around the same cycle, written as the plain recurrence:
+ *   r = b - A x, z = M r, p = z, rho = z.r;  then per iteration
+ *   t = A p, alpha = rho / p.t, x += alpha p, r -= alpha t,
+ *   z = M r, beta = -(z.t) / (p.t), rho = z.r, p = z + beta p.
+ * hist[c] = ||r_c|| / ||b|| with the recursively updated r, before iteration
+ * c; the stopping rule and the return codes are those of or_solve.  Singular
+ * problems: b projected to zero mean, x projected once at the end. */
+int or_fcg(or_hier *H, const double *b_in, double *x, double rtol, int max_iter, int fixed, int precond,
+           double *hist, int *iters_out)
+{
+    size_t n = (size_t)H->nx[0] * H->ny[0] * H->nz[0];
+    double *b = (double *)malloc(sizeof(double) * n), *r = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n), *p = (double *)malloc(sizeof(double) * n);
+    double *t = (double *)malloc(sizeof(double) * n);
+    memcpy(b, b_in, sizeof(double) * n);
+    if (H->singular) subtract_mean(n, b);
+    double nb = norm2(n, b);
+    int status = 0, c = 0;
+    if (nb == 0.0) {
+        memset(x, 0, sizeof(double) * n);
+        if (hist) hist[0] = 0.0;
+        if (iters_out) *iters_out = 0;
+        free(b); free(r); free(z); free(p); free(t);
+        return 0;
+    }
+    or_residual(H->nx[0], H->ny[0], H->nz[0], H->h[0], H->bc, H->k[0], b, x, r);
+    if (precond) {
+        memset(z, 0, sizeof(double) * n);
+        or_vcycle(H, z, r);
+    } else {
+        memcpy(z, r, sizeof(double) * n);
+    }
+    memcpy(p, z, sizeof(double) * n);
+    double rho = dot(n, z, r);
+    for (c = 0;; ++c) {
+        double rel = norm2(n, r) / nb;
+        if (hist) hist[c] = rel;
+        if (!isfinite(rel)) { status = -5; break; }
+        if (!fixed && rel <= rtol) break;
+        if (c == max_iter) {
+            if (!fixed) status = -4;
+            break;
+        }
+        or_apply(H->nx[0], H->ny[0], H->nz[0], H->h[0], H->bc, H->k[0], p, t);
+        double pt = dot(n, p, t), alpha = rho / pt;
+        for (size_t q = 0; q < n; ++q) x[q] += alpha * p[q];
+        for (size_t q = 0; q < n; ++q) r[q] -= alpha * t[q];
+        if (precond) {
+            memset(z, 0, sizeof(double) * n);
+            or_vcycle(H, z, r);
+        } else {
+            memcpy(z, r, sizeof(double) * n);
+        }
+        double beta = -dot(n, z, t) / pt;
+        rho = dot(n, z, r);
+        for (size_t q = 0; q < n; ++q) p[q] = z[q] + beta * p[q];
+    }
+    if (H->singular) subtract_mean(n, x);
+    if (iters_out) *iters_out = c;
+    free(b); free(r); free(z); free(p); free(t);
+    return status;
+}

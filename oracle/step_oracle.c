@@ -30,7 +30,12 @@
  *    Sec. 2.3.5 (linear detectors Eqs. Sx-lin..Sz-lin); the two maxima are kept
  *    apart (k_max of Eq. max-k vs the clamp k_max of Eq. alpha_min_and_max);
  *  - the VOF step uses the latest velocity u^{n+1} in all its coefficients;
- *  - Eqs. ph_disc and surface-tension-k are followed as printed.
+ *  - Eqs. ph_disc and surface-tension-k are followed as printed; the
+ *    surface-tension source of the momentum residual (Eq. Petrov) takes the
+ *    sign for which the Stage-1 pressure balances it, as Eq. hydro-pressure
+ *    states (printed, the two signs disagree: the pressure of Eq. ph_disc has
+ *    the physical Laplace jump, so its gradient is -s_t, and the printed
+ *    -f(s_t; w_m) would double the force at a static drop).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -60,6 +65,10 @@ void or_q1_filter(double h, double w[27]);
 
 static int NX, NY, NZ;
 static double H;
+/* Test-only periodic box: when set, every halo wraps (no walls, no affine
+ * bottom halo) and the pressure solves are periodic.  The tank rules above are
+ * the default. */
+static int WRAP = 0;
 
 static size_t pid(int i, int j, int k) { return (size_t)(i + 1) + (size_t)(NX + 2) * ((size_t)(j + 1) + (size_t)(NY + 2) * (size_t)(k + 1)); }
 static size_t cid(int i, int j, int k) { return (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * (size_t)k); }
@@ -75,7 +84,8 @@ static double halo(int rule, double mirror, double lift) {
 
 /* Pad u with per-face rules, axis by axis.  lift (may be NULL) is the padded
  * field whose value at the mirror cell times lift_scale is added on R_AFFINE
- * faces. */
+ * faces.  In the periodic test mode every face takes the opposite interior
+ * value instead. */
 static void pad(const double *u, const int rule[6], const double *liftp, double lift_scale, double *up)
 {
     for (int k = 0; k < NZ; ++k)
@@ -83,16 +93,31 @@ static void pad(const double *u, const int rule[6], const double *liftp, double 
             for (int i = 0; i < NX; ++i) up[pid(i, j, k)] = u[cid(i, j, k)];
     for (int k = 0; k < NZ; ++k)
         for (int j = 0; j < NY; ++j) {
+            if (WRAP) {
+                up[pid(-1, j, k)] = up[pid(NX - 1, j, k)];
+                up[pid(NX, j, k)] = up[pid(0, j, k)];
+                continue;
+            }
             up[pid(-1, j, k)] = halo(rule[0], up[pid(0, j, k)], liftp ? lift_scale * liftp[pid(0, j, k)] : 0.0);
             up[pid(NX, j, k)] = halo(rule[1], up[pid(NX - 1, j, k)], liftp ? lift_scale * liftp[pid(NX - 1, j, k)] : 0.0);
         }
     for (int k = 0; k < NZ; ++k)
         for (int i = -1; i <= NX; ++i) {
+            if (WRAP) {
+                up[pid(i, -1, k)] = up[pid(i, NY - 1, k)];
+                up[pid(i, NY, k)] = up[pid(i, 0, k)];
+                continue;
+            }
             up[pid(i, -1, k)] = halo(rule[2], up[pid(i, 0, k)], liftp ? lift_scale * liftp[pid(i, 0, k)] : 0.0);
             up[pid(i, NY, k)] = halo(rule[3], up[pid(i, NY - 1, k)], liftp ? lift_scale * liftp[pid(i, NY - 1, k)] : 0.0);
         }
     for (int j = -1; j <= NY; ++j)
         for (int i = -1; i <= NX; ++i) {
+            if (WRAP) {
+                up[pid(i, j, -1)] = up[pid(i, j, NZ - 1)];
+                up[pid(i, j, NZ)] = up[pid(i, j, 0)];
+                continue;
+            }
             up[pid(i, j, -1)] = halo(rule[4], up[pid(i, j, 0)], liftp ? lift_scale * liftp[pid(i, j, 0)] : 0.0);
             up[pid(i, j, NZ)] = halo(rule[5], up[pid(i, j, NZ - 1)], liftp ? lift_scale * liftp[pid(i, j, NZ - 1)] : 0.0);
         }
@@ -170,6 +195,12 @@ static void build_filters(double h)
     or_q1_filter(h, WLAP);
 }
 
+static void set_grid(int nx, int ny, int nz, double h)
+{
+    NX = nx; NY = ny; NZ = nz; H = h;
+    build_filters(h);
+}
+
 /* ------------------------------------------------------------- rules */
 
 static const int RULE_EVEN[6] = {R_EVEN, R_EVEN, R_EVEN, R_EVEN, R_EVEN, R_EVEN};
@@ -189,6 +220,13 @@ static void rule_grad(int d, int r[6])
 }
 static const int RULE_PNH[6] = {R_EVEN, R_EVEN, R_EVEN, R_EVEN, R_EVEN, R_ODD};
 static const int RULE_PHS[6] = {R_EVEN, R_EVEN, R_EVEN, R_EVEN, R_AFFINE, R_ODD};
+
+/* the pressure hierarchy: Neumann except zero on top (periodic in the test mode) */
+static or_hier *pressure_hierarchy(void)
+{
+    const int bcT[6] = {1, 1, 1, 1, 1, 0}, bcW[6] = {2, 2, 2, 2, 2, 2};
+    return or_setup(NX, NY, NZ, H, WRAP ? bcW : bcT, NULL, 2.0 / 3.0, 2, 4, 0);
+}
 
 /* ------------------------------------------------------------- PG pieces */
 
@@ -222,7 +260,37 @@ static void pg_isotropic(const double *u, const double *v, const double *w, cons
     }
 }
 
-/* ------------------------------------------------------------- the step */
+/* ------------------------------------------------------------- stages */
+
+/* grad C in derivative units (Cd), the normals, the curvature of
+ * Eq. surface-tension-k and the surface-tension vectors of
+ * Eq. surface-tension-uvw. */
+static void surface(const double *C, double sigma_t, double *Cd[3], double *nrm[3], double *kappa, double *st[3],
+                    double *tmp)
+{
+    size_t n = ncell();
+    const double ml = H * H * H;
+    int rg[3][6];
+    for (int d = 0; d < 3; ++d) rule_grad(d, rg[d]);
+    for (int d = 0; d < 3; ++d) {
+        apply(C, RULE_EVEN, WD[d], Cd[d]);
+        for (size_t p = 0; p < n; ++p) Cd[d][p] /= ml;
+    }
+    const double eps_t = 1e-7 / H;
+    for (size_t p = 0; p < n; ++p) {
+        double l = sqrt(Cd[0][p] * Cd[0][p] + Cd[1][p] * Cd[1][p] + Cd[2][p] * Cd[2][p]);
+        for (int d = 0; d < 3; ++d) nrm[d][p] = Cd[d][p] / (eps_t + l);
+    }
+    for (size_t p = 0; p < n; ++p) kappa[p] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        apply(nrm[d], rg[d], WD[d], tmp);
+        for (size_t p = 0; p < n; ++p) kappa[p] += tmp[p];
+    }
+    for (size_t p = 0; p < n; ++p) {
+        kappa[p] /= ml;
+        for (int d = 0; d < 3; ++d) st[d][p] = sigma_t * kappa[p] * Cd[d][p];
+    }
+}
 
 static void solve_pressure(or_hier *Hr, const double *b, double *x, int cycles, or_step_info *info)
 {
@@ -232,11 +300,108 @@ static void solve_pressure(or_hier *Hr, const double *b, double *x, int cycles, 
     if (info && info->solves < 8) info->relres[info->solves++] = hist[cyc];
 }
 
+/* Stage 3: n_corr solves of Eq. ph_disc2 for dp_nh with the corrections of
+ * Eq. vel-cor applied to q (the Stage-2 estimate in, q^{n+1} out) and
+ * p_nh += dp_nh. */
+static void correct(const or_step_params *P, or_hier *Hr, const double *rho, double *q[3], double *p_nh,
+                    or_step_info *info)
+{
+    size_t n = ncell();
+    const double ml = H * H * H, dt = P->dt;
+    int rv[3][6];
+    for (int d = 0; d < 3; ++d) rule_vel(d, rv[d]);
+    double *b = alloc(), *tmp = alloc(), *tmp2 = alloc(), *dp = alloc();
+    for (int it = 0; it < P->n_corr; ++it) {
+        for (size_t p = 0; p < n; ++p) b[p] = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            for (size_t p = 0; p < n; ++p) tmp2[p] = rho[p] * q[d][p];
+            apply(tmp2, rv[d], WD[d], tmp);
+            for (size_t p = 0; p < n; ++p) b[p] -= tmp[p] / dt;
+            apply(rho, RULE_EVEN, WD[d], tmp);
+            for (size_t p = 0; p < n; ++p) b[p] += q[d][p] * tmp[p] / dt;
+        }
+        for (size_t p = 0; p < n; ++p) dp[p] = 0.0;
+        solve_pressure(Hr, b, dp, P->mg_cycles, info);
+        for (int d = 0; d < 3; ++d) {
+            apply(dp, RULE_PNH, WD[d], tmp);
+            for (size_t p = 0; p < n; ++p) q[d][p] += -dt * (tmp[p] / ml) / rho[p];
+        }
+        for (size_t p = 0; p < n; ++p) p_nh[p] += dp[p];
+    }
+    free(b); free(tmp); free(tmp2); free(dp);
+}
+
+/* Stage 4 coefficients: the anisotropic compressive diffusivities of
+ * Sec. 2.3.5 (detectors Eqs. Sx-lin..Sz-lin with the 0.05/0.95 override,
+ * weights w+ and w-, k- of Eqs. negativek and normalisation, k+ of
+ * Eq. positivek, clamps of Eq. alpha_min_and_max).  Cd = grad C in
+ * derivative units; a receives the advection residual of Eq. a_psi. */
+static void vof_coefs(const double *C, const double *u, const double *v, const double *w, double *const Cd[3],
+                      double dt, double *kd[3], double *a)
+{
+    const double Kp = 300.0, Km = 300.0, beta = 0.1, eps_x = 1e-4, Kpos = 3.0, eps_k = 1e-7;
+    const double h = H, kmin = 1e-4 / dt * h * h, kclamp = 0.05 / dt * h * h;
+    const double *Pd[3] = {Cd[0], Cd[1], Cd[2]};
+    double *adv = alloc();
+    adv_residual(u, v, w, Pd, 2.0, adv, a);
+    free(adv);
+    double *Cp = palloc();
+    pad(C, RULE_EVEN, NULL, 0.0, Cp);
+    for (int kk = 0; kk < NZ; ++kk)
+        for (int j = 0; j < NY; ++j)
+            for (int i = 0; i < NX; ++i) {
+                size_t p = cid(i, j, kk);
+                double c0 = Cp[pid(i, j, kk)];
+                double S[3];
+                S[0] = (c0 - Cp[pid(i - 1, j, kk)]) * (Cp[pid(i + 1, j, kk)] - c0);
+                S[1] = (c0 - Cp[pid(i, j - 1, kk)]) * (Cp[pid(i, j + 1, kk)] - c0);
+                S[2] = (c0 - Cp[pid(i, j, kk - 1)]) * (Cp[pid(i, j, kk + 1)] - c0);
+                if (c0 > 0.95 || c0 < 0.05) S[0] = S[1] = S[2] = -1.0;
+                double cx = Cd[0][p], cy = Cd[1][p], cz = Cd[2][p];
+                double g2 = cx * cx + cy * cy + cz * cz;
+                double proj = (u[p] * cx + v[p] * cy + w[p] * cz) / (eps_x + g2);
+                double us = cx * proj, vs = cy * proj, ws = cz * proj;
+                double kneg = -beta * (u[p] * u[p] + v[p] * v[p] + w[p] * w[p]) /
+                              (eps_x + g2 * (fabs(us) + fabs(vs) + fabs(ws)) / 3.0);
+                double G = fabs(cx) + fabs(cy) + fabs(cz);
+                double kabs = (1.0 / 16.0) * h * fabs(a[p]) / (eps_k + G / 3.0);
+                for (int d = 0; d < 3; ++d) {
+                    double wp = -fmax(-1.0, fmin(0.0, Kp * S[d]));
+                    double wm = fmin(1.0, fmax(0.0, Km * S[d]));
+                    double kk2 = wp * (Kpos * kabs) + wm * (kneg / h);
+                    kd[d][p] = fmax(-kmin, fmin(kclamp, kk2));
+                }
+            }
+    free(Cp);
+}
+
+/* Stage 4: C^{n+1} = C^n - dt f(s_C; w_ml^-1) (Eq. transport-indicator-1)
+ * with s_C = m_l (u C_x + v C_y + w C_z) + sum_d f_diff(C, k_d; w_dd^PG)
+ * (Eq. Petrov-C). */
+static void vof_update(double *C, const double *u, const double *v, const double *w, double *const Cd[3], double dt)
+{
+    size_t n = ncell();
+    const double ml = H * H * H;
+    double *a = alloc(), *tmp = alloc(), *kd[3];
+    for (int d = 0; d < 3; ++d) kd[d] = alloc();
+    vof_coefs(C, u, v, w, Cd, dt, kd, a);
+    double *sC = alloc();
+    for (size_t p = 0; p < n; ++p) sC[p] = ml * (u[p] * Cd[0][p] + v[p] * Cd[1][p] + w[p] * Cd[2][p]);
+    for (int d = 0; d < 3; ++d) {
+        fdiff(C, RULE_EVEN, kd[d], RULE_EVEN, WPG[d], tmp);
+        for (size_t p = 0; p < n; ++p) sC[p] += tmp[p];
+    }
+    for (size_t p = 0; p < n; ++p) C[p] = C[p] - dt * sC[p] / ml;
+    for (int d = 0; d < 3; ++d) free(kd[d]);
+    free(sC); free(a); free(tmp);
+}
+
+/* ------------------------------------------------------------- the step */
+
 int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C, double *u, double *v,
             double *w, double *p_hs, double *p_nh, or_step_info *info)
 {
-    NX = nx; NY = ny; NZ = nz; H = h;
-    build_filters(h);
+    set_grid(nx, ny, nz, h);
     if (info) memset(info, 0, sizeof(*info));
     const size_t n = ncell();
     const double ml = h * h * h, dt = P->dt;
@@ -254,28 +419,10 @@ int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C
         mu[p] = P->mu_l * C[p] + P->mu_g * (1.0 - C[p]);
     }
     /* grad C (derivative units), normals, curvature, surface tension */
-    for (int d = 0; d < 3; ++d) {
-        apply(C, RULE_EVEN, WD[d], Cd[d]);
-        for (size_t p = 0; p < n; ++p) Cd[d][p] /= ml;
-    }
-    const double eps_t = 1e-7 / h;
-    for (size_t p = 0; p < n; ++p) {
-        double l = sqrt(Cd[0][p] * Cd[0][p] + Cd[1][p] * Cd[1][p] + Cd[2][p] * Cd[2][p]);
-        for (int d = 0; d < 3; ++d) nrm[d][p] = Cd[d][p] / (eps_t + l);
-    }
     double *kappa = alloc();
-    for (int d = 0; d < 3; ++d) {
-        apply(nrm[d], rg[d], WD[d], tmp);
-        for (size_t p = 0; p < n; ++p) kappa[p] += tmp[p];
-    }
-    for (size_t p = 0; p < n; ++p) {
-        kappa[p] /= ml;
-        for (int d = 0; d < 3; ++d) st[d][p] = P->sigma_t * kappa[p] * Cd[d][p];
-    }
+    surface(C, P->sigma_t, Cd, nrm, kappa, st, tmp);
 
-    /* pressure hierarchy: Neumann except zero on top, constant coefficient */
-    const int bcP[6] = {1, 1, 1, 1, 1, 0};
-    or_hier *Hr = or_setup(nx, ny, nz, h, bcP, NULL, 2.0 / 3.0, 2, 4, 0);
+    or_hier *Hr = pressure_hierarchy();
     if (!Hr) return -1;
 
     /* ---- Stage 1: hydrostatic + surface-tension pressure, Eq. ph_disc ---- */
@@ -288,7 +435,7 @@ int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C
     apply(tmp2, RULE_EVEN, WD[2], tmp);
     for (size_t p = 0; p < n; ++p) b[p] += tmp[p];
     /* lift of the affine bottom halo: A applied to the halo constants alone */
-    {
+    if (!WRAP) {
         double *zero = alloc(), *liftp = palloc(), *rhop = palloc();
         pad(rho, RULE_EVEN, NULL, 0.0, rhop);
         pad(zero, RULE_PHS, rhop, P->g * h, liftp);
@@ -329,8 +476,11 @@ int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C
             for (size_t p = 0; p < n; ++p) tmp[p] += gp[p];
             apply(p_nh, RULE_PNH, WD[c], gp);
             for (size_t p = 0; p < n; ++p) tmp[p] += gp[p];
+            /* the surface-tension source with the sign that the Stage-1
+             * pressure balances (Eq. hydro-pressure): p_hs of Eq. ph_disc has
+             * gradient -s_t for kappa = +div n, so s_t enters as +f(s_t; w_m) */
             apply(st[c], rg[c], WM, gp);
-            for (size_t p = 0; p < n; ++p) tmp[p] -= gp[p];
+            for (size_t p = 0; p < n; ++p) tmp[p] += gp[p];
             if (c == 2) {
                 for (size_t p = 0; p < n; ++p) src[p] = -P->g * rho[p];
                 apply(src, RULE_EVEN, WM, gp);
@@ -346,72 +496,11 @@ int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C
     }
 
     /* ---- Stage 3: non-hydrostatic correction, Eqs. ph_disc2, vel-cor ---- */
-    double *dp = alloc();
-    for (int it = 0; it < P->n_corr; ++it) {
-        for (size_t p = 0; p < n; ++p) b[p] = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            for (size_t p = 0; p < n; ++p) tmp2[p] = rho[p] * qt[d][p];
-            apply(tmp2, rv[d], WD[d], tmp);
-            for (size_t p = 0; p < n; ++p) b[p] -= tmp[p] / dt;
-            apply(rho, RULE_EVEN, WD[d], tmp);
-            for (size_t p = 0; p < n; ++p) b[p] += qt[d][p] * tmp[p] / dt;
-        }
-        for (size_t p = 0; p < n; ++p) dp[p] = 0.0;
-        solve_pressure(Hr, b, dp, P->mg_cycles, info);
-        for (int d = 0; d < 3; ++d) {
-            apply(dp, RULE_PNH, WD[d], tmp);
-            for (size_t p = 0; p < n; ++p) qt[d][p] += -dt * (tmp[p] / ml) / rho[p];
-        }
-        for (size_t p = 0; p < n; ++p) p_nh[p] += dp[p];
-    }
+    correct(P, Hr, rho, qt, p_nh, info);
     for (int c = 0; c < 3; ++c) memcpy(q[c], qt[c], n * sizeof(double));
 
     /* ---- Stage 4: volume fraction, Eqs. Petrov-C, transport-indicator-1 ---- */
-    {
-        const double Kp = 300.0, Km = 300.0, beta = 0.1, eps_x = 1e-4, Kpos = 3.0, eps_k = 1e-7;
-        const double kmin = 1e-4 / dt * h * h, kclamp = 0.05 / dt * h * h;
-        const double *Pd[3] = {Cd[0], Cd[1], Cd[2]};
-        adv_residual(u, v, w, Pd, 2.0, adv, a);
-        double *Cp = palloc();
-        pad(C, RULE_EVEN, NULL, 0.0, Cp);
-        double *kd[3];
-        for (int d = 0; d < 3; ++d) kd[d] = alloc();
-        for (int kk = 0; kk < nz; ++kk)
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i) {
-                    size_t p = cid(i, j, kk);
-                    double c0 = Cp[pid(i, j, kk)];
-                    double S[3];
-                    S[0] = (c0 - Cp[pid(i - 1, j, kk)]) * (Cp[pid(i + 1, j, kk)] - c0);
-                    S[1] = (c0 - Cp[pid(i, j - 1, kk)]) * (Cp[pid(i, j + 1, kk)] - c0);
-                    S[2] = (c0 - Cp[pid(i, j, kk - 1)]) * (Cp[pid(i, j, kk + 1)] - c0);
-                    if (c0 > 0.95 || c0 < 0.05) S[0] = S[1] = S[2] = -1.0;
-                    double cx = Cd[0][p], cy = Cd[1][p], cz = Cd[2][p];
-                    double g2 = cx * cx + cy * cy + cz * cz;
-                    double proj = (u[p] * cx + v[p] * cy + w[p] * cz) / (eps_x + g2);
-                    double us = cx * proj, vs = cy * proj, ws = cz * proj;
-                    double kneg = -beta * (u[p] * u[p] + v[p] * v[p] + w[p] * w[p]) /
-                                  (eps_x + g2 * (fabs(us) + fabs(vs) + fabs(ws)) / 3.0);
-                    double G = fabs(cx) + fabs(cy) + fabs(cz);
-                    double kabs = (1.0 / 16.0) * h * fabs(a[p]) / (eps_k + G / 3.0);
-                    for (int d = 0; d < 3; ++d) {
-                        double wp = -fmax(-1.0, fmin(0.0, Kp * S[d]));
-                        double wm = fmin(1.0, fmax(0.0, Km * S[d]));
-                        double kk2 = wp * (Kpos * kabs) + wm * (kneg / h);
-                        kd[d][p] = fmax(-kmin, fmin(kclamp, kk2));
-                    }
-                }
-        free(Cp);
-        double *sC = alloc();
-        for (size_t p = 0; p < n; ++p) sC[p] = ml * (u[p] * Cd[0][p] + v[p] * Cd[1][p] + w[p] * Cd[2][p]);
-        for (int d = 0; d < 3; ++d) {
-            fdiff(C, RULE_EVEN, kd[d], RULE_EVEN, WPG[d], tmp);
-            for (size_t p = 0; p < n; ++p) sC[p] += tmp[p];
-        }
-        for (size_t p = 0; p < n; ++p) C[p] = C[p] - dt * sC[p] / ml;
-        for (int d = 0; d < 3; ++d) free(kd[d]);
-        free(sC);
-    }
+    vof_update(C, u, v, w, Cd, dt);
 
     or_free(Hr);
     for (int c = 0; c < 3; ++c) {
@@ -420,11 +509,11 @@ int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C
     }
     for (int d = 0; d < 3; ++d) { free(Cd[d]); free(nrm[d]); free(st[d]); }
     free(rho); free(mu); free(tmp); free(tmp2); free(b); free(kappa); free(adv); free(a); free(gp); free(src);
-    free(dp);
     return 0;
 }
 
-/* Exposed pieces for the pins. */
+/* ------------------------------------------------------------- pieces for the pins */
+
 void or_step_filters(double h, double *wx, double *wm, double *wpgx, double *wlap)
 {
     build_filters(h);
@@ -432,4 +521,96 @@ void or_step_filters(double h, double *wx, double *wm, double *wpgx, double *wla
     memcpy(wm, WM, sizeof(WM));
     memcpy(wpgx, WPG[0], sizeof(WPG[0]));
     memcpy(wlap, WLAP, sizeof(WLAP));
+}
+
+/* 1: every halo wraps and the pressure solves are periodic; 0: the tank. */
+void or_step_set_periodic(int on) { WRAP = on ? 1 : 0; }
+
+/* Curvature and surface-tension vectors of C (Eqs. surface-tension-k,
+ * surface-tension-uvw) and grad C in derivative units. */
+void or_step_surface(int nx, int ny, int nz, double h, double sigma_t, const double *C, double *Cx, double *Cy,
+                     double *Cz, double *kappa, double *stx, double *sty, double *stz)
+{
+    set_grid(nx, ny, nz, h);
+    double *Cd[3] = {Cx, Cy, Cz}, *st[3] = {stx, sty, stz}, *nrm[3], *tmp = alloc();
+    for (int d = 0; d < 3; ++d) nrm[d] = alloc();
+    surface(C, sigma_t, Cd, nrm, kappa, st, tmp);
+    for (int d = 0; d < 3; ++d) free(nrm[d]);
+    free(tmp);
+}
+
+/* Velocity diffusivity of component comp (0..2) as Stage 2 forms it from the
+ * velocity (u, v, w): a = advection residual (Eq. a_psi), k = Eq. k_Psi-n. */
+void or_step_pg_velocity(int nx, int ny, int nz, double h, int comp, const double *u, const double *v,
+                         const double *w, const double *rho, const double *mu, double *a, double *k)
+{
+    set_grid(nx, ny, nz, h);
+    const double *q[3] = {u, v, w};
+    const double ml = h * h * h;
+    size_t n = ncell();
+    int rv[6];
+    rule_vel(comp, rv);
+    double *Pd[3], *adv = alloc();
+    for (int d = 0; d < 3; ++d) {
+        Pd[d] = alloc();
+        apply(q[comp], rv, WD[d], Pd[d]);
+        for (size_t p = 0; p < n; ++p) Pd[d][p] /= ml;
+    }
+    const double *cPd[3] = {Pd[0], Pd[1], Pd[2]};
+    adv_residual(u, v, w, cPd, 2.0, adv, a);
+    pg_isotropic(u, v, w, cPd, a, rho, mu, k);
+    for (int d = 0; d < 3; ++d) free(Pd[d]);
+    free(adv);
+}
+
+/* Stage-4 diffusivities (kx, ky, kz) and the advection residual a of C. */
+void or_step_vof_coefs(int nx, int ny, int nz, double h, double dt, const double *C, const double *u,
+                       const double *v, const double *w, double *kx, double *ky, double *kz, double *a)
+{
+    set_grid(nx, ny, nz, h);
+    const double ml = h * h * h;
+    size_t n = ncell();
+    double *Cd[3], *kd[3] = {kx, ky, kz};
+    for (int d = 0; d < 3; ++d) {
+        Cd[d] = alloc();
+        apply(C, RULE_EVEN, WD[d], Cd[d]);
+        for (size_t p = 0; p < n; ++p) Cd[d][p] /= ml;
+    }
+    vof_coefs(C, u, v, w, Cd, dt, kd, a);
+    for (int d = 0; d < 3; ++d) free(Cd[d]);
+}
+
+/* Stage 4 alone: C updated in place with the velocity (u, v, w). */
+void or_step_vof(int nx, int ny, int nz, double h, double dt, double *C, const double *u, const double *v,
+                 const double *w)
+{
+    set_grid(nx, ny, nz, h);
+    const double ml = h * h * h;
+    size_t n = ncell();
+    double *Cd[3];
+    for (int d = 0; d < 3; ++d) {
+        Cd[d] = alloc();
+        apply(C, RULE_EVEN, WD[d], Cd[d]);
+        for (size_t p = 0; p < n; ++p) Cd[d][p] /= ml;
+    }
+    vof_update(C, u, v, w, Cd, dt);
+    for (int d = 0; d < 3; ++d) free(Cd[d]);
+}
+
+/* Stage 3 alone: n_corr corrections of the velocity estimate (u, v, w) in
+ * place with rho from C (Eq. rho), p_nh += dp_nh. */
+int or_step_correct(int nx, int ny, int nz, double h, const or_step_params *P, const double *C, double *u,
+                    double *v, double *w, double *p_nh, or_step_info *info)
+{
+    set_grid(nx, ny, nz, h);
+    if (info) memset(info, 0, sizeof(*info));
+    size_t n = ncell();
+    double *rho = alloc(), *q[3] = {u, v, w};
+    for (size_t p = 0; p < n; ++p) rho[p] = P->rho_l * C[p] + P->rho_g * (1.0 - C[p]);
+    or_hier *Hr = pressure_hierarchy();
+    if (!Hr) { free(rho); return -1; }
+    correct(P, Hr, rho, q, p_nh, info);
+    or_free(Hr);
+    free(rho);
+    return 0;
 }

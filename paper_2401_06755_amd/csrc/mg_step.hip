@@ -28,7 +28,11 @@
 // printed.  mu blends like Eq. rho.  The velocities take the isotropic
 // coefficient of Eq. k_Psi-n; the volume fraction the anisotropic compressive
 // coefficients of Sec. 2.3.5 with the linear detectors, evaluated with the
-// new velocity.
+// new velocity.  The surface-tension source of the momentum residual takes the
+// sign that the Stage-1 pressure balances (Eq. hydro-pressure): with the
+// curvature div n of Eq. surface-tension-k, the pressure of Eq. ph_disc has the
+// physical Laplace jump across a drop and gradient -s_t, so s_t enters the
+// predictor as +f(s_t; w_m).
 #include "mg_internal.h"
 
 #include <cmath>
@@ -446,10 +450,10 @@ __global__ __launch_bounds__(MT_X * MT_Y) void momentum_lds_kernel(Grid g, Phys 
                 }
                 s += ghs[c];
                 s += gnh[c];
-                {
+                {   // surface tension with the sign the Stage-1 pressure balances
                     Nb t;
                     gather(t, &sm[9 + c][0][0], slot, li, lj);
-                    s -= F.mass(t);
+                    s += F.mass(t);
                 }
                 if (c == 2) s -= buoy;
                 s += r0 * F.ml * adv.p[c][id];

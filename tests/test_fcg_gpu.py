@@ -3,9 +3,11 @@
 FCG(1) with one sawtooth V(0,2) cycle from zero as the preconditioner M:
 alpha = (z.r)/(p.Ap), x += alpha p, r -= alpha Ap, z = M r,
 beta = -(z.Ap)/(p.Ap), p = z + beta p.  Checks:
-* the residual history of the first iterations equals the same recurrence
-  written here with the oracle's operator and V-cycle, to 1e-9 relative per
-  entry (CG amplifies rounding differences from iteration to iteration, so
+* the residual history of the first iterations equals the oracle's FCG(1)
+  (its operator, its V-cycle, the same recurrence), to 1e-9 relative per
+  entry; the 64^3 case has three levels above the one-workgroup coarse end,
+  so its stopping rule runs inside the preconditioning cycle's first
+  restriction-chain launch (CG amplifies rounding differences from iteration to iteration, so
   the comparison stops after a few iterations);
 * converged solves satisfy the oracle's FP64 system to rtol (5% slack for
   the different summation order of the two residuals) in fewer outer
@@ -42,31 +44,11 @@ def dev(a):
 
 
 def oracle_fcg_history(work, iters):
-    """FCG(1) on the oracle's operator and V-cycle; relative residual norms."""
-    h, bc, k = work["h"], work["bc"], work["k"]
-    b = work["b"] - work["b"].mean() if all(v != D for v in bc) else work["b"]
-    OH = oracle.Hierarchy(work["shape"], h, bc, k=k)
-    A = lambda v: oracle.apply(v, h, bc, k)
-    M = lambda r: OH.vcycle(np.zeros_like(r), r)
-    x = np.zeros_like(b)
-    r = b.copy()
-    nb = np.linalg.norm(b)
-    hist = [np.linalg.norm(r) / nb]
-    z = M(r)
-    p = z.copy()
-    rho = np.vdot(z, r)
-    for _ in range(iters):
-        q = A(p)
-        pq = np.vdot(p, q)
-        a = rho / pq
-        x += a * p
-        r -= a * q
-        hist.append(np.linalg.norm(r) / nb)
-        z = M(r)
-        beta = -np.vdot(z, q) / pq
-        rho = np.vdot(z, r)
-        p = z + beta * p
-    return np.array(hist), x
+    """The oracle's FCG(1) (cycle from zero as preconditioner), fixed count."""
+    OH = oracle.Hierarchy(work["shape"], work["h"], work["bc"], k=work["k"])
+    x, hist, st = OH.fcg(work["b"], max_iter=iters, fixed=True)
+    assert st == 0
+    return hist, x
 
 
 def sphere_work(shape, bc, seed):
@@ -77,7 +59,8 @@ def sphere_work(shape, bc, seed):
                 b=inputs.gaussian(shape, seed, zero_mean=False))
 
 
-@pytest.mark.parametrize("shape,bc", [((32, 32, 32), (N,) * 6), ((48, 16, 32), (N, N, N, N, N, D))])
+@pytest.mark.parametrize("shape,bc", [((32, 32, 32), (N,) * 6), ((48, 16, 32), (N, N, N, N, N, D)),
+                                      ((64, 64, 64), (N, N, N, N, N, D))])
 def test_fcg_history_matches_oracle_recurrence(mg, shape, bc):
     work = sphere_work(shape, bc, seed=11)
     iters = 6
@@ -90,8 +73,6 @@ def test_fcg_history_matches_oracle_recurrence(mg, shape, bc):
     assert len(got) == iters + 1
     np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-13)
     x = xd.cpu().numpy().reshape(work["b"].shape)
-    if all(v != D for v in bc):
-        xw = xw - xw.mean()
     assert np.max(np.abs(x - xw)) <= 1e-9 * np.abs(xw).max()
 
 

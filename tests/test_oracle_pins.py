@@ -413,3 +413,227 @@ def test_fixed_cycle_mode_and_zero_rhs():
     assert st0 == 0 and np.all(x0 == 0) and len(hist0) == 1
     _, histn, stn = H.solve(w["b"], rtol=1e-14, max_cycles=2)
     assert stn == -4 and len(histn) == 3
+
+
+# --------------------------------------------------------------------------
+# Nodal Jacobi diagonal, coefficient coarsening map, the whole V-cycle as
+# matrices assembled here from independent pieces
+# --------------------------------------------------------------------------
+
+def _pad_coef(k, bc):
+    """One-cell halo of a coefficient: nearest interior value (wrap on periodic
+    axes), axis by axis; independent of the oracle's padding."""
+    out = k
+    for ax, (lo, hi) in zip((2, 1, 0), ((bc[0], bc[1]), (bc[2], bc[3]), (bc[4], bc[5]))):
+        mode = "wrap" if (lo == P and hi == P) else "edge"
+        width = [(0, 0)] * 3
+        width[ax] = (1, 1)
+        out = np.pad(out, width, mode=mode)
+    return out
+
+
+def _link_diagonal(k, h, bc):
+    """Interior Jacobi diagonal of the link form: the sum over the 26 links of
+    (-w_s)(k_i + k_{i+s})/2, with the coefficient continued past the walls
+    (nodes not folded into the diagonal: the convolutional reading)."""
+    nz, ny, nx = k.shape
+    kp = _pad_coef(k, bc)
+    w = indep.q1_tensor_filter(h)
+    d = np.zeros_like(k)
+    for c in (-1, 0, 1):
+        for b in (-1, 0, 1):
+            for a in (-1, 0, 1):
+                if (a, b, c) == (0, 0, 0):
+                    continue
+                kn = kp[1 + c:1 + c + nz, 1 + b:1 + b + ny, 1 + a:1 + a + nx]
+                d += -w[c + 1, b + 1, a + 1] * 0.5 * (k + kn)
+    return d
+
+
+@pytest.mark.parametrize("bc", BCS_TINY)
+def test_nodal_jacobi_diagonal(bc):
+    """The nodal diagonal (Eq. k-T's coefficient of x_i): at cells away from
+    every wall it is the diagonal of the link-form matrix; at every cell it is
+    the link sum with the coefficient halo.  Dropping or mis-scaling the
+    neighbour-k term fails both."""
+    rng = np.random.default_rng(61)
+    shape = (6, 5, 7)
+    h = 0.2
+    k = np.exp(rng.uniform(-2, 2, size=shape))
+    d = oracle.diag((7, 5, 6), h, bc, k)
+    ad = indep.link_matrix(k, h, bc).diagonal().reshape(shape)
+    inner = (slice(1, -1),) * 3
+    np.testing.assert_allclose(d[inner], ad[inner], rtol=1e-14)
+    np.testing.assert_allclose(d, _link_diagonal(k, h, bc), rtol=1e-14)
+    assert np.max(np.abs(d - 8 * h / 3 * k)) > 1e-3 * np.abs(d).max()  # the neighbour term matters
+
+
+@pytest.mark.parametrize("child", [(a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)])
+def test_coarsen_k_parent_map_single_spike(child):
+    """A spike in one fine cell changes exactly its parent: the mean of the
+    eight children, or their harmonic mean."""
+    a, b, c = child
+    k = np.ones((6, 4, 8))
+    I, J, K = 2, 1, 1
+    k[2 * K + c, 2 * J + b, 2 * I + a] = 9.0
+    want = np.ones((3, 2, 4))
+    want[K, J, I] = (7.0 + 9.0) / 8.0
+    np.testing.assert_array_equal(oracle.coarsen_k(k), want)
+    want[K, J, I] = 8.0 / (7.0 + 1.0 / 9.0)
+    np.testing.assert_allclose(oracle.coarsen_k(k, harmonic=True), want, rtol=1e-15)
+
+
+def _agg_matrix(nx, ny, nz):
+    """R: coarse cell I collects its 8 children (0/1 entries)."""
+    cx, cy, cz = nx // 2, ny // 2, nz // 2
+    rows, cols = [], []
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                rows.append(i // 2 + cx * (j // 2 + cy * (k // 2)))
+                cols.append(i + nx * (j + ny * k))
+    import scipy.sparse as sp
+    return sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(cx * cy * cz, nx * ny * nz))
+
+
+def _prolong1d(nc, lo, hi):
+    """1D cell-centred linear interpolation: fine 2I+a takes 3/4 of coarse I and
+    1/4 of I-1 (a = 0) or I+1 (a = 1), the neighbour folded by the wall rule."""
+    Pm = np.zeros((2 * nc, nc))
+    for I in range(nc):
+        for a in (0, 1):
+            f = 2 * I + a
+            Pm[f, I] += 0.75
+            m, s = indep._fold_axis(I + (1 if a else -1), nc, lo, hi)
+            Pm[f, m] += 0.25 * s
+    return Pm
+
+
+def _vcycle_by_matrices(x, b, dims, h, bc, k, nu, omega=2.0 / 3.0):
+    """Sawtooth V(0, nu) written with explicit matrices: restriction of the
+    residual down every level, exact coarsest solve (minimum-norm for a
+    singular operator), then per level upwards prolongation (+ x at the
+    finest) and nu weighted-Jacobi sweeps against the level's right-hand side."""
+    import scipy.sparse as sp
+    nx, ny, nz = dims
+    L = oracle.num_levels(nx, ny, nz)
+    A, D, R, Pm, dd = [], [], [], [], []
+    kl = k
+    for l in range(L):
+        d = (nx >> l, ny >> l, nz >> l)
+        hl = h * 2 ** l
+        dd.append(d)
+        if k is None:
+            A.append(indep.kron_matrix(*d, hl, bc))
+            D.append(np.full(d[0] * d[1] * d[2], 8 * hl / 3))
+        else:
+            A.append(indep.link_matrix(kl, hl, bc))
+            D.append(_link_diagonal(kl, hl, bc).reshape(-1))
+            if l + 1 < L:
+                kl = kl.reshape(d[2] // 2, 2, d[1] // 2, 2, d[0] // 2, 2).mean(axis=(1, 3, 5))
+        if l + 1 < L:
+            R.append(_agg_matrix(*d))
+            c = (d[0] // 2, d[1] // 2, d[2] // 2)
+            Pm.append(sp.csr_matrix(np.kron(_prolong1d(c[2], bc[4], bc[5]),
+                                            np.kron(_prolong1d(c[1], bc[2], bc[3]), _prolong1d(c[0], bc[0], bc[1])))))
+    xv, bv = x.reshape(-1), b.reshape(-1)
+    rhs = [None] * L
+    rhs[0] = bv
+    if L > 1:
+        rhs[1] = R[0] @ (bv - A[0] @ xv)
+        for l in range(1, L - 1):
+            rhs[l + 1] = R[l] @ rhs[l]
+    Ac = A[L - 1].toarray()
+    if L == 1:
+        return x + (np.linalg.pinv(Ac) @ (bv - A[0] @ xv)).reshape(x.shape)
+    e = np.linalg.pinv(Ac) @ rhs[L - 1]
+    for l in range(L - 2, -1, -1):
+        y = Pm[l] @ e + (xv if l == 0 else 0.0)
+        for _ in range(nu):
+            y = y + omega * (rhs[l] - A[l] @ y) / D[l]
+        e = y
+    return e.reshape(x.shape)
+
+
+@pytest.mark.parametrize("dims,bc,nodal,nu", [
+    ((8, 8, 8), (D,) * 6, False, 2),
+    ((8, 8, 8), (N, N, N, N, N, D), True, 2),
+    ((16, 16, 16), (D, N, P, P, N, D), True, 2),
+    ((16, 16, 16), (N,) * 6, True, 2),
+    ((24, 16, 16), (D,) * 6, False, 3),
+    ((16, 8, 16), (P, P, D, D, N, N), True, 1),
+])
+def test_vcycle_equals_matrix_cycle(dims, bc, nodal, nu):
+    """One oracle V-cycle equals the cycle written with matrices assembled here
+    (aggregation R, Kronecker 3/4-1/4 prolongation with wall folding, weighted
+    Jacobi with the interior diagonal, exact coarsest solve) at two and three
+    levels.  Pre-smoothing, a skipped level, a wrong prolongation target or
+    right-hand side fails this."""
+    nx, ny, nz = dims
+    h = 1.0 / nx
+    rng = np.random.default_rng(sum(dims) + nu)
+    shape = (nz, ny, nx)
+    k = np.exp(rng.uniform(-1, 1, size=shape)) if nodal else None
+    x = rng.standard_normal(shape)
+    b = rng.standard_normal(shape)
+    if all(v != D for v in bc):
+        b -= b.mean()  # singular operator: a consistent right-hand side
+    H = oracle.Hierarchy(dims, h, bc, k=k, nu_post=nu)
+    assert H.levels in (2, 3)
+    got = H.vcycle(x, b)
+    want = _vcycle_by_matrices(x, b, dims, h, bc, k, nu)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+# --------------------------------------------------------------------------
+# The FCG(1) outer iteration
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nodal", [False, True])
+def test_fcg_identity_preconditioner_is_cg(nodal):
+    """With the identity as preconditioner FCG(1) is conjugate gradients: its
+    iterates equal scipy's CG iterates on the independently assembled matrix."""
+    import scipy.sparse.linalg as spla_
+
+    n = 16
+    h = 1.0 / n
+    bc = (D, N, N, N, N, D)
+    rng = np.random.default_rng(21)
+    shape = (n, n, n)
+    k = np.exp(rng.uniform(-1, 1, size=shape)) if nodal else None
+    b = rng.standard_normal(shape)
+    A = indep.link_matrix(k, h, bc) if nodal else indep.kron_matrix(n, n, n, h, bc)
+    H = oracle.Hierarchy((n, n, n), h, bc, k=k)
+    xs = []
+    spla_.cg(A, b.reshape(-1), x0=np.zeros(n ** 3), rtol=0.0, atol=0.0, maxiter=8,
+             callback=lambda xk: xs.append(xk.copy()))
+    for it in (1, 4, 8):
+        x, hist, st = H.fcg(b, max_iter=it, fixed=True, precond=False)
+        assert st == 0 and len(hist) == it + 1
+        np.testing.assert_allclose(x.reshape(-1), xs[it - 1], rtol=0, atol=1e-11 * np.abs(xs[it - 1]).max())
+        r = b.reshape(-1) - A @ x.reshape(-1)
+        assert abs(np.linalg.norm(r) / np.linalg.norm(b) - hist[-1]) <= 1e-10 * hist[-1]
+
+
+@pytest.mark.parametrize("bc", [(D,) * 6, (N,) * 6])
+def test_fcg_converges_to_sparse_direct_solution(bc):
+    """FCG(1) with the cycle as preconditioner reaches the sparse direct
+    solution of the independently assembled system, in fewer iterations than
+    the stationary cycle needs."""
+    n = 16
+    w = inputs.dense_sphere(n, seed=4, radius=0.3)
+    b = w["b"] - (w["b"].mean() if bc == (N,) * 6 else 0.0)
+    H = oracle.Hierarchy(w["shape"], w["h"], bc, k=w["k"])
+    x, hist, st = H.fcg(b, rtol=1e-12, max_iter=200)
+    assert st == 0 and hist[-1] <= 1e-12
+    _, hs, sts = H.solve(b, rtol=1e-12, max_cycles=2000)
+    assert sts == 0 and len(hist) < len(hs)
+    A = indep.link_matrix(w["k"], w["h"], bc)
+    if bc == (N,) * 6:
+        Ad = A.toarray()
+        xd = np.linalg.lstsq(Ad, b.reshape(-1), rcond=None)[0]
+        xd -= xd.mean()
+    else:
+        xd = spla.spsolve(A.tocsc(), b.reshape(-1))
+    xd = xd.reshape(x.shape)
+    np.testing.assert_allclose(x, xd, rtol=0, atol=1e-8 * np.abs(xd).max())
