@@ -63,9 +63,29 @@ KCLASS = {"resid": 0, "sweeps": 1, "sweep": 2}
 # HBM bytes per finest-level launch (256^3, FP64, nodal k) from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for
 # a plain 256 MiB device copy (fetch x2.0, write x1.0); the commands and raw
-# counts are in profiles/dense_sphere_256_fp64_fine_kernels.md.  Valid for each
-# kernel as profiled; a kernel changed since then has no entry (traffic null).
-MEASURED_TRAFFIC_FP64_256 = {"resid": 570.8e6, "sweeps": 635.7e6}
+# counts are in profiles/dense_sphere_256_fp64_fine_kernels.md.  Each figure
+# carries a hash of the kernel's source files as profiled; once those files
+# change, the figure no longer describes the kernel and traffic is null.
+KERNEL_SOURCES = {"resid": ("mg_stencil.hip", "mg_device.h"),
+                  "sweeps": ("mg_fused.hip", "mg_device.h")}
+MEASURED_TRAFFIC_FP64_256 = {"resid": (570.8e6, "85a0b1de8b285334"),
+                             "sweeps": (635.7e6, "4fae73de90d721fe")}
+
+
+def kernel_source_hash(cls):
+    import hashlib
+
+    m = hashlib.sha256()
+    for f in KERNEL_SOURCES[cls]:
+        with open(os.path.join(ROOT, "paper_2401_06755_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+def measured_traffic(table):
+    """Counter-measured bytes per launch of each kernel class whose sources
+    still hash to the profiled ones."""
+    return {cls: val for cls, (val, hsh) in table.items() if kernel_source_hash(cls) == hsh}
 
 
 def log(msg):
@@ -457,7 +477,7 @@ def main():
                      autotune=not args.no_autotune)
     value = r64["n"] * r64["cycles"] / r64["dt"] / 1e9
     best, roof, per_kernel = roofline(r64, "fp64",
-                                      MEASURED_TRAFFIC_FP64_256 if args.n == 256 else None)
+                                      measured_traffic(MEASURED_TRAFFIC_FP64_256) if args.n == 256 else None)
     model_bytes = cycle_model_bytes(r64["levels"], "fp64")
     out = {
         "metric": "V-cycle Gcell-updates/s (solve to relative residual 1e-8)",

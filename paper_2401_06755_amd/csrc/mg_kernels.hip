@@ -26,11 +26,6 @@ __global__ __launch_bounds__(256) void restrict_kernel(const T *f, T *c, int nx,
     }
 }
 
-// Up to three successive restrictions (sum of the 8 children) in one launch:
-// each workgroup owns a 16^3 block of the input level and writes the 8^3, 4^3
-// and 2^3 blocks of the next levels under it.  A coarse cell depends only on
-// its own children, so no workgroup waits for another.  Sums in the order of
-// restrict_kernel (x pairs, then y, then z), so the results are the same.
 // The stopping rule on the latest residual norm (thread 0 of one workgroup):
 // record the relative residual and set done / status.
 __device__ void stop_rule(SolveState *st, double sumsq)
@@ -66,6 +61,11 @@ __device__ double reduce_512(const double *p, int n, double *red)
     return s;
 }
 
+// Up to three successive restrictions (sum of the 8 children) in one launch:
+// each workgroup owns a 16^3 block of the input level and writes the 8^3, 4^3
+// and 2^3 blocks of the next levels under it.  A coarse cell depends only on
+// its own children, so no workgroup waits for another.  Sums in the order of
+// restrict_kernel (x pairs, then y, then z), so the results are the same.
 template <typename T>
 __global__ __launch_bounds__(512) void restrict_chain_kernel(const T *f, T *c1, T *c2, T *c3, int nx, int ny, int nz,
                                                              int depth, const int *done, SolveState *st,
@@ -77,10 +77,15 @@ __global__ __launch_bounds__(512) void restrict_chain_kernel(const T *f, T *c1, 
         // the chain's critical path): stopping rule of the residual the
         // previous cycle ended with, unless a stand-alone launch already took it
         __shared__ double red[8];
-        if (st->taken) {
-            if (threadIdx.x == 0) st->taken = 0;
-            return;
+        __shared__ int taken;
+        // one thread reads and clears the flag; every thread branches on the
+        // shared copy, so no wave can read it after the clear
+        if (threadIdx.x == 0) {
+            taken = st->taken;
+            st->taken = 0;
         }
+        __syncthreads();
+        if (taken) return;  // uniform
         const double s = reduce_512(partials, np, red);
         if (threadIdx.x == 0) stop_rule(st, s);
         return;

@@ -313,6 +313,9 @@ class Server:
                rtol: float = 1e-8, max_cycles: int = 1000, tag: int = 0):
         n = cfg.nx * cfg.ny * cfg.nz
         kp = _field(k, n, "k") if k is not None else None
+        # the server's slot streams are not ordered after torch's: the inputs
+        # must be complete on the device before the library copies them
+        torch.cuda.current_stream().synchronize()
         _check(lib().nn4mg_server_submit(self._h, ctypes.byref(cfg), kp, _field(b, n, "b"), _field(x, n, "x"),
                                          float(rtol), int(max_cycles), int(tag)))
         # tags need not be unique: per tag, the count of requests in flight and

@@ -59,3 +59,13 @@ def test_roofline_fields():
     assert abs(roof["frac"] - want / 8000.0) < 1e-4
     assert roof["traffic"] == 6.0e8
     assert "sweep" not in per_kernel  # classes that did not run are left out
+
+
+def test_measured_traffic_tied_to_kernel_sources():
+    # the counter figures hold only for the kernel sources they were taken on
+    cur = {cls: bench.kernel_source_hash(cls) for cls in bench.KERNEL_SOURCES}
+    table = {cls: (1.0e9, cur[cls]) for cls in cur}
+    assert bench.measured_traffic(table) == {cls: 1.0e9 for cls in cur}
+    stale = dict(table, sweeps=(1.0e9, "0" * 16))
+    got = bench.measured_traffic(stale)
+    assert "sweeps" not in got and got["resid"] == 1.0e9
