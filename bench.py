@@ -406,27 +406,99 @@ def bubble_bench(nn4mg, torch, inputs, steps, rtol):
             "tiles_per_level": r16["tiles"]}
 
 
-def cpu_baseline(work, min_seconds=10.0, max_cycles=12):
-    """FP64 V-cycles of the same workload in the oracle (single-threaded C),
-    repeated until about ten seconds of host time (a bounded sample)."""
+def _cpu_leg(threads):
+    """Runs in a child process: the oracle timed on `threads` host threads
+    (1: the parity build; more: the OpenMP build of the same sources, chosen
+    by the environment before the oracle is loaded).  Median of 5 runs of one
+    V-cycle of the 256^3 dense-sphere workload and of the whole 64^3 Poisson
+    solve to 1e-8, after one warm-up of each."""
+    import statistics
+
     import numpy as np
 
     import oracle
+    from paper_2401_06755_amd import inputs
 
-    nx, ny, nz = work["shape"]
-    OH = oracle.Hierarchy(work["shape"], work["h"], work["bc"], k=work["k"])
-    x = np.zeros_like(work["b"])
-    b = work["b"] - work["b"].mean()
-    cycles = 0
-    t0 = time.perf_counter()
-    while cycles < max_cycles and (cycles == 0 or time.perf_counter() - t0 < min_seconds):
+    out = {"threads": threads}
+    w = inputs.dense_sphere(256, seed=2)
+    OH = oracle.Hierarchy(w["shape"], w["h"], w["bc"], k=w["k"])
+    b = w["b"] - w["b"].mean()
+    x = OH.vcycle(np.zeros_like(b), b)  # warm-up
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
         x = OH.vcycle(x, b)
-        cycles += 1
-    dt = time.perf_counter() - t0
-    return {"value": round(nx * ny * nz * cycles / dt / 1e9, 5), "unit": "Gcell-updates/s", "cores": 1,
+        ts.append(time.perf_counter() - t0)
+    out["dense_sphere_256_s_per_cycle"] = statistics.median(ts)
+    p = inputs.poisson_sine_noise(64, seed=1)
+    P = oracle.Hierarchy(p["shape"], p["h"], p["bc"])
+    _, hist, _ = P.solve(p["b"], rtol=1e-8, max_cycles=100)  # warm-up
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        P.solve(p["b"], rtol=1e-8, max_cycles=100)
+        ts.append(time.perf_counter() - t0)
+    out["poisson64_solve_s"] = statistics.median(ts)
+    out["poisson64_cycles"] = len(hist) - 1
+    return out
+
+
+def _host_description():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
+def cpu_baseline(gpu_cycles_per_solve):
+    """The FP64 oracle on the host, beside the GPU: one thread (the parity
+    build as it stands) and every thread the process may use (the OpenMP
+    build; OMP_NUM_THREADS if set, else the affinity mask).  Each leg runs in
+    a child process (about 15 s on one thread); value is the all-threads
+    figure in the benchmark's unit on the 256^3 workload's V-cycles, with the
+    whole 256^3 solve projected from the median cycle time and the GPU's
+    cycle count (a whole oracle solve there takes minutes)."""
+    import subprocess
+
+    import oracle
+
+    oracle.build(force=False)
+    oracle.build_timing()
+    model, ncpu, avail = _host_description()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or avail
+    legs = {}
+    for name, t in (("one_thread", 1), ("all_threads", threads)):
+        env = dict(os.environ, OMP_NUM_THREADS=str(t))
+        if t > 1:
+            env["NN4MG_ORACLE_OPENMP"] = "1"
+        code = f"import json, bench; print(json.dumps(bench._cpu_leg({t})))"
+        p = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                           timeout=600)
+        if p.returncode != 0:
+            raise RuntimeError(f"CPU baseline leg ({t} threads) failed: {p.stderr[-2000:]}")
+        legs[name] = json.loads(p.stdout.strip().splitlines()[-1])
+    n = 256 ** 3
+    best = legs["all_threads"]
+    for leg in legs.values():
+        leg["dense_sphere_256_Gcell_updates_per_s"] = round(n / leg["dense_sphere_256_s_per_cycle"] / 1e9, 5)
+        leg["dense_sphere_256_solve_s_projected"] = round(leg["dense_sphere_256_s_per_cycle"] * gpu_cycles_per_solve, 1)
+    return {"value": best["dense_sphere_256_Gcell_updates_per_s"], "unit": "Gcell-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{cycles} FP64 V(0,2) cycles of the {nx}x{ny}x{nz} variable-density workload from x = 0, "
-                      f"{dt:.1f} s on one host core"}
+            "sample": f"median of 5 FP64 V(0,2) cycles of the 256^3 dense-sphere workload (and of 5 whole 64^3 "
+                      f"Poisson solves to 1e-8) per leg, after a warm-up; OpenMP build on {threads} threads, "
+                      f"parity build on 1",
+            "host": {"cpu_model": model, "os_cpu_count": ncpu, "threads_available": avail},
+            "legs": legs}
 
 
 def main():
@@ -552,8 +624,8 @@ def main():
         log("Eq. speed fit: time step at 64^3 .. 256^3")
         out["eq_speed"] = eq_speed_fit(nn4mg, torch)
     if not args.no_cpu_baseline:
-        log("CPU baseline: oracle, one V-cycle")
-        out["cpu_baseline"] = cpu_baseline(work)
+        log("CPU baseline: oracle on one and on all host threads")
+        out["cpu_baseline"] = cpu_baseline(r64["info"].cycles)
     print(json.dumps(out), flush=True)
 
 

@@ -43,7 +43,8 @@ enum nn4mg_status {
     NN4MG_ENOMEM = -2,     /* device or host allocation failed */
     NN4MG_EDEVICE = -3,    /* a HIP call failed */
     NN4MG_ENOTCONV = -4,   /* max_cycles reached before rtol; x is valid */
-    NN4MG_EBREAKDOWN = -5, /* non-finite residual */
+    NN4MG_EBREAKDOWN = -5, /* non-finite residual, residual above 1e3 x the first (divergence), or
+                              p.Ap <= 0 in flexible CG; x holds the last iterate */
     NN4MG_EBUSY = -6       /* server: request not admissible now */
 };
 
@@ -126,6 +127,7 @@ int nn4mg_update_coef(nn4mg_t h, const double *k_dev);
  *   norm2_out: host double receiving ||r||_2, or NULL (then no sync).
  * b is used as given (no projection, even for singular problems). */
 int nn4mg_residual(nn4mg_t h, const double *x_dev, const double *b_dev, double *r_dev, double *norm2_out);
+
 
 /* One outer iteration on x: FP64 precision: x <- V(x, b), one sawtooth
  * V(0, nu_post) cycle; reduced precisions: x <- x + V32(0, b - A x).  b is used
@@ -259,7 +261,9 @@ typedef struct {
     int mg_cycles;        /* cycles per pressure solve (paper: 20) */
     int n_corr;           /* pressure-velocity corrections (paper: 2) */
     int n_vel_iter;       /* velocity predictor iterations (paper: 2) */
-    int reserved[5];      /* zero */
+    int mg_cycles_nh;     /* cycles of each correction solve (the j of the paper's i-j strategies,
+                             Sec. 3.2, with i = n_corr); 0: mg_cycles */
+    int reserved[4];      /* zero */
 } nn4mg_step_params;
 
 typedef struct {
@@ -267,6 +271,9 @@ typedef struct {
     double relres[8];     /* final relative residual of each */
     double ms_total;      /* device time of the step (HIP events) */
     double ms_mg;         /* device time inside the pressure solves */
+    double volume;        /* sum over cells of C^{n+1} h^3 after the step: the integral of the volume
+                             fraction whose ratio to the initial one, C(t)/C0, is the mass-conservation
+                             measure of Sec. 3.2 (Fig. Multigrid_iteration) */
 } nn4mg_step_info;
 
 /* Water/air defaults: rho 1000/1, mu 1e-3/1.8e-5, g 9.81, sigma 0.07, dt 1e-4,
@@ -284,6 +291,19 @@ int nn4mg_step_create(int nx, int ny, int nz, double h, const nn4mg_step_params 
  * non-hydrostatic pressure.  Synchronous. */
 int nn4mg_step(nn4mg_step_t s, double *C, double *u, double *v, double *w, double *p_hs, double *p_nh,
                nn4mg_step_info *info);
+/* nsteps successive steps on the same fields (the time loop of Sec. 2.4, as
+ * in the mass-conservation study of Sec. 3.2).
+ *   volume: host array of nsteps + 1 doubles, or NULL; volume[0] = sum C h^3
+ *           before the first step, volume[n] after step n.
+ *   steps_done: host int (may be NULL), the steps completed.
+ *   info: host record of the last step run (may be NULL).
+ * Stops at the first failing step and returns its status: EBREAKDOWN when the
+ * volume fraction becomes non-finite (the printed scheme's corrections can
+ * amplify interface velocities by about (rho_l - rho_g) / (2 rho_g) per
+ * correction at a sharp interface); the fields then hold that step's output.
+ * Synchronous. */
+int nn4mg_step_run(nn4mg_step_t s, int nsteps, double *C, double *u, double *v, double *w, double *p_hs,
+                   double *p_nh, double *volume, int *steps_done, nn4mg_step_info *info);
 int nn4mg_step_destroy(nn4mg_step_t s);
 
 /* Release the hierarchy (synchronises its stream first).  NULL is accepted. */

@@ -21,6 +21,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = [os.path.join(_HERE, "nn4mg_oracle.c"), os.path.join(_HERE, "step_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "_liboracle.so")
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the same sources, for
+# the CPU test that runs the oracle's pins under the sanitizers (loaded instead
+# of the plain build when NN4MG_ORACLE_SANITIZED=1, with libasan preloaded).
+_SAN_PATH = os.path.join(_HERE, "_liboracle_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
 
 BC_DIRICHLET0, BC_NEUMANN0, BC_PERIODIC = 0, 1, 2
 
@@ -36,15 +41,43 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+def build_sanitized() -> str:
+    """The oracle built with ASan and UBSan (same flags otherwise)."""
+    srcs = [s for s in _SRC if os.path.exists(s)]
+    cmd = ["gcc", "-O1", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-shared", "-fPIC", *SAN_FLAGS,
+           "-o", _SAN_PATH + ".tmp", *srcs, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_SAN_PATH + ".tmp", _SAN_PATH)
+    return _SAN_PATH
+
+
+# OpenMP build of the same sources, used only to time the oracle on every host
+# core beside the GPU (the parity build above ignores the pragmas).
+_OMP_PATH = os.path.join(_HERE, "_liboracle_omp.so")
+
+
+def build_timing() -> str:
+    srcs = [s for s in _SRC if os.path.exists(s)]
+    cmd = ["gcc", "-O2", "-fopenmp", "-std=c99", "-shared", "-fPIC", "-o", _OMP_PATH + ".tmp", *srcs, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_OMP_PATH + ".tmp", _OMP_PATH)
+    return _OMP_PATH
+
+
 _lib = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build()
-        L = ctypes.CDLL(_LIB_PATH)
+        if os.environ.get("NN4MG_ORACLE_SANITIZED") == "1":
+            L = ctypes.CDLL(_SAN_PATH)
+        elif os.environ.get("NN4MG_ORACLE_OPENMP") == "1":
+            L = ctypes.CDLL(_OMP_PATH)
+        else:
+            if not os.path.exists(_LIB_PATH):
+                build()
+            L = ctypes.CDLL(_LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         i, d, vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
@@ -87,7 +120,7 @@ class StepParams(ctypes.Structure):
     _fields_ = [("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double), ("mu_l", ctypes.c_double),
                 ("mu_g", ctypes.c_double), ("g", ctypes.c_double), ("sigma_t", ctypes.c_double),
                 ("dt", ctypes.c_double), ("mg_cycles", ctypes.c_int), ("n_corr", ctypes.c_int),
-                ("n_vel_iter", ctypes.c_int)]
+                ("n_vel_iter", ctypes.c_int), ("mg_cycles_nh", ctypes.c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -118,8 +151,10 @@ def _declare_step(L):
 
 
 def step_params(rho_l=1000.0, rho_g=1.0, mu_l=1e-3, mu_g=1.8e-5, g=9.81, sigma_t=0.07, dt=1e-4, mg_cycles=20,
-                n_corr=2, n_vel_iter=2):
-    return StepParams(rho_l, rho_g, mu_l, mu_g, g, sigma_t, dt, mg_cycles, n_corr, n_vel_iter)
+                n_corr=2, n_vel_iter=2, mg_cycles_nh=0):
+    """mg_cycles: cycles of every pressure solve; mg_cycles_nh (if > 0) those
+    of the correction solves only (the j of the i-j strategies, Sec. 3.2)."""
+    return StepParams(rho_l, rho_g, mu_l, mu_g, g, sigma_t, dt, mg_cycles, n_corr, n_vel_iter, mg_cycles_nh)
 
 
 def step(state, h, params=None):

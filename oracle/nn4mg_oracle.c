@@ -14,7 +14,7 @@
  * tensor, and the variable-coefficient operator is the three-filter identity
  * of Eq. (k-T) in Sec. 2.2.4. No blocking, no fusion, no reordering.
  *
- * Readings where the paper is silent (each is listed in the design doc):
+ * Readings where the paper is silent:
  *  - cell-centred nodes, x_i = (i + 1/2) h (Fig. 1 caption);
  *  - Dirichlet-zero halo = minus the mirrored interior value, so the boundary
  *    sits on the cell face at every level (Sec. 2.3.3 / Fig. bc-applied:
@@ -73,6 +73,7 @@ static double halo_value(int bc, int coef, double mirror, double image)
 /* Copy u into the interior of up and fill the one-cell halo, x then y then z. */
 void or_pad(const double *u, int nx, int ny, int nz, const int bc[6], int coef, double *up)
 {
+    #pragma omp parallel for  /* timing build only (-fopenmp); ignored by the parity build */
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i)
@@ -124,6 +125,7 @@ void or_q1_filter(double h, double w[27])
  * weight times padded value. */
 void or_filter_apply(const double *up, int nx, int ny, int nz, const double w[27], double *out)
 {
+    #pragma omp parallel for  /* timing build only (-fopenmp); ignored by the parity build */
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -160,10 +162,12 @@ void or_apply(int nx, int ny, int nz, double h, const int bc[6], const double *k
     double *f_kx = (double *)malloc(sizeof(double) * n), *f_x = (double *)malloc(sizeof(double) * n),
            *f_k = (double *)malloc(sizeof(double) * n);
     or_pad(k, nx, ny, nz, bc, 1, kp);
+    #pragma omp parallel for  /* timing build only (-fopenmp); ignored by the parity build */
     for (size_t p = 0; p < np; ++p) kxp[p] = kp[p] * xp[p];
     or_filter_apply(kxp, nx, ny, nz, w, f_kx);
     or_filter_apply(xp, nx, ny, nz, w, f_x);
     or_filter_apply(kp, nx, ny, nz, w, f_k);
+    #pragma omp parallel for  /* timing build only (-fopenmp); ignored by the parity build */
     for (size_t p = 0; p < n; ++p) y[p] = 0.5 * (f_kx[p] + k[p] * f_x[p] - x[p] * f_k[p]);
     free(xp); free(kp); free(kxp); free(f_kx); free(f_x); free(f_k);
 }
@@ -195,6 +199,7 @@ void or_residual(int nx, int ny, int nz, double h, const int bc[6], const double
     size_t n = (size_t)nx * ny * nz;
     double *ax = (double *)malloc(sizeof(double) * n);
     or_apply(nx, ny, nz, h, bc, k, x, ax);
+    #pragma omp parallel for  /* timing build only (-fopenmp); ignored by the parity build */
     for (size_t p = 0; p < n; ++p) r[p] = b[p] - ax[p];
     free(ax);
 }
@@ -209,6 +214,7 @@ void or_jacobi(int nx, int ny, int nz, double h, const int bc[6], const double *
     or_diag(nx, ny, nz, h, bc, k, d);
     for (int s = 0; s < nsweeps; ++s) {
         or_residual(nx, ny, nz, h, bc, k, b, y, r);
+        #pragma omp parallel for  /* timing build only (-fopenmp); ignored by the parity build */
         for (size_t p = 0; p < n; ++p) y[p] += omega * r[p] / d[p];
     }
     free(d); free(r);
@@ -222,6 +228,7 @@ void or_jacobi(int nx, int ny, int nz, double h, const int bc[6], const double *
 void or_restrict(int nx, int ny, int nz, const double *r, double *rc)
 {
     int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    #pragma omp parallel for  /* timing build only (-fopenmp); ignored by the parity build */
     for (int K = 0; K < cz; ++K)
         for (int J = 0; J < cy; ++J)
             for (int I = 0; I < cx; ++I) {
@@ -243,6 +250,7 @@ void or_prolong(int cx, int cy, int cz, const int bc[6], const double *ec, doubl
     double *ep = pad_alloc(cx, cy, cz);
     or_pad(ec, cx, cy, cz, bc, 0, ep);
     const double wt[2] = {0.75, 0.25};
+    #pragma omp parallel for  /* timing build only (-fopenmp); ignored by the parity build */
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -262,6 +270,7 @@ void or_prolong(int cx, int cy, int cz, const int bc[6], const double *ec, doubl
 void or_coarsen_k(int nx, int ny, int nz, const double *k, double *kc, int harmonic)
 {
     int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    #pragma omp parallel for  /* timing build only (-fopenmp); ignored by the parity build */
     for (int K = 0; K < cz; ++K)
         for (int J = 0; J < cy; ++J)
             for (int I = 0; I < cx; ++I) {

@@ -9,7 +9,7 @@
  * w_x = G (x) M (x) M (the printed w_x of Sec. 2.2.3), w_m = M (x) M (x) M,
  * w_lap = K M M + M K M + M M K, w_xx^PG = K (x) M (x) M.
  *
- * Readings (listed in the design doc):
+ * Readings where the paper is silent, garbled or inconsistent:
  *  - Psi_x inside the Petrov-Galerkin formulas (Eqs. k-abs, k-square, a_psi,
  *    normalisation, negativek) is in derivative units, f(Psi; w_x) / m_l;
  *    the residuals (Eqs. Petrov, Petrov-Cs, ph_disc, ph_disc2) use the filters
@@ -47,6 +47,7 @@ enum { R_EVEN = 0, R_ODD = 1, R_AFFINE = 2 };
 typedef struct {
     double rho_l, rho_g, mu_l, mu_g, g, sigma_t, dt;
     int mg_cycles, n_corr, n_vel_iter;
+    int mg_cycles_nh; /* cycles of each correction solve (the j of the i-j strategies, Sec. 3.2); 0: mg_cycles */
 } or_step_params;
 
 typedef struct {
@@ -321,7 +322,7 @@ static void correct(const or_step_params *P, or_hier *Hr, const double *rho, dou
             for (size_t p = 0; p < n; ++p) b[p] += q[d][p] * tmp[p] / dt;
         }
         for (size_t p = 0; p < n; ++p) dp[p] = 0.0;
-        solve_pressure(Hr, b, dp, P->mg_cycles, info);
+        solve_pressure(Hr, b, dp, P->mg_cycles_nh > 0 ? P->mg_cycles_nh : P->mg_cycles, info);
         for (int d = 0; d < 3; ++d) {
             apply(dp, RULE_PNH, WD[d], tmp);
             for (size_t p = 0; p < n; ++p) q[d][p] += -dt * (tmp[p] / ml) / rho[p];

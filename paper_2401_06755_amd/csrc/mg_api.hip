@@ -1120,9 +1120,9 @@ int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady
     StateHeader hd;
     int rc;
     if ((rc = read_header(H, &hd))) return rc;
-    if (!(hd.nb > 0.0)) {
+    if (hd.nb == 0.0) {
         HIP_TRY(launch_fill(x, n, 0.0, s));
-    } else if (H->singular) {
+    } else if (H->singular && hd.status != -5) {
         HIP_TRY(launch_sum_partials(x, n, nullptr, 1, H->partials, s));
         HIP_TRY(launch_reduce(H->partials, sum_blocks(n), 1.0 / (double)n, H->scal + 1, s));
         HIP_TRY(launch_sub_scalar(x, n, H->scal + 1, s));
@@ -1133,7 +1133,9 @@ int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady
     prof_close_solve(H, S.nres - 1, S.nb > 0.0);
     int status = NN4MG_OK;
     if (S.status == -4) status = fail(NN4MG_ENOTCONV, "max_cycles reached before rtol");
-    if (S.status == -5) status = fail(NN4MG_EBREAKDOWN, "non-finite residual");
+    if (S.status == -5)
+        status = fail(NN4MG_EBREAKDOWN, "breakdown: non-finite residual, residual grown past 1e3 times the first, "
+                                         "or a non-positive p.Ap in flexible CG");
     if (info) {
         info->cycles = S.nres > 0 ? S.nres - 1 : 0;
         info->status = status;

@@ -27,7 +27,13 @@ __global__ __launch_bounds__(256) void restrict_kernel(const T *f, T *c, int nx,
 }
 
 // The stopping rule on the latest residual norm (thread 0 of one workgroup):
-// record the relative residual and set done / status.
+// record the relative residual and set done / status.  A non-finite residual,
+// or one that has grown past kDivergence times the first, is a breakdown: a
+// convergent cycle never grows the residual by that much, so the iteration
+// diverges (a smoother weight past its stability bound, a coarse operator the
+// cycle cannot use) and further cycles only overflow.
+constexpr double kDivergence = 1.0e3;
+
 __device__ void stop_rule(SolveState *st, double sumsq)
 {
     const double rel = sqrt(sumsq) / st->nb;
@@ -35,7 +41,7 @@ __device__ void stop_rule(SolveState *st, double sumsq)
     if (idx < 512) st->hist[idx] = rel;
     st->last = rel;
     st->nres = idx + 1;
-    if (!isfinite(rel)) {
+    if (!isfinite(rel) || (idx > 0 && rel > kDivergence * st->hist[0])) {
         st->done = 1;
         st->status = -5;
     } else if (!st->fixed && rel <= st->rtol) {
@@ -256,7 +262,14 @@ __global__ void set_nb_kernel(SolveState *st, const double *sumsq)
 {
     const double nb = sqrt(*sumsq);
     st->nb = nb;
-    if (!(nb > 0.0)) {
+    if (!isfinite(nb)) {
+        // a non-finite right-hand side: breakdown before any cycle, x untouched
+        st->done = 1;
+        st->status = -5;
+        st->hist[0] = nb;
+        st->last = nb;
+        st->nres = 1;
+    } else if (!(nb > 0.0)) {
         st->done = 1;
         st->hist[0] = 0.0;
         st->last = 0.0;

@@ -587,6 +587,8 @@ struct nn4mg_stepper {
     nn4mg_t P = nullptr;       // constant-coefficient pressure hierarchy
     double *mem = nullptr;     // all work fields, one allocation
     double *rho, *mu, *Cd[3], *nrm[3], *st[3], *b, *px, *qa[3], *qb[3], *qt[3], *adv[3], *kq[3], *tmp;
+    double *red = nullptr;     // per-block partials of sum C, then the volume (last entry)
+    int nred = 0;
     hipEvent_t ev[4]{};        // step start / end, solve start / end
 };
 
@@ -614,11 +616,11 @@ dim3 mom_grid(const Grid &g)
 
 // Fixed-cycle solve of A x = b on the pressure hierarchy; the work pair
 // (b, px) is the same for every solve, so a captured cycle stays valid.
-int pressure_solve(nn4mg_stepper *S, int slot, nn4mg_step_info *info, float *ms_mg)
+int pressure_solve(nn4mg_stepper *S, int slot, int cycles, nn4mg_step_info *info, float *ms_mg)
 {
     nn4mg_info si;
     STEP_TRY(hipEventRecord(S->ev[2], S->s), "hipEventRecord");
-    int rc = nn4mg_solve(S->P, S->b, S->px, 0.0, S->p.mg_cycles, 1, &si);
+    int rc = nn4mg_solve(S->P, S->b, S->px, 0.0, cycles, 1, &si);
     if (rc != NN4MG_OK && rc != NN4MG_ENOTCONV) return rc;
     STEP_TRY(hipEventRecord(S->ev[3], S->s), "hipEventRecord");
     STEP_TRY(hipEventSynchronize(S->ev[3]), "hipEventSynchronize");
@@ -632,6 +634,15 @@ int pressure_solve(nn4mg_stepper *S, int slot, nn4mg_step_info *info, float *ms_
     return NN4MG_OK;
 }
 
+// sum C h^3 over the grid into S->red[S->nred] (fixed-order block partials)
+int enqueue_volume(nn4mg_stepper *S, const double *C)
+{
+    const double h = S->g.h;
+    STEP_TRY(launch_sum_partials(C, S->g.n, nullptr, 1, S->red, S->s), "sum partials");
+    STEP_TRY(launch_reduce(S->red, S->nred, h * h * h, S->red + S->nred, S->s), "reduce");
+    return NN4MG_OK;
+}
+
 int check_params(const nn4mg_step_params *p)
 {
     if (!p) return set_error(NN4MG_EINVAL, "params is NULL");
@@ -640,6 +651,9 @@ int check_params(const nn4mg_step_params *p)
     if (!(p->dt > 0.0)) return set_error(NN4MG_EINVAL, "dt must be > 0");
     if (!std::isfinite(p->g) || !std::isfinite(p->sigma_t)) return set_error(NN4MG_EINVAL, "g, sigma_t must be finite");
     if (p->mg_cycles < 1 || p->mg_cycles > 511) return set_error(NN4MG_EINVAL, "mg_cycles must be in [1, 511]");
+    if (p->mg_cycles_nh < 0 || p->mg_cycles_nh > 511) return set_error(NN4MG_EINVAL, "mg_cycles_nh must be in [0, 511]");
+    for (int i = 0; i < 4; ++i)
+        if (p->reserved[i] != 0) return set_error(NN4MG_EINVAL, "reserved fields must be zero");
     if (p->n_corr < 0 || p->n_corr > 7) return set_error(NN4MG_EINVAL, "n_corr must be in [0, 7]");
     if (p->n_vel_iter < 1 || p->n_vel_iter > 64) return set_error(NN4MG_EINVAL, "n_vel_iter must be in [1, 64]");
     return NN4MG_OK;
@@ -672,6 +686,7 @@ int nn4mg_step_destroy(nn4mg_step_t S)
     else (void)hipDeviceSynchronize();
     if (S->P) nn4mg_destroy(S->P);
     if (S->mem) (void)hipFree(S->mem);
+    if (S->red) (void)hipFree(S->red);
     for (auto &e : S->ev)
         if (e) (void)hipEventDestroy(e);
     delete S;
@@ -728,6 +743,13 @@ int nn4mg_step_create(int nx, int ny, int nz, double h, const nn4mg_step_params 
     for (int d = 0; d < 3; ++d) S->adv[d] = take();
     for (int d = 0; d < 3; ++d) S->kq[d] = take();
     S->tmp = take();
+    S->nred = sum_blocks(n);
+    if ((e = hipMalloc((void **)&S->red, (size_t)(S->nred + 1) * sizeof(double))) != hipSuccess) {
+        (void)hipGetLastError();
+        S->red = nullptr;
+        nn4mg_step_destroy(S);
+        return set_error(NN4MG_ENOMEM, "step reduction buffer: hipMalloc failed");
+    }
     for (auto &ev : S->ev)
         if ((e = hipEventCreate(&ev)) != hipSuccess) {
             ev = nullptr;
@@ -771,7 +793,7 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     hipLaunchKernelGGL(rhs_hydrostatic_kernel, grid, blk, 0, s, g, p.g, c3(S->st), (const double *)S->rho, S->b);
     STEP_TRY(hipGetLastError(), "step kernels");
     STEP_TRY(hipMemcpyAsync(S->px, p_hs, g.n * sizeof(double), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
-    if ((rc = pressure_solve(S, 0, info, &ms_mg))) return rc;
+    if ((rc = pressure_solve(S, 0, p.mg_cycles, info, &ms_mg))) return rc;
     STEP_TRY(hipMemcpyAsync(p_hs, S->px, g.n * sizeof(double), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
 
     // Stage 2: velocity predictor iterations, q^ from q^n
@@ -806,7 +828,8 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
         hipLaunchKernelGGL(rhs_nonhydrostatic_kernel, grid, blk, 0, s, g, p.dt, c3(qin), (const double *)S->rho,
                            S->b);
         STEP_TRY(launch_fill(S->px, g.n, 0.0, s), "fill");
-        if ((rc = pressure_solve(S, 1 + it, info, &ms_mg))) return rc;
+        if ((rc = pressure_solve(S, 1 + it, p.mg_cycles_nh > 0 ? p.mg_cycles_nh : p.mg_cycles, info, &ms_mg)))
+            return rc;
         hipLaunchKernelGGL(correct_kernel, grid, blk, 0, s, g, p.dt, (const double *)S->px, (const double *)S->rho,
                            c3(qin), f3(q), p_nh);
         qin = q;
@@ -822,12 +845,42 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     STEP_TRY(hipMemcpyAsync(C, S->b, g.n * sizeof(double), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
     STEP_TRY(hipGetLastError(), "step kernels");
     STEP_TRY(hipEventRecord(S->ev[1], s), "hipEventRecord");
-    STEP_TRY(hipEventSynchronize(S->ev[1]), "hipEventSynchronize");
+    // the volume of fluid after the step, sum C h^3 (the integral of C^{n+1})
+    double vol = 0.0;
+    if ((rc = enqueue_volume(S, C))) return rc;
+    STEP_TRY(hipMemcpyAsync(&vol, S->red + S->nred, sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    STEP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (info) {
         float ms = 0.0f;
         STEP_TRY(hipEventElapsedTime(&ms, S->ev[0], S->ev[1]), "hipEventElapsedTime");
         info->ms_total = ms;
         info->ms_mg = ms_mg;
+        info->volume = vol;
+    }
+    if (!std::isfinite(vol)) return set_error(NN4MG_EBREAKDOWN, "non-finite volume fraction after the step");
+    return NN4MG_OK;
+}
+
+int nn4mg_step_run(nn4mg_step_t S, int nsteps, double *C, double *u, double *v, double *w, double *p_hs, double *p_nh,
+                   double *volume, int *steps_done, nn4mg_step_info *info)
+{
+    if (!S || !C || !u || !v || !w || !p_hs || !p_nh) return set_error(NN4MG_EINVAL, "NULL argument");
+    if (nsteps < 0) return set_error(NN4MG_EINVAL, "nsteps must be >= 0");
+    if (steps_done) *steps_done = 0;
+    int rc;
+    if (volume) {
+        if ((rc = enqueue_volume(S, C))) return rc;
+        STEP_TRY(hipMemcpyAsync(volume, S->red + S->nred, sizeof(double), hipMemcpyDeviceToHost, S->s),
+                 "hipMemcpyAsync");
+        STEP_TRY(hipStreamSynchronize(S->s), "hipStreamSynchronize");
+    }
+    nn4mg_step_info si;
+    for (int n = 0; n < nsteps; ++n) {
+        rc = nn4mg_step(S, C, u, v, w, p_hs, p_nh, &si);
+        if (info) *info = si;
+        if (volume && (rc == NN4MG_OK || rc == NN4MG_EBREAKDOWN)) volume[n + 1] = si.volume;
+        if (rc) return rc;
+        if (steps_done) *steps_done = n + 1;
     }
     return NN4MG_OK;
 }

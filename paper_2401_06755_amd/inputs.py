@@ -134,3 +134,20 @@ def water_block(nx: int = 128, ny: int | None = None, nz: int | None = None, x1:
     C = np.ascontiguousarray(np.broadcast_to(C, (nz, ny, nx)))
     zero = np.zeros((nz, ny, nx))
     return h, dict(C=C, u=zero.copy(), v=zero.copy(), w=zero.copy(), p_hs=zero.copy(), p_nh=zero.copy())
+
+
+def bubble_state(nx: int = 32, ny: int | None = None, nz: int | None = None, radius: float = 1.0 / 6.0,
+                 centre_z: float = 1.0 / 3.0):
+    """Rising air bubble in a water tank for the time step (Sec. 3.2 set-up,
+    scaled to a box of width 1): nx x ny x nz cells of h = 1/nx (default
+    1 x 1 x 2 box), water (C = 1) everywhere except a sphere of radius 1/6 at
+    (1/2, 1/2, 1/3) (the paper's bubble of radius H/2 at height H in a
+    3H x 3H x 6H tank), two-cell linear ramp; fluid at rest, pressures zero.
+    Returns (h, dict of (nz, ny, nx) arrays)."""
+    ny = nx if ny is None else ny
+    nz = 2 * nx if nz is None else nz
+    h = 1.0 / nx
+    C = 1.0 - sphere_fraction((nx, ny, nz), h, (0.5, 0.5 * ny * h, centre_z), radius)
+    zero = np.zeros((nz, ny, nx))
+    return h, dict(C=np.ascontiguousarray(C), u=zero.copy(), v=zero.copy(), w=zero.copy(), p_hs=zero.copy(),
+                   p_nh=zero.copy())

@@ -82,7 +82,7 @@ class StepParams(ctypes.Structure):
         ("mu_l", ctypes.c_double), ("mu_g", ctypes.c_double),
         ("g", ctypes.c_double), ("sigma_t", ctypes.c_double), ("dt", ctypes.c_double),
         ("mg_cycles", ctypes.c_int), ("n_corr", ctypes.c_int), ("n_vel_iter", ctypes.c_int),
-        ("reserved", ctypes.c_int * 5),
+        ("mg_cycles_nh", ctypes.c_int), ("reserved", ctypes.c_int * 4),
     ]
 
 
@@ -90,7 +90,7 @@ class StepInfo(ctypes.Structure):
     _fields_ = [
         ("solves", ctypes.c_int),
         ("relres", ctypes.c_double * 8),
-        ("ms_total", ctypes.c_double), ("ms_mg", ctypes.c_double),
+        ("ms_total", ctypes.c_double), ("ms_mg", ctypes.c_double), ("volume", ctypes.c_double),
     ]
 
 
@@ -156,6 +156,9 @@ def lib():
     L.nn4mg_step_create.argtypes = [i, i, i, d, stp, vp, ctypes.POINTER(vp)]
     L.nn4mg_step.restype = i
     L.nn4mg_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(StepInfo)]
+    L.nn4mg_step_run.restype = i
+    L.nn4mg_step_run.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, ctypes.POINTER(d), ctypes.POINTER(i),
+                                 ctypes.POINTER(StepInfo)]
     L.nn4mg_step_destroy.restype = i
     L.nn4mg_step_destroy.argtypes = [vp]
     L.nn4mg_destroy.restype = i
@@ -394,6 +397,22 @@ class Stepper:
         info = StepInfo()
         _check(lib().nn4mg_step(self._h, *ptrs, ctypes.byref(info)))
         return info
+
+    def run(self, state: dict, nsteps: int, raise_on_breakdown: bool = True):
+        """nsteps steps in place (nn4mg_step_run).  Returns (volumes, steps
+        done, info of the last step): volumes[n] = sum C h^3 after step n,
+        volumes[0] before the first."""
+        if not self._h:
+            raise RuntimeError("stepper destroyed")
+        ptrs = [_field(state[k], self.n, k) for k in STEP_FIELDS]
+        vol = (ctypes.c_double * (int(nsteps) + 1))()
+        done = ctypes.c_int(0)
+        info = StepInfo()
+        code = lib().nn4mg_step_run(self._h, int(nsteps), *ptrs, vol, ctypes.byref(done), ctypes.byref(info))
+        if not (code == NN4MG_EBREAKDOWN and not raise_on_breakdown):
+            _check(code)
+        n = done.value + (1 if code == NN4MG_EBREAKDOWN else 0)
+        return [vol[i] for i in range(n + 1)], done.value, info
 
     def close(self):
         if getattr(self, "_h", None):

@@ -111,3 +111,38 @@ def test_constant_coefficient_mixed(mg):
 def test_fp16_needs_nodal(mg):
     with pytest.raises(mg.Nn4mgError):
         mg.Hierarchy(mg.config_default(16, 16, 16, 1 / 16, precision=2))
+
+
+@pytest.mark.parametrize("shape,bc", [((32, 32, 32), (N, N, N, N, N, D)), ((48, 16, 32), (D, N, P, P, N, N))])
+def test_fp16_storage_exact_coefficients_bitwise_fp32(mg, shape, bc):
+    """k in {0.5, 1}: the means of 8 children on every coarser level are
+    multiples of 2^-4, 2^-7, 2^-10 in [0.5, 1], all exact in FP16 (spacing
+    2^-11 there), so the FP16-stored coefficient holds the same values as the
+    FP32 copy on every level.  The FP16_COEF cycle must then equal the
+    FP32_SMOOTH cycle bit for bit (one cycle and ten fixed cycles), and both
+    stay within the FP32 bar of the oracle's FP64 cycle."""
+    import torch
+
+    nx, ny, nz = shape
+    h = 1.0 / nx
+    rng = np.random.default_rng(21)
+    k = np.where(rng.random((nz, ny, nx)) < 0.5, 0.5, 1.0)
+    b = inputs.gaussian((nx, ny, nz), 22, zero_mean=False)
+    x0 = rng.standard_normal(b.shape)
+    out = {}
+    for prec in (1, 2):
+        cfg = mg.config_default(nx, ny, nz, h, bc=bc, coef_mode=1, precision=prec)
+        H = mg.Hierarchy(cfg, dev(k))
+        assert len(H.levels()) >= 3
+        xd = dev(x0)
+        H.vcycle(dev(b), xd)
+        xs = dev(np.zeros_like(b))
+        H.solve(dev(b), xs, max_cycles=10, fixed_cycles=True)
+        torch.cuda.synchronize()
+        out[prec] = (host(xd, b.shape), host(xs, b.shape))
+        H.close()
+    np.testing.assert_array_equal(out[2][0], out[1][0])
+    np.testing.assert_array_equal(out[2][1], out[1][1])
+    want = oracle.Hierarchy(shape, h, bc, k=k).vcycle(x0, b)
+    corr = want - x0
+    assert np.max(np.abs((out[2][0] - x0) - corr)) <= 2e-5 * np.abs(corr).max()

@@ -62,6 +62,7 @@ def assert_fields_close(got, want, tol):
             scale = max(scale, vel)
         scale = max(scale, 1e-300)
         err = np.abs(got[k] - want[k]).max()
+        print(f"  {k}: max rel diff {err / scale:.2e}", flush=True)
         assert np.all(np.isfinite(got[k])), k
         assert err <= tol * scale, f"{k}: max err {err:.3e} vs scale {scale:.3e} (rel {err / scale:.3e})"
 

@@ -1,0 +1,100 @@
+"""The time loop (nn4mg_step_run) against the oracle's step applied in turn,
+with the volume diagnostic of the mass-conservation study (Sec. 3.2,
+Fig. Multigrid_iteration: C(t)/C0 with C(t) the integral of C^n).
+
+Reduced rising bubble (inputs.bubble_state: an air bubble of radius H/2 at
+height H in a 3H x 3H x 6H water tank, here 16 x 16 x 32 cells of a 6 mm wide
+tank) at density ratio 2, where the printed correction does not amplify
+interface velocities, for two of the paper's i-j strategies (i corrections,
+j cycles per correction solve).  Bar: every field after 3 steps within 1e-9 of
+its largest oracle value (the bar of the single-step parity tests), and the
+volume after every step within 1e-10 relative of the oracle's sum C h^3.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_06755_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("C", "u", "v", "w", "p_hs", "p_nh")
+WIDTH = 6e-3
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_06755_amd import nn4mg
+
+    nn4mg.lib()
+    return nn4mg
+
+
+@pytest.mark.parametrize("i,j", [(1, 10), (2, 20)])
+def test_three_steps_and_volume_match_oracle(mg, i, j):
+    import torch
+
+    nx = 16
+    _, st = inputs.bubble_state(nx)
+    h = WIDTH / nx
+    params = dict(rho_g=500.0, dt=1e-5, n_corr=i, mg_cycles=20, mg_cycles_nh=j)
+    print(f"step run bubble 16x16x32 strategy {i}-{j}", flush=True)
+    nz, ny, _ = st["C"].shape
+    dev = {k: torch.from_numpy(np.ascontiguousarray(st[k]).reshape(-1).copy()).cuda() for k in FIELDS}
+    S = mg.Stepper(nx, ny, nz, h, mg.step_params(**params))
+    vols, done, info = S.run(dev, 3)
+    torch.cuda.synchronize()
+    S.close()
+    assert done == 3 and len(vols) == 4 and info.solves == 1 + i
+    got = {k: dev[k].cpu().numpy().reshape(nz, ny, nx) for k in FIELDS}
+    ref = {k: np.ascontiguousarray(st[k]).copy() for k in FIELDS}
+    want_vol = [ref["C"].sum() * h ** 3]
+    for _ in range(3):
+        oracle.step(ref, h, oracle.step_params(**params))
+        want_vol.append(ref["C"].sum() * h ** 3)
+    vel = max(np.abs(ref[q]).max() for q in ("u", "v", "w"))
+    for k in FIELDS:
+        scale = max(np.abs(ref[k]).max(), vel if k in ("u", "v", "w") else 0.0, 1e-300)
+        err = np.abs(got[k] - ref[k]).max()
+        print(f"  {k}: max rel diff {err / scale:.2e}", flush=True)
+        assert err <= 1e-9 * scale, (k, err / scale)
+    np.testing.assert_allclose(vols, want_vol, rtol=1e-10, atol=0)
+
+
+def test_run_reports_breakdown(mg):
+    """The printed scheme at density ratio 1000 on a sharp bubble: the
+    corrections amplify the interface velocities until the fields overflow
+    (the oracle does the same within six steps); the loop stops there with
+    EBREAKDOWN and reports the steps it completed."""
+    import torch
+
+    nx = 16
+    h, st = inputs.bubble_state(nx)
+    nz, ny, _ = st["C"].shape
+    dev = {k: torch.from_numpy(np.ascontiguousarray(st[k]).reshape(-1).copy()).cuda() for k in FIELDS}
+    S = mg.Stepper(nx, ny, nz, h, mg.step_params())
+    vols, done, info = S.run(dev, 40, raise_on_breakdown=False)
+    S.close()
+    assert done < 40 and not np.isfinite(vols[-1]) and np.all(np.isfinite(vols[:-1]))
+    with pytest.raises(mg.Nn4mgError) as e:
+        S2 = mg.Stepper(nx, ny, nz, h, mg.step_params())
+        _, st2 = inputs.bubble_state(nx)
+        dev2 = {k: torch.from_numpy(np.ascontiguousarray(st2[k]).reshape(-1).copy()).cuda() for k in FIELDS}
+        try:
+            S2.run(dev2, 40)
+        finally:
+            S2.close()
+    assert e.value.code == mg.NN4MG_EBREAKDOWN
+
+
+def test_step_params_reserved_and_ranges(mg):
+    with pytest.raises(mg.Nn4mgError):
+        mg.Stepper(16, 16, 32, WIDTH / 16, mg.step_params(mg_cycles_nh=-1))
+    p = mg.step_params()
+    p.reserved[0] = 1
+    with pytest.raises(mg.Nn4mgError):
+        mg.Stepper(16, 16, 32, WIDTH / 16, p)
