@@ -128,6 +128,26 @@ int nn4mg_update_coef(nn4mg_t h, const double *k_dev);
  * b is used as given (no projection, even for singular problems). */
 int nn4mg_residual(nn4mg_t h, const double *x_dev, const double *b_dev, double *r_dev, double *norm2_out);
 
+/* nn4mg_residual without a hierarchy and without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same kernel and launch shape as
+ * nn4mg_residual on a hierarchy set up from cfg, so r and the norm are the same.
+ *   cfg: as for nn4mg_setup (validated the same way).
+ *   k_dev: nx*ny*nz device doubles (> 0, not checked) iff coef_mode == NODAL;
+ *          read in place (not copied); ignored for CONST.
+ *   x_dev, b_dev, r_dev, norm2_out: as for nn4mg_residual.
+ *   hip_stream: the hipStream_t to enqueue on (NULL = the null stream); with
+ *          norm2_out the call synchronises it.
+ * The per-workgroup norm partials live in a static device array of 2 MiB that
+ * each GPU holds until the process ends (at most 262144 residual workgroups,
+ * about 8.6e9 cells at the default launch shape; larger grids get EINVAL when
+ * a norm is asked for).  Calls on one GPU share that array: calls that overlap
+ * on one GPU (several host threads or streams) race on it.
+ * Errors: EINVAL (bad cfg, NULL x/b, NULL k for NODAL, too many workgroups),
+ * EDEVICE. */
+int nn4mg_residual_noalloc(const nn4mg_config *cfg, const double *k_dev, const double *x_dev, const double *b_dev,
+                           double *r_dev, double *norm2_out, void *hip_stream);
+
 
 /* One outer iteration on x: FP64 precision: x <- V(x, b), one sawtooth
  * V(0, nu_post) cycle; reduced precisions: x <- x + V32(0, b - A x).  b is used

@@ -16,6 +16,7 @@
 #include <cstddef>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -975,6 +976,88 @@ int nn4mg_residual(nn4mg_t H, const double *x, const double *b, double *r, doubl
         HIP_TRY(hipMemcpyAsync(&s, H->scal, sizeof(double), hipMemcpyDeviceToHost, H->stream));
         HIP_TRY(hipStreamSynchronize(H->stream));
         *norm2_out = std::sqrt(s);
+    }
+    return NN4MG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free residual
+// Device memory of nn4mg_residual_noalloc: the residual kernel's per-workgroup
+// sums of r^2 and the reduced sum.  Each GPU holds its own copy for the life
+// of the process; calls on one GPU share it.
+constexpr int kStaticPartials = 1 << 18;                 // workgroups of one residual launch, at most
+constexpr int kStaticDoubles = kStaticPartials + 32;     // + the reduced sum (own 256-byte line)
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current; the host-side name is not a device address).
+int static_scratch(double **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(NN4MG_EDEVICE, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(NN4MG_EDEVICE, "hipGetSymbolAddress returned NULL for the static scratch");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NN4MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nn4mg_residual_noalloc(const nn4mg_config *cfg, const double *k_dev, const double *x_dev, const double *b_dev,
+                           double *r_dev, double *norm2_out, void *hip_stream)
+{
+    int rc;
+    if ((rc = validate(cfg))) return rc;
+    if (!x_dev || !b_dev) return fail(NN4MG_EINVAL, "NULL argument");
+    const bool nodal = cfg->coef_mode == NN4MG_COEF_NODAL;
+    if (nodal && !k_dev) return fail(NN4MG_EINVAL, "nodal coefficient mode needs k");
+    const int L = count_levels(cfg->nx, cfg->ny, cfg->nz, cfg->min_coarse);
+    const bool mixed = cfg->precision != NN4MG_PREC_FP64;
+    StencilArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g.nx = cfg->nx;
+    a.g.ny = cfg->ny;
+    a.g.nz = cfg->nz;
+    for (int f = 0; f < 6; ++f) a.g.bc[f] = cfg->bc[f];
+    // the launch shape nn4mg_setup gives the finest residual of this config
+    a.t = default_tiles_for(cfg->nx, cfg->ny, cfg->nz, NN4MG_KCLASS_FINE_RESID, mixed, cfg->nu_post == 2 && L >= 2);
+    a.h = cfg->h;
+    a.omega = cfg->omega;
+    a.yin = x_dev;
+    a.b = b_dev;
+    a.k = nodal ? k_dev : nullptr;
+    a.r = r_dev;
+    const int nblk = a.t.blocks();
+    if (norm2_out && nblk > kStaticPartials)
+        return fail(NN4MG_EINVAL, "grid needs " + std::to_string(nblk) + " residual workgroups; the static scratch holds " +
+                                      std::to_string(kStaticPartials));
+    double *ptr = nullptr;
+    if (norm2_out && (rc = static_scratch(&ptr))) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    a.partials = norm2_out ? ptr : nullptr;
+    HIP_TRY(launch_stencil(1, nodal ? KT_F64 : KT_NONE, IN_PLAIN, OUT_RESID, 0, a, st));
+    if (norm2_out) {
+        // every workgroup writes its partial, so nothing needs clearing first
+        HIP_TRY(launch_reduce(ptr, nblk, 1.0, ptr + kStaticPartials, st));
+        double sum = 0.0;
+        HIP_TRY(hipMemcpyAsync(&sum, ptr + kStaticPartials, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        *norm2_out = std::sqrt(sum);
     }
     return NN4MG_OK;
 }

@@ -118,6 +118,8 @@ def lib():
     L.nn4mg_residual.restype = i
     L.nn4mg_residual.argtypes = [vp, vp, vp, vp, ctypes.POINTER(d)]
     L.nn4mg_vcycle.restype = i
+    L.nn4mg_residual_noalloc.restype = i
+    L.nn4mg_residual_noalloc.argtypes = [cfgp, vp, vp, vp, vp, ctypes.POINTER(d), vp]
     L.nn4mg_vcycle.argtypes = [vp, vp, vp]
     L.nn4mg_solve.restype = i
     L.nn4mg_solve.argtypes = [vp, vp, vp, d, i, i, ctypes.POINTER(Info)]
@@ -206,6 +208,20 @@ def _field(t: torch.Tensor, n: int, name: str):
     if t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def residual_noalloc(cfg: Config, x: torch.Tensor, b: torch.Tensor, k: torch.Tensor | None = None,
+                     r: torch.Tensor | None = None, norm: bool = True, stream: torch.cuda.Stream | None = None):
+    """r = b - A x on the finest level of cfg with no hierarchy and no device
+    allocation (nn4mg_residual_noalloc), on the current torch stream."""
+    n = cfg.nx * cfg.ny * cfg.nz
+    st = stream if stream is not None else torch.cuda.current_stream()
+    out = ctypes.c_double(0.0)
+    _check(lib().nn4mg_residual_noalloc(ctypes.byref(cfg), _field(k, n, "k") if k is not None else None,
+                                        _field(x, n, "x"), _field(b, n, "b"),
+                                        _field(r, n, "r") if r is not None else None,
+                                        ctypes.byref(out) if norm else None, ctypes.c_void_p(st.cuda_stream)))
+    return out.value if norm else None
 
 
 class Hierarchy:
