@@ -20,7 +20,9 @@ tolerance), the 64^3 constant-coefficient Dirichlet Poisson solve, the
 difference from the FP64 solve of the same system), one two-phase time step on
 a 128^3 collapsing column split into pressure solves and explicit stencils (and
 the same step at 64^3 .. 256^3 with M_s and H_s of Eq. speed fitted), the
-served stream of 512 solves of uneven sizes (solves/s, p50/p99 latency), and
+mass-conservation study of the i-j correction strategies over 1000 steps of a
+reduced rising bubble (C(t)/C0), the served stream of 512 solves of uneven
+sizes (solves/s, p50/p99 latency), and
 the FP64 oracle timed on the host over a bounded sample of V-cycles of the same
 workload.
 """
@@ -287,12 +289,13 @@ def serving_bench(nn4mg, torch, n_requests, budget_gib, slots, seed_base=4000):
                                                     zip(reqs, closed["cycles"])) / closed["wall"] / 1e9, 3)}
 
 
-def step_bench(nn4mg, torch, n, steps):
+def step_bench(nn4mg, torch, n, steps, order=1):
     """One full two-phase time step (Sec. 2.4 Stages 1-4) on the n^3 collapsing
     water column (water/air, 20 cycles x 3 pressure solves), each timed step
     starting from the same initial state; device time from HIP events, split
     into the pressure solves (H) and the explicit momentum/volume-fraction
-    stencils (M) like Eq. speed."""
+    stencils (M) like Eq. speed.  order 2: quadratic ConvFEM filters for the
+    momentum, interface and volume-fraction advection terms."""
     import numpy as np
 
     from paper_2401_06755_amd import inputs
@@ -300,7 +303,7 @@ def step_bench(nn4mg, torch, n, steps):
     h, st = inputs.water_block(n)
     init = {k: torch.from_numpy(np.ascontiguousarray(st[k]).reshape(-1)).cuda() for k in nn4mg.STEP_FIELDS}
     dev = {k: torch.empty_like(v) for k, v in init.items()}
-    S = nn4mg.Stepper(n, n, n, h, nn4mg.step_params())
+    S = nn4mg.Stepper(n, n, n, h, nn4mg.step_params(order=order))
     tot, mg = [], []
     for i in range(steps + 1):
         for k in dev:
@@ -316,13 +319,62 @@ def step_bench(nn4mg, torch, n, steps):
     cycles = p.mg_cycles * (1 + p.n_corr)
     return {"workload": f"collapsing water column {n}^3 (block [0,0.25]x[0,1]x[0,0.5]), water/air, "
                         f"dt 1e-4, {p.n_vel_iter} predictor iterations, {p.n_corr} corrections, "
-                        f"{p.mg_cycles} cycles per pressure solve",
+                        f"{p.mg_cycles} cycles per pressure solve, "
+                        + ("linear filters" if order != 2 else
+                           "quadratic ConvFEM filters for momentum/interface/VOF advection (p = 2)"),
             "ms_per_step": round(t, 3), "ms_pressure_solves": round(m, 3), "ms_explicit": round(t - m, 3),
             "solve_share": round(m / t, 3), "steps_timed": steps,
-            "M_s": (t - m) * 1e-3 / cells, "H_s": m * 1e-3 / (cycles * cells),
+            "p": 2 if order == 2 else 1,
+            "M_s": (t - m) * 1e-3 / (cells * (2 if order == 2 else 1)), "H_s": m * 1e-3 / (cycles * cells),
             "relres": [info.relres[i] for i in range(info.solves)],
             "paper_context": {"M_s": 1.2e-8, "H_s": 1.1e-10, "hardware": "NVIDIA A10",
                               "note": "Eq. speed coefficients: seconds per node (times polynomial order p; here p = 1)"}}
+
+
+def mass_study(nn4mg, torch, nx=32, steps=1000, ratio=2.0):
+    """The mass-conservation study of Sec. 3.2 (Fig. Multigrid_iteration):
+    C(t)/C0, C(t) = sum C^n h^3, over `steps` steps of a rising air bubble
+    (radius H/2 at height H in a 3H x 3H x 6H water tank, 6 mm wide, nx x nx x
+    2nx cells) for the i-j strategies (i corrections, j cycles per correction
+    solve; the hydrostatic solve keeps 20).  The density ratio is 2, not the
+    paper's water/air: the printed correction multiplies the light-phase
+    interface speed by about (rho_l - rho_g) / (2 rho_g) per correction, which
+    diverges within a few steps at a sharp interface once the ratio exceeds 3."""
+    import numpy as np
+
+    from paper_2401_06755_amd import inputs
+
+    width = 6e-3
+    _, st = inputs.bubble_state(nx)
+    h = width / nx
+    nz, ny = st["C"].shape[:2]
+    out = {"workload": f"rising bubble {nx}x{nx}x{2 * nx}, tank 6 mm x 6 mm x 12 mm, bubble radius 1 mm at "
+                       f"(3, 3, 2) mm, density ratio {ratio:g} (rho_l 1000), mu 1e-3/1.8e-5, sigma 0.07, "
+                       f"dt 1e-5 s, {steps} steps, 2 predictor iterations, hydrostatic solve 20 cycles",
+           "strategies": {}}
+    sample = sorted(set([0] + list(range(0, steps + 1, max(1, steps // 10))) + [steps]))
+    for i, j in ((1, 10), (2, 10), (1, 20), (2, 20)):
+        dev = {k: torch.from_numpy(np.ascontiguousarray(st[k]).reshape(-1).copy()).cuda() for k in nn4mg.STEP_FIELDS}
+        S = nn4mg.Stepper(nx, ny, nz, h, nn4mg.step_params(rho_g=1000.0 / ratio, dt=1e-5, n_corr=i, mg_cycles=20,
+                                                           mg_cycles_nh=j))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vols, done, info = S.run(dev, steps, raise_on_breakdown=False)
+        dt = time.perf_counter() - t0
+        S.close()
+        v = np.array(vols)
+        ratio_t = v / v[0]
+        out["strategies"][f"{i}-{j}"] = {
+            "steps_done": done,
+            "C_over_C0": {str(n): float(ratio_t[n]) for n in sample if n < len(ratio_t)},
+            "max_abs_drift": float(np.max(np.abs(ratio_t - 1.0))),
+            "final_drift": float(ratio_t[-1] - 1.0),
+            "ms_per_step": round(dt / max(done, 1) * 1e3, 3)}
+        log(f"  strategy {i}-{j}: {done} steps, C(t)/C0 - 1 = {ratio_t[-1] - 1.0:.3e}, "
+            f"{dt / max(done, 1) * 1e3:.2f} ms/step")
+    out["note"] = ("the paper gives this study only as a figure (no values), so the comparison is "
+                   "qualitative: more corrections (i) and more cycles (j) should conserve better")
+    return out
 
 
 def eq_speed_fit(nn4mg, torch, sizes=(64, 96, 128, 192, 256), steps=2):
@@ -517,6 +569,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--step-n", type=int, default=128, help="time-step grid edge (0: skip)")
     ap.add_argument("--step-steps", type=int, default=3)
+    ap.add_argument("--mass-steps", type=int, default=1000,
+                    help="steps per strategy of the mass-conservation study (0: skip)")
     ap.add_argument("--no-poisson64", action="store_true", help="skip the 64^3 constant-coefficient leg")
     ap.add_argument("--no-bubble", action="store_true", help="skip the 256x256x512 FP16-coefficient leg")
     ap.add_argument("--no-eq-speed", action="store_true", help="skip the multi-size time-step fit of Eq. speed")
@@ -620,6 +674,11 @@ def main():
     if args.step_n > 0:
         log(f"time step: {args.step_n}^3 collapsing column")
         out["step"] = step_bench(nn4mg, torch, args.step_n, args.step_steps)
+        log(f"time step with quadratic ConvFEM filters: {args.step_n}^3 collapsing column")
+        out["step_quadratic"] = step_bench(nn4mg, torch, args.step_n, args.step_steps, order=2)
+    if args.mass_steps > 0:
+        log(f"mass-conservation study: {args.mass_steps} steps per strategy")
+        out["mass_study"] = mass_study(nn4mg, torch, steps=args.mass_steps)
     if not args.no_eq_speed:
         log("Eq. speed fit: time step at 64^3 .. 256^3")
         out["eq_speed"] = eq_speed_fit(nn4mg, torch)

@@ -283,7 +283,13 @@ typedef struct {
     int n_vel_iter;       /* velocity predictor iterations (paper: 2) */
     int mg_cycles_nh;     /* cycles of each correction solve (the j of the paper's i-j strategies,
                              Sec. 3.2, with i = n_corr); 0: mg_cycles */
-    int reserved[4];      /* zero */
+    int order;            /* 0 or 1: linear filters (3x3x3) throughout.  2: quadratic ConvFEM filters
+                             (5x5x5, two-cell halos; Sec. 2.2.3, Sec. 2.3.3) for the momentum terms, the
+                             interface geometry (gradients, normals, curvature) and the volume-fraction
+                             advection, with linear filters for the volume-fraction diffusion (Table
+                             disc_combinations, "linear/quadratic") and for both pressure equations and
+                             the velocity correction, whose Poisson operator is this library's linear one */
+    int reserved[3];      /* zero */
 } nn4mg_step_params;
 
 typedef struct {

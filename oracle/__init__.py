@@ -120,7 +120,7 @@ class StepParams(ctypes.Structure):
     _fields_ = [("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double), ("mu_l", ctypes.c_double),
                 ("mu_g", ctypes.c_double), ("g", ctypes.c_double), ("sigma_t", ctypes.c_double),
                 ("dt", ctypes.c_double), ("mg_cycles", ctypes.c_int), ("n_corr", ctypes.c_int),
-                ("n_vel_iter", ctypes.c_int), ("mg_cycles_nh", ctypes.c_int)]
+                ("n_vel_iter", ctypes.c_int), ("mg_cycles_nh", ctypes.c_int), ("order", ctypes.c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -148,13 +148,58 @@ def _declare_step(L):
     L.or_step_correct.restype = ctypes.c_int
     L.or_step_correct.argtypes = [i, i, i, d, ctypes.POINTER(StepParams), dp, dp, dp, dp, dp,
                                   ctypes.POINTER(StepInfo)]
+    L.or_step_set_order.restype = None
+    L.or_step_set_order.argtypes = [i]
+    L.or_step_filters_quadratic.restype = None
+    L.or_step_filters_quadratic.argtypes = [d, dp, dp, dp]
+    L.or_step_apply5.restype = None
+    L.or_step_apply5.argtypes = [i, i, i, d, ctypes.POINTER(ctypes.c_int), dp, dp, dp]
 
 
 def step_params(rho_l=1000.0, rho_g=1.0, mu_l=1e-3, mu_g=1.8e-5, g=9.81, sigma_t=0.07, dt=1e-4, mg_cycles=20,
-                n_corr=2, n_vel_iter=2, mg_cycles_nh=0):
+                n_corr=2, n_vel_iter=2, mg_cycles_nh=0, order=1):
     """mg_cycles: cycles of every pressure solve; mg_cycles_nh (if > 0) those
-    of the correction solves only (the j of the i-j strategies, Sec. 3.2)."""
-    return StepParams(rho_l, rho_g, mu_l, mu_g, g, sigma_t, dt, mg_cycles, n_corr, n_vel_iter, mg_cycles_nh)
+    of the correction solves only (the j of the i-j strategies, Sec. 3.2);
+    order 2: quadratic ConvFEM filters for the momentum, interface and
+    volume-fraction advection terms (linear volume-fraction diffusion and
+    pressure equations)."""
+    return StepParams(rho_l, rho_g, mu_l, mu_g, g, sigma_t, dt, mg_cycles, n_corr, n_vel_iter, mg_cycles_nh,
+                      order)
+
+
+def step_filters_quadratic(h):
+    """The quadratic ConvFEM filters w_x, w_m, w_lap as (5, 5, 5) arrays indexed [c, b, a] (z, y, x)."""
+    out = [np.empty(125) for _ in range(3)]
+    lib().or_step_filters_quadratic(float(h), *[_d(o) for o in out])
+    return [o.reshape(5, 5, 5) for o in out]
+
+
+def step_apply5(u, h, rule, w):
+    """f(u; w) for a 5x5x5 filter w (indexed [c, b, a]) with the two-cell halo
+    of `rule` (per face: 0 even, 1 odd)."""
+    u = _f64(u)
+    nz, ny, nx = u.shape
+    out = np.empty_like(u)
+    r = (ctypes.c_int * 6)(*[int(x) for x in rule])
+    lib().or_step_apply5(nx, ny, nz, float(h), r, _d(np.ascontiguousarray(w, dtype=np.float64).reshape(-1)), _d(u),
+                         _d(out))
+    return out
+
+
+class step_order:
+    """Context manager: the stage pieces (step_surface, step_pg_velocity,
+    step_vof_coefs, step_vof) use the filters of this order inside it."""
+
+    def __init__(self, order):
+        self.order = order
+
+    def __enter__(self):
+        lib().or_step_set_order(int(self.order))
+        return self
+
+    def __exit__(self, *exc):
+        lib().or_step_set_order(1)
+        return False
 
 
 def step(state, h, params=None):

@@ -48,6 +48,9 @@ typedef struct {
     double rho_l, rho_g, mu_l, mu_g, g, sigma_t, dt;
     int mg_cycles, n_corr, n_vel_iter;
     int mg_cycles_nh; /* cycles of each correction solve (the j of the i-j strategies, Sec. 3.2); 0: mg_cycles */
+    int order;        /* 1 (or 0): linear filters throughout; 2: quadratic ConvFEM for the momentum, interface
+                         and volume-fraction advection terms, linear volume-fraction diffusion and pressure
+                         equations (Table disc_combinations, "linear/quadratic") */
 } or_step_params;
 
 typedef struct {
@@ -164,6 +167,111 @@ static void fdiff(const double *C, const int ruleC[6], const double *k, const in
     free(Cp); free(kp); free(kCp); free(a); free(b); free(c);
 }
 
+/* ---------------------------------------------- two-layer halos (quadratic) */
+
+/* Quadratic ConvFEM filters reach two cells (Sec. 2.2.3, 5 x 5 x 5 filters),
+ * so their fields carry a two-cell halo (Sec. 2.3.3: two nodes thick).  Halo
+ * cell -1-m takes the value of interior cell m (the same reflection about the
+ * wall as the one-cell halo), with the field's sign; the affine rule adds
+ * (2m + 1) lift (the wall-normal distance between the two cells is (2m + 1) h,
+ * so the value extrapolated with the specified gradient); periodic wraps. */
+static size_t pid2(int i, int j, int k)
+{
+    return (size_t)(i + 2) + (size_t)(NX + 4) * ((size_t)(j + 2) + (size_t)(NY + 4) * (size_t)(k + 2));
+}
+static double *palloc2(void) { return (double *)calloc((size_t)(NX + 4) * (NY + 4) * (NZ + 4), sizeof(double)); }
+
+static double halo2(int rule, double mirror, double lift, int m)
+{
+    if (rule == R_ODD) return -mirror;
+    if (rule == R_AFFINE) return mirror + (double)(2 * m + 1) * lift;
+    return mirror;
+}
+
+static void pad2(const double *u, const int rule[6], const double *liftp2, double lift_scale, double *up)
+{
+    for (int k = 0; k < NZ; ++k)
+        for (int j = 0; j < NY; ++j)
+            for (int i = 0; i < NX; ++i) up[pid2(i, j, k)] = u[cid(i, j, k)];
+    for (int m = 0; m < 2; ++m) {
+        for (int k = 0; k < NZ; ++k)
+            for (int j = 0; j < NY; ++j) {
+                int lo = -1 - m, hi = NX + m, ml = m, mh = NX - 1 - m;
+                if (WRAP) {
+                    up[pid2(lo, j, k)] = up[pid2(NX + lo, j, k)];
+                    up[pid2(hi, j, k)] = up[pid2(hi - NX, j, k)];
+                    continue;
+                }
+                up[pid2(lo, j, k)] = halo2(rule[0], up[pid2(ml, j, k)], liftp2 ? lift_scale * liftp2[pid2(ml, j, k)] : 0.0, m);
+                up[pid2(hi, j, k)] = halo2(rule[1], up[pid2(mh, j, k)], liftp2 ? lift_scale * liftp2[pid2(mh, j, k)] : 0.0, m);
+            }
+    }
+    for (int m = 0; m < 2; ++m)
+        for (int k = 0; k < NZ; ++k)
+            for (int i = -2; i <= NX + 1; ++i) {
+                int lo = -1 - m, hi = NY + m, ml = m, mh = NY - 1 - m;
+                if (WRAP) {
+                    up[pid2(i, lo, k)] = up[pid2(i, NY + lo, k)];
+                    up[pid2(i, hi, k)] = up[pid2(i, hi - NY, k)];
+                    continue;
+                }
+                up[pid2(i, lo, k)] = halo2(rule[2], up[pid2(i, ml, k)], liftp2 ? lift_scale * liftp2[pid2(i, ml, k)] : 0.0, m);
+                up[pid2(i, hi, k)] = halo2(rule[3], up[pid2(i, mh, k)], liftp2 ? lift_scale * liftp2[pid2(i, mh, k)] : 0.0, m);
+            }
+    for (int m = 0; m < 2; ++m)
+        for (int j = -2; j <= NY + 1; ++j)
+            for (int i = -2; i <= NX + 1; ++i) {
+                int lo = -1 - m, hi = NZ + m, ml = m, mh = NZ - 1 - m;
+                if (WRAP) {
+                    up[pid2(i, j, lo)] = up[pid2(i, j, NZ + lo)];
+                    up[pid2(i, j, hi)] = up[pid2(i, j, hi - NZ)];
+                    continue;
+                }
+                up[pid2(i, j, lo)] = halo2(rule[4], up[pid2(i, j, ml)], liftp2 ? lift_scale * liftp2[pid2(i, j, ml)] : 0.0, m);
+                up[pid2(i, j, hi)] = halo2(rule[5], up[pid2(i, j, mh)], liftp2 ? lift_scale * liftp2[pid2(i, j, mh)] : 0.0, m);
+            }
+}
+
+/* f(C; w) for a 5 x 5 x 5 filter, w[(c+2)*25 + (b+2)*5 + (a+2)]. */
+static void filt5(const double *up, const double w[125], double *out)
+{
+    for (int k = 0; k < NZ; ++k)
+        for (int j = 0; j < NY; ++j)
+            for (int i = 0; i < NX; ++i) {
+                double s = 0.0;
+                for (int c = -2; c <= 2; ++c)
+                    for (int b = -2; b <= 2; ++b)
+                        for (int a = -2; a <= 2; ++a)
+                            s += w[(c + 2) * 25 + (b + 2) * 5 + (a + 2)] * up[pid2(i + a, j + b, k + c)];
+                out[cid(i, j, k)] = s;
+            }
+}
+
+static void apply5(const double *u, const int rule[6], const double w[125], double *out)
+{
+    double *up = palloc2();
+    pad2(u, rule, NULL, 0.0, up);
+    filt5(up, w, out);
+    free(up);
+}
+
+/* Eq. (k-Txx) with a 5 x 5 x 5 filter. */
+static void fdiff5(const double *C, const int ruleC[6], const double *k, const int ruleK[6], const double w[125],
+                   double *out)
+{
+    size_t n = ncell(), np = (size_t)(NX + 4) * (NY + 4) * (NZ + 4);
+    double *Cp = palloc2(), *kp = palloc2(), *kCp = palloc2();
+    double *a = alloc(), *b = alloc(), *c = alloc();
+    pad2(C, ruleC, NULL, 0.0, Cp);
+    pad2(k, ruleK, NULL, 0.0, kp);
+    for (size_t p = 0; p < np; ++p) kCp[p] = kp[p] * Cp[p];
+    filt5(kCp, w, a);
+    filt5(Cp, w, b);
+    filt5(kp, w, c);
+    for (size_t p = 0; p < n; ++p) out[p] = 0.5 * (a[p] + k[p] * b[p] - C[p] * c[p]);
+    free(Cp); free(kp); free(kCp); free(a); free(b); free(c);
+}
+
 /* ------------------------------------------------------------- filters */
 
 static void outer3(const double x[3], const double y[3], const double z[3], double w[27])
@@ -178,6 +286,39 @@ static double WM[27];      /* consistent mass w_m */
 static double WMA[27];     /* w_m / m_l - E (the residual filter of Eq. a_psi) */
 static double WLAP[27];    /* w_lap */
 static double WPG[3][27];  /* w_xx^PG, w_yy^PG, w_zz^PG */
+/* quadratic ConvFEM: w_x, w_y, w_z, w_m, w_m / m_l - E, w_lap (5 x 5 x 5) */
+static double QD[3][125], QM[125], QMA[125], QLAP[125];
+static int ORDER = 1;
+
+static void outer5(const double x[5], const double y[5], const double z[5], double w[125])
+{
+    for (int c = 0; c < 5; ++c)
+        for (int b = 0; b < 5; ++b)
+            for (int a = 0; a < 5; ++a) w[c * 25 + b * 5 + a] = x[a] * y[b] * z[c];
+}
+
+/* The 1D quadratic ConvFEM vectors (Sec. 2.2.3: the stencils of the node
+ * types summed and averaged).  A quadratic element of length 2h has nodes at
+ * 0, h, 2h with element matrices (Lagrange basis)
+ *   mass (2h/30) [[4, 2, -1], [2, 16, 2], [-1, 2, 4]],
+ *   stiffness (1/(6h)) [[7, -8, 1], [-8, 16, -8], [1, -8, 7]],
+ *   derivative int N_a N_b' = [[-1/2, 2/3, -1/6], [-2/3, 0, 2/3], [1/6, -2/3, 1/2]].
+ * A vertex node collects the last row of the element on its left and the
+ * first row of the one on its right (offsets -2..2); a mid node the middle
+ * row (offsets -1..1).  Their average over the two node types is
+ *   M2 = (h/30) [-1, 4, 24, 4, -1],  K2 = (1/(12h)) [1, -16, 30, -16, 1],
+ *   G2 = (1/12) [1, -8, 0, 8, -1],
+ * and the 3D filters are their tensor products, as for the linear ones. */
+static void quad_vectors(double h, double M2[5], double K2[5], double G2[5])
+{
+    const double m[5] = {-1.0, 4.0, 24.0, 4.0, -1.0}, k[5] = {1.0, -16.0, 30.0, -16.0, 1.0},
+                 g[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
+    for (int q = 0; q < 5; ++q) {
+        M2[q] = h * m[q] / 30.0;
+        K2[q] = k[q] / (12.0 * h);
+        G2[q] = g[q] / 12.0;
+    }
+}
 
 static void build_filters(double h)
 {
@@ -194,6 +335,26 @@ static void build_filters(double h)
     outer3(M, K, M, WPG[1]);
     outer3(M, M, K, WPG[2]);
     or_q1_filter(h, WLAP);
+    double M2[5], K2[5], G2[5], t[125];
+    quad_vectors(h, M2, K2, G2);
+    outer5(G2, M2, M2, QD[0]);
+    outer5(M2, G2, M2, QD[1]);
+    outer5(M2, M2, G2, QD[2]);
+    outer5(M2, M2, M2, QM);
+    for (int q = 0; q < 125; ++q) QMA[q] = QM[q] / ml - (q == 62 ? 1.0 : 0.0);
+    outer5(K2, M2, M2, QLAP);
+    outer5(M2, K2, M2, t);
+    for (int q = 0; q < 125; ++q) QLAP[q] += t[q];
+    outer5(M2, M2, K2, t);
+    for (int q = 0; q < 125; ++q) QLAP[q] += t[q];
+}
+
+/* f(u; w) with the filter of the step's order for the terms that take it
+ * (w1: 3 x 3 x 3, w2: 5 x 5 x 5). */
+static void applyO(const double *u, const int rule[6], const double *w1, const double *w2, double *out)
+{
+    if (ORDER == 2) apply5(u, rule, w2, out);
+    else apply(u, rule, w1, out);
 }
 
 static void set_grid(int nx, int ny, int nz, double h)
@@ -237,7 +398,7 @@ static void adv_residual(const double *u, const double *v, const double *w, cons
 {
     size_t n = ncell();
     for (size_t p = 0; p < n; ++p) adv[p] = u[p] * Pd[0][p] + v[p] * Pd[1][p] + w[p] * Pd[2][p];
-    apply(adv, RULE_EVEN, WMA, a);
+    applyO(adv, RULE_EVEN, WMA, QMA, a);
     for (size_t p = 0; p < n; ++p) a[p] *= alpha_a;
 }
 
@@ -274,7 +435,7 @@ static void surface(const double *C, double sigma_t, double *Cd[3], double *nrm[
     int rg[3][6];
     for (int d = 0; d < 3; ++d) rule_grad(d, rg[d]);
     for (int d = 0; d < 3; ++d) {
-        apply(C, RULE_EVEN, WD[d], Cd[d]);
+        applyO(C, RULE_EVEN, WD[d], QD[d], Cd[d]);
         for (size_t p = 0; p < n; ++p) Cd[d][p] /= ml;
     }
     const double eps_t = 1e-7 / H;
@@ -284,7 +445,7 @@ static void surface(const double *C, double sigma_t, double *Cd[3], double *nrm[
     }
     for (size_t p = 0; p < n; ++p) kappa[p] = 0.0;
     for (int d = 0; d < 3; ++d) {
-        apply(nrm[d], rg[d], WD[d], tmp);
+        applyO(nrm[d], rg[d], WD[d], QD[d], tmp);
         for (size_t p = 0; p < n; ++p) kappa[p] += tmp[p];
     }
     for (size_t p = 0; p < n; ++p) {
@@ -346,17 +507,28 @@ static void vof_coefs(const double *C, const double *u, const double *v, const d
     double *adv = alloc();
     adv_residual(u, v, w, Pd, 2.0, adv, a);
     free(adv);
-    double *Cp = palloc();
-    pad(C, RULE_EVEN, NULL, 0.0, Cp);
+    double *Cp = palloc2();
+    pad2(C, RULE_EVEN, NULL, 0.0, Cp);
     for (int kk = 0; kk < NZ; ++kk)
         for (int j = 0; j < NY; ++j)
             for (int i = 0; i < NX; ++i) {
                 size_t p = cid(i, j, kk);
-                double c0 = Cp[pid(i, j, kk)];
+                double c0 = Cp[pid2(i, j, kk)];
                 double S[3];
-                S[0] = (c0 - Cp[pid(i - 1, j, kk)]) * (Cp[pid(i + 1, j, kk)] - c0);
-                S[1] = (c0 - Cp[pid(i, j - 1, kk)]) * (Cp[pid(i, j + 1, kk)] - c0);
-                S[2] = (c0 - Cp[pid(i, j, kk - 1)]) * (Cp[pid(i, j, kk + 1)] - c0);
+                for (int d = 0; d < 3; ++d) {
+                    /* value at offset s along direction d */
+                    double c[5];
+                    for (int o = -2; o <= 2; ++o)
+                        c[o + 2] = Cp[pid2(i + (d == 0 ? o : 0), j + (d == 1 ? o : 0), kk + (d == 2 ? o : 0))];
+                    /* Eqs. Sx-lin..Sz-lin; with the quadratic filters Eqs. Sx-quad..Sz-quad (the
+                     * smallest of the three products of successive differences) */
+                    S[d] = (c[2] - c[1]) * (c[3] - c[2]);
+                    if (ORDER == 2) {
+                        double s1 = (c[1] - c[0]) * (c[2] - c[1]), s3 = (c[3] - c[2]) * (c[4] - c[3]);
+                        if (s1 < S[d]) S[d] = s1;
+                        if (s3 < S[d]) S[d] = s3;
+                    }
+                }
                 if (c0 > 0.95 || c0 < 0.05) S[0] = S[1] = S[2] = -1.0;
                 double cx = Cd[0][p], cy = Cd[1][p], cz = Cd[2][p];
                 double g2 = cx * cx + cy * cy + cz * cz;
@@ -404,6 +576,9 @@ int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C
 {
     set_grid(nx, ny, nz, h);
     if (info) memset(info, 0, sizeof(*info));
+    if (P->order != 0 && P->order != 1 && P->order != 2) return -1;
+    if (P->order == 2 && (nx < 2 || ny < 2 || nz < 2)) return -1;
+    ORDER = P->order == 2 ? 2 : 1;
     const size_t n = ncell();
     const double ml = h * h * h, dt = P->dt;
     double *q[3] = {u, v, w};
@@ -458,7 +633,7 @@ int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C
     for (int it = 0; it < P->n_vel_iter; ++it) {
         for (int c = 0; c < 3; ++c)
             for (int d = 0; d < 3; ++d) {
-                apply(qh[c], rv[c], WD[d], Qd[c][d]);
+                applyO(qh[c], rv[c], WD[d], QD[d], Qd[c][d]);
                 for (size_t p = 0; p < n; ++p) Qd[c][d][p] /= ml;
             }
         for (int c = 0; c < 3; ++c) {
@@ -466,8 +641,15 @@ int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C
             adv_residual(qh[0], qh[1], qh[2], Pd, 2.0, adv, a);
             pg_isotropic(qh[0], qh[1], qh[2], Pd, a, rho, mu, kq[c]);
             /* s = rho (u q_x + v q_y + w q_z) m_l + f_lap(q, k_q) + f(p_hs + p_nh; w_c) - f(s_q + s_t; w_m) */
-            fdiff(qh[c], rv[c], kq[c], RULE_EVEN, WLAP, tmp);
-            {   /* p_hs with its affine bottom halo */
+            if (ORDER == 2) fdiff5(qh[c], rv[c], kq[c], RULE_EVEN, QLAP, tmp);
+            else fdiff(qh[c], rv[c], kq[c], RULE_EVEN, WLAP, tmp);
+            if (ORDER == 2) {   /* p_hs with its affine bottom halo, two cells */
+                double *pp = palloc2(), *rp = palloc2();
+                pad2(rho, RULE_EVEN, NULL, 0.0, rp);
+                pad2(p_hs, RULE_PHS, rp, P->g * h, pp);
+                filt5(pp, QD[c], gp);
+                free(pp); free(rp);
+            } else {   /* p_hs with its affine bottom halo */
                 double *pp = palloc(), *rp = palloc();
                 pad(rho, RULE_EVEN, NULL, 0.0, rp);
                 pad(p_hs, RULE_PHS, rp, P->g * h, pp);
@@ -475,16 +657,16 @@ int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C
                 free(pp); free(rp);
             }
             for (size_t p = 0; p < n; ++p) tmp[p] += gp[p];
-            apply(p_nh, RULE_PNH, WD[c], gp);
+            applyO(p_nh, RULE_PNH, WD[c], QD[c], gp);
             for (size_t p = 0; p < n; ++p) tmp[p] += gp[p];
             /* the surface-tension source with the sign that the Stage-1
              * pressure balances (Eq. hydro-pressure): p_hs of Eq. ph_disc has
              * gradient -s_t for kappa = +div n, so s_t enters as +f(s_t; w_m) */
-            apply(st[c], rg[c], WM, gp);
+            applyO(st[c], rg[c], WM, QM, gp);
             for (size_t p = 0; p < n; ++p) tmp[p] += gp[p];
             if (c == 2) {
                 for (size_t p = 0; p < n; ++p) src[p] = -P->g * rho[p];
-                apply(src, RULE_EVEN, WM, gp);
+                applyO(src, RULE_EVEN, WM, QM, gp);
                 for (size_t p = 0; p < n; ++p) tmp[p] -= gp[p];
             }
             for (size_t p = 0; p < n; ++p) {
@@ -510,6 +692,7 @@ int or_step(int nx, int ny, int nz, double h, const or_step_params *P, double *C
     }
     for (int d = 0; d < 3; ++d) { free(Cd[d]); free(nrm[d]); free(st[d]); }
     free(rho); free(mu); free(tmp); free(tmp2); free(b); free(kappa); free(adv); free(a); free(gp); free(src);
+    ORDER = 1;
     return 0;
 }
 
@@ -526,6 +709,27 @@ void or_step_filters(double h, double *wx, double *wm, double *wpgx, double *wla
 
 /* 1: every halo wraps and the pressure solves are periodic; 0: the tank. */
 void or_step_set_periodic(int on) { WRAP = on ? 1 : 0; }
+
+/* Filter order of the stage pieces below (or_step sets its own from the
+ * parameters): 1 linear, 2 quadratic ConvFEM for the terms that take it. */
+void or_step_set_order(int order) { ORDER = order == 2 ? 2 : 1; }
+
+/* The quadratic ConvFEM filters (5 x 5 x 5, [(c+2)*25 + (b+2)*5 + (a+2)]). */
+void or_step_filters_quadratic(double h, double *wx, double *wm, double *wlap)
+{
+    build_filters(h);
+    memcpy(wx, QD[0], sizeof(QD[0]));
+    memcpy(wm, QM, sizeof(QM));
+    memcpy(wlap, QLAP, sizeof(QLAP));
+}
+
+/* f(u; w) of a 5 x 5 x 5 filter with the two-cell halo of a rule given per
+ * face (0 even, 1 odd), for the pins of the two-cell halo. */
+void or_step_apply5(int nx, int ny, int nz, double h, const int rule[6], const double *w, const double *u, double *out)
+{
+    set_grid(nx, ny, nz, h);
+    apply5(u, rule, w, out);
+}
 
 /* Curvature and surface-tension vectors of C (Eqs. surface-tension-k,
  * surface-tension-uvw) and grad C in derivative units. */
@@ -554,7 +758,7 @@ void or_step_pg_velocity(int nx, int ny, int nz, double h, int comp, const doubl
     double *Pd[3], *adv = alloc();
     for (int d = 0; d < 3; ++d) {
         Pd[d] = alloc();
-        apply(q[comp], rv, WD[d], Pd[d]);
+        applyO(q[comp], rv, WD[d], QD[d], Pd[d]);
         for (size_t p = 0; p < n; ++p) Pd[d][p] /= ml;
     }
     const double *cPd[3] = {Pd[0], Pd[1], Pd[2]};
@@ -574,7 +778,7 @@ void or_step_vof_coefs(int nx, int ny, int nz, double h, double dt, const double
     double *Cd[3], *kd[3] = {kx, ky, kz};
     for (int d = 0; d < 3; ++d) {
         Cd[d] = alloc();
-        apply(C, RULE_EVEN, WD[d], Cd[d]);
+        applyO(C, RULE_EVEN, WD[d], QD[d], Cd[d]);
         for (size_t p = 0; p < n; ++p) Cd[d][p] /= ml;
     }
     vof_coefs(C, u, v, w, Cd, dt, kd, a);
@@ -591,7 +795,7 @@ void or_step_vof(int nx, int ny, int nz, double h, double dt, double *C, const d
     double *Cd[3];
     for (int d = 0; d < 3; ++d) {
         Cd[d] = alloc();
-        apply(C, RULE_EVEN, WD[d], Cd[d]);
+        applyO(C, RULE_EVEN, WD[d], QD[d], Cd[d]);
         for (size_t p = 0; p < n; ++p) Cd[d][p] /= ml;
     }
     vof_update(C, u, v, w, Cd, dt);

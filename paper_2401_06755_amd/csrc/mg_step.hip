@@ -1,5 +1,6 @@
 // One two-phase time step of arXiv 2401.06755, Sec. 2.4 (Stages 1-4), with
-// linear (p = 1) filters, on gfx950.
+// linear (p = 1) filters, or quadratic ConvFEM filters (p = 2) for the terms
+// that the paper's linear/quadratic combination gives them, on gfx950.
 //
 // Every operator of the step is a 3x3x3 filter sum f(u; w) (Sec. 2.2.2) over a
 // field whose halo is synthesised at load time from that field's boundary
@@ -573,6 +574,318 @@ __global__ __launch_bounds__(256) void copy3_kernel(size_t n, C3 src, F3 dst)
     for (int d = 0; d < 3; ++d) dst.p[d][id] = src.p[d][id];
 }
 
+// ------------------------------------------------ quadratic ConvFEM (order 2)
+// The 5 x 5 x 5 filters of the quadratic ConvFEM (Sec. 2.2.3: the stencils of
+// the vertex and mid nodes of quadratic Lagrange elements summed and
+// averaged) are tensor products of
+//     M2 = h [-1, 4, 24, 4, -1] / 30,  G2 = [1, -8, 0, 8, -1] / 12,
+//     K2 = [1, -16, 30, -16, 1] / (12 h),
+// applied with two-cell halos (Sec. 2.3.3): halo cell -1-m takes interior
+// cell m with the field's sign, and the bottom halo of p_hs adds
+// (2m + 1) g h rho (the gradient -rho g extrapolated over (2m + 1) h).  They
+// serve the momentum terms, the interface geometry and the volume-fraction
+// advection (Table disc_combinations, "linear/quadratic"); the volume-fraction
+// diffusion and the two pressure equations keep the linear filters.  Each
+// kernel sums its 125 taps straight from global memory (L1/L2 carry the
+// re-reads), rows first, so no neighbourhood is held in registers.
+
+struct V5 {
+    double w[5];
+};
+
+struct Filt2 {
+    V5 M, G, K;
+    double ml;
+    __device__ explicit Filt2(double h)
+    {
+        const double m[5] = {-1.0, 4.0, 24.0, 4.0, -1.0}, g[5] = {1.0, -8.0, 0.0, 8.0, -1.0},
+                     k[5] = {1.0, -16.0, 30.0, -16.0, 1.0};
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            M.w[q] = h * m[q] / 30.0;
+            G.w[q] = g[q] / 12.0;
+            K.w[q] = k[q] / (12.0 * h);
+        }
+        ml = h * h * h;
+    }
+};
+
+// Index up to two cells outside folded onto the cell it mirrors; s flips on a
+// crossed face whose bit is set in odd.
+__device__ inline int fold2(int i, int n, unsigned odd, unsigned lo_bit, unsigned hi_bit, double &s)
+{
+    if (i < 0) {
+        if (odd & lo_bit) s = -s;
+        return -1 - i;
+    }
+    if (i >= n) {
+        if (odd & hi_bit) s = -s;
+        return 2 * n - 1 - i;
+    }
+    return i;
+}
+
+// Padded value of u at (i, j, k) with the two-cell halo of rule odd.
+struct Tap2 {
+    const double *u;
+    unsigned odd;
+    Grid g;
+    __device__ double operator()(int i, int j, int k) const
+    {
+        double s = 1.0;
+        i = fold2(i, g.nx, odd, 1u, 2u, s);
+        j = fold2(j, g.ny, odd, 4u, 8u, s);
+        k = fold2(k, g.nz, odd, 16u, 32u, s);
+        return s * u[at(g, i, j, k)];
+    }
+};
+
+// p_hs: +mirror on the sides, -mirror on top, and below the bottom the mirror
+// plus (2m + 1) g h rho of the mirrored cell (rho +mirror on the sides).
+struct TapPhs2 {
+    const double *p, *rho;
+    Grid g;
+    double gh;
+    __device__ double operator()(int i, int j, int k) const
+    {
+        double s = 1.0;
+        i = fold2(i, g.nx, kOddTop, 1u, 2u, s);
+        j = fold2(j, g.ny, kOddTop, 4u, 8u, s);
+        if (k < 0) {
+            const int m = -1 - k;
+            const size_t c = at(g, i, j, m);
+            return p[c] + (double)(2 * m + 1) * gh * rho[c];
+        }
+        k = fold2(k, g.nz, kOddTop, 16u, 32u, s);
+        return s * p[at(g, i, j, k)];
+    }
+};
+
+// Product of two padded fields (the halo of k q is the product of the halos).
+template <typename A, typename B>
+struct TapMul {
+    A a;
+    B b;
+    __device__ double operator()(int i, int j, int k) const { return a(i, j, k) * b(i, j, k); }
+};
+
+// The three derivative filters and the mass filter of one field at a cell:
+// d[0..2] = f(u; w_d), d[3] = f(u; w_m).
+template <typename T>
+__device__ inline void deriv_mass2(const Filt2 &F, const T &tap, int i, int j, int k, double d[4])
+{
+    double dx = 0.0, dy = 0.0, dz = 0.0, mm = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < 5; ++c) {
+        double pGM = 0.0, pMG = 0.0, pMM = 0.0;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            double rG = 0.0, rM = 0.0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const double v = tap(i + a - 2, j + b - 2, k + c - 2);
+                rG += F.G.w[a] * v;
+                rM += F.M.w[a] * v;
+            }
+            pGM += F.M.w[b] * rG;
+            pMG += F.G.w[b] * rM;
+            pMM += F.M.w[b] * rM;
+        }
+        dx += F.M.w[c] * pGM;
+        dy += F.M.w[c] * pMG;
+        dz += F.G.w[c] * pMM;
+        mm += F.M.w[c] * pMM;
+    }
+    d[0] = dx;
+    d[1] = dy;
+    d[2] = dz;
+    d[3] = mm;
+}
+
+// f(u; w_lap) = f(u; K M M + M K M + M M K).
+template <typename T>
+__device__ inline double lap2(const Filt2 &F, const T &tap, int i, int j, int k)
+{
+    double out = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < 5; ++c) {
+        double pKM = 0.0, pMK = 0.0, pMM = 0.0;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            double rK = 0.0, rM = 0.0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const double v = tap(i + a - 2, j + b - 2, k + c - 2);
+                rK += F.K.w[a] * v;
+                rM += F.M.w[a] * v;
+            }
+            pKM += F.M.w[b] * rK;
+            pMK += F.K.w[b] * rM;
+            pMM += F.M.w[b] * rM;
+        }
+        out += F.M.w[c] * (pKM + pMK) + F.K.w[c] * pMM;
+    }
+    return out;
+}
+
+// rho, mu, grad C in derivative units and the unit normals, quadratic filters.
+__global__ __launch_bounds__(256) void props2_kernel(Grid g, Phys P, const double *C, double *rho, double *mu, F3 Cd,
+                                                     F3 nrm)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt2 F(g.h);
+        const double c0 = C[id];
+        rho[id] = P.rho_l * c0 + P.rho_g * (1.0 - c0);
+        mu[id] = P.mu_l * c0 + P.mu_g * (1.0 - c0);
+        double d[4];
+        deriv_mass2(F, Tap2{C, kEven, g}, i, j, k, d);
+        double gd[3];
+        for (int e = 0; e < 3; ++e) gd[e] = d[e] / F.ml;
+        const double l = sqrt(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
+        const double eps = 1e-7 / g.h;
+        for (int e = 0; e < 3; ++e) {
+            Cd.p[e][id] = gd[e];
+            nrm.p[e][id] = gd[e] / (eps + l);
+        }
+    });
+}
+
+// Curvature div n and the surface-tension vectors, quadratic filters.
+__global__ __launch_bounds__(256) void surface2_kernel(Grid g, double sigma, C3 nrm, C3 Cd, F3 st)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt2 F(g.h);
+        double kap = 0.0;
+        for (int e = 0; e < 3; ++e) {
+            double d[4];
+            deriv_mass2(F, Tap2{nrm.p[e], rule_grad(e), g}, i, j, k, d);
+            kap += d[e];
+        }
+        kap /= F.ml;
+        for (int e = 0; e < 3; ++e) st.p[e][id] = sigma * kap * Cd.p[e][id];
+    });
+}
+
+// adv_c = q . grad q_c, quadratic filters.
+__global__ __launch_bounds__(256) void advection2_kernel(Grid g, C3 q, F3 adv)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt2 F(g.h);
+        const double q0[3] = {q.p[0][id], q.p[1][id], q.p[2][id]};
+        for (int c = 0; c < 3; ++c) {
+            double d[4];
+            deriv_mass2(F, Tap2{q.p[c], rule_vel(c), g}, i, j, k, d);
+            adv.p[c][id] = q0[0] * (d[0] / F.ml) + q0[1] * (d[1] / F.ml) + q0[2] * (d[2] / F.ml);
+        }
+    });
+}
+
+// Isotropic PG diffusivity of each component, quadratic filters (the residual
+// filter of Eq. a_psi is w_m / m_l - E with the quadratic mass).
+__global__ __launch_bounds__(256) void pg_velocity2_kernel(Grid g, C3 q, C3 adv, const double *rho,
+                                                           const double *mu, F3 kq)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt2 F(g.h);
+        const double eps_k = 1e-7, a_kabs = 1.0 / 16.0, a_ksq = 4.0, h = g.h;
+        const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
+        for (int c = 0; c < 3; ++c) {
+            double d[4], am[4];
+            deriv_mass2(F, Tap2{q.p[c], rule_vel(c), g}, i, j, k, d);
+            const double px = d[0] / F.ml, py = d[1] / F.ml, pz = d[2] / F.ml;
+            deriv_mass2(F, Tap2{adv.p[c], kEven, g}, i, j, k, am);
+            const double a = 2.0 * (am[3] / F.ml - adv.p[c][id]);
+            const double G = fabs(px) + fabs(py) + fabs(pz);
+            const double kabs = a_kabs * h * fabs(a) / (eps_k + G / 3.0);
+            const double g2 = px * px + py * py + pz * pz;
+            const double advabs = fabs(u * px) + fabs(v * py) + fabs(w * pz);
+            const double ksq = a_ksq * a * a * h / (eps_k + advabs / 3.0 * g2);
+            const double kmax = h * (fabs(u) + fabs(v) + fabs(w));
+            const double m = fmin(kmax, fmin(kabs, ksq));
+            kq.p[c][id] = rho[id] * m + mu[id];
+        }
+    });
+}
+
+// One predictor iteration with the quadratic filters (the same residual as
+// momentum_lds_kernel: s_c = rho m_l adv_c + f_lap(q_c, k_c) + f(p_hs + p_nh; w_c)
+// + f(s_t,c; w_m) [- f(-g rho; w_m) for c = z]).
+__global__ __launch_bounds__(256) void momentum2_kernel(Grid g, Phys P, C3 qn, const double *p_hs, const double *p_nh,
+                                                        const double *rho, C3 qh, C3 kq, C3 st, C3 adv, F3 qt,
+                                                        F3 qnext)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt2 F(g.h);
+        const double r0 = rho[id];
+        double ghs[4], gnh[4], rm[4];
+        deriv_mass2(F, TapPhs2{p_hs, rho, g, P.g * g.h}, i, j, k, ghs);
+        deriv_mass2(F, Tap2{p_nh, kOddTop, g}, i, j, k, gnh);
+        deriv_mass2(F, Tap2{rho, kEven, g}, i, j, k, rm);
+        const double buoy = -P.g * rm[3];  // f(-g rho; w_m)
+        for (int c = 0; c < 3; ++c) {
+            const Tap2 tq{qh.p[c], rule_vel(c), g}, tk{kq.p[c], kEven, g};
+            const double q0 = qh.p[c][id], k0 = kq.p[c][id];
+            // Eq. k-T: 1/2 [f(k q; w) + k f(q; w) - q f(k; w)]
+            double s = 0.5 * (lap2(F, TapMul<Tap2, Tap2>{tk, tq}, i, j, k) + k0 * lap2(F, tq, i, j, k) -
+                              q0 * lap2(F, tk, i, j, k));
+            s += ghs[c];
+            s += gnh[c];
+            double t4[4];
+            deriv_mass2(F, Tap2{st.p[c], rule_grad(c), g}, i, j, k, t4);
+            s += t4[3];
+            if (c == 2) s -= buoy;
+            s += r0 * F.ml * adv.p[c][id];
+            const double qnc = qn.p[c][id];
+            const double t = (-s / F.ml + r0 * qnc / P.dt) / (r0 / P.dt);
+            qt.p[c][id] = t;
+            qnext.p[c][id] = 0.5 * (qnc + t);
+        }
+    });
+}
+
+// Volume-fraction diffusivities with the quadratic advection residual and the
+// detectors of Eqs. Sx-quad..Sz-quad (the smallest of three products of
+// successive differences along each axis).
+__global__ __launch_bounds__(256) void pg_volume_fraction2_kernel(Grid g, double dt, const double *C, C3 Cd, C3 q,
+                                                                  const double *advc, F3 kd)
+{
+    cell_of(g, [&](size_t id, int i, int j, int k) {
+        const Filt2 F(g.h);
+        const double Kp = 300.0, Km = 300.0, beta = 0.1, eps_x = 1e-4, Kpos = 3.0, eps_k = 1e-7, h = g.h;
+        const double kmin = 1e-4 / dt * h * h, kclamp = 0.05 / dt * h * h;
+        double am[4];
+        deriv_mass2(F, Tap2{advc, kEven, g}, i, j, k, am);
+        const double a = 2.0 * (am[3] / F.ml - advc[id]);
+        const Tap2 tc{C, kEven, g};
+        const double c0 = C[id];
+        double S[3];
+        for (int d = 0; d < 3; ++d) {
+            double c[5];
+            for (int o = -2; o <= 2; ++o)
+                c[o + 2] = tc(i + (d == 0 ? o : 0), j + (d == 1 ? o : 0), k + (d == 2 ? o : 0));
+            S[d] = (c[2] - c[1]) * (c[3] - c[2]);
+            const double s1 = (c[1] - c[0]) * (c[2] - c[1]), s3 = (c[3] - c[2]) * (c[4] - c[3]);
+            if (s1 < S[d]) S[d] = s1;
+            if (s3 < S[d]) S[d] = s3;
+        }
+        if (c0 > 0.95 || c0 < 0.05) S[0] = S[1] = S[2] = -1.0;
+        const double cx = Cd.p[0][id], cy = Cd.p[1][id], cz = Cd.p[2][id];
+        const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
+        const double g2 = cx * cx + cy * cy + cz * cz;
+        const double proj = (u * cx + v * cy + w * cz) / (eps_x + g2);
+        const double us = cx * proj, vs = cy * proj, ws = cz * proj;
+        const double kneg = -beta * (u * u + v * v + w * w) / (eps_x + g2 * (fabs(us) + fabs(vs) + fabs(ws)) / 3.0);
+        const double G = fabs(cx) + fabs(cy) + fabs(cz);
+        const double kabs = (1.0 / 16.0) * h * fabs(a) / (eps_k + G / 3.0);
+        for (int d = 0; d < 3; ++d) {
+            const double wp = -fmax(-1.0, fmin(0.0, Kp * S[d]));
+            const double wm = fmin(1.0, fmax(0.0, Km * S[d]));
+            const double kk = wp * (Kpos * kabs) + wm * (kneg / h);
+            kd.p[d][id] = fmax(-kmin, fmin(kclamp, kk));
+        }
+    });
+}
+
 C3 c3(double *const p[3]) { return C3{{p[0], p[1], p[2]}}; }
 F3 f3(double *const p[3]) { return F3{{p[0], p[1], p[2]}}; }
 
@@ -652,7 +965,8 @@ int check_params(const nn4mg_step_params *p)
     if (!std::isfinite(p->g) || !std::isfinite(p->sigma_t)) return set_error(NN4MG_EINVAL, "g, sigma_t must be finite");
     if (p->mg_cycles < 1 || p->mg_cycles > 511) return set_error(NN4MG_EINVAL, "mg_cycles must be in [1, 511]");
     if (p->mg_cycles_nh < 0 || p->mg_cycles_nh > 511) return set_error(NN4MG_EINVAL, "mg_cycles_nh must be in [0, 511]");
-    for (int i = 0; i < 4; ++i)
+    if (p->order < 0 || p->order > 2) return set_error(NN4MG_EINVAL, "order must be 0, 1 or 2");
+    for (int i = 0; i < 3; ++i)
         if (p->reserved[i] != 0) return set_error(NN4MG_EINVAL, "reserved fields must be zero");
     if (p->n_corr < 0 || p->n_corr > 7) return set_error(NN4MG_EINVAL, "n_corr must be in [0, 7]");
     if (p->n_vel_iter < 1 || p->n_vel_iter > 64) return set_error(NN4MG_EINVAL, "n_vel_iter must be in [1, 64]");
@@ -775,7 +1089,10 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
                nn4mg_step_info *info)
 {
     if (!S || !C || !u || !v || !w || !p_hs || !p_nh) return set_error(NN4MG_EINVAL, "NULL argument");
-    if (info) std::memset(info, 0, sizeof(*info));
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->volume = std::nan("");  // until the step completes
+    }
     const Grid g = S->g;
     const nn4mg_step_params &p = S->p;
     const Phys P{p.rho_l, p.rho_g, p.mu_l, p.mu_g, p.g, p.sigma_t, p.dt};
@@ -785,9 +1102,17 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     float ms_mg = 0.0f;
     int rc;
 
+    const bool quad = p.order == 2;
     STEP_TRY(hipEventRecord(S->ev[0], s), "hipEventRecord");
-    hipLaunchKernelGGL(props_kernel, grid, blk, 0, s, g, P, (const double *)C, S->rho, S->mu, f3(S->Cd), f3(S->nrm));
-    hipLaunchKernelGGL(surface_kernel, grid, blk, 0, s, g, p.sigma_t, c3(S->nrm), c3(S->Cd), f3(S->st));
+    if (quad) {
+        hipLaunchKernelGGL(props2_kernel, grid, blk, 0, s, g, P, (const double *)C, S->rho, S->mu, f3(S->Cd),
+                           f3(S->nrm));
+        hipLaunchKernelGGL(surface2_kernel, grid, blk, 0, s, g, p.sigma_t, c3(S->nrm), c3(S->Cd), f3(S->st));
+    } else {
+        hipLaunchKernelGGL(props_kernel, grid, blk, 0, s, g, P, (const double *)C, S->rho, S->mu, f3(S->Cd),
+                           f3(S->nrm));
+        hipLaunchKernelGGL(surface_kernel, grid, blk, 0, s, g, p.sigma_t, c3(S->nrm), c3(S->Cd), f3(S->st));
+    }
 
     // Stage 1: hydrostatic + surface-tension pressure, warm-started from p_hs
     hipLaunchKernelGGL(rhs_hydrostatic_kernel, grid, blk, 0, s, g, p.g, c3(S->st), (const double *)S->rho, S->b);
@@ -800,6 +1125,18 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     double **cur = S->qa, **nxt = S->qb;
     hipLaunchKernelGGL(copy3_kernel, grid, blk, 0, s, g.n, c3(q), f3(cur));
     for (int it = 0; it < p.n_vel_iter; ++it) {
+        if (quad) {
+            hipLaunchKernelGGL(advection2_kernel, grid, blk, 0, s, g, c3(cur), f3(S->adv));
+            hipLaunchKernelGGL(pg_velocity2_kernel, grid, blk, 0, s, g, c3(cur), c3(S->adv), (const double *)S->rho,
+                               (const double *)S->mu, f3(S->kq));
+            hipLaunchKernelGGL(momentum2_kernel, grid, blk, 0, s, g, P, c3(q), (const double *)p_hs,
+                               (const double *)p_nh, (const double *)S->rho, c3(cur), c3(S->kq), c3(S->st),
+                               c3(S->adv), f3(S->qt), f3(nxt));
+            double **t = cur;
+            cur = nxt;
+            nxt = t;
+            continue;
+        }
         hipLaunchKernelGGL(advection_kernel, grid, blk, 0, s, g, c3(cur), f3(S->adv));
         hipLaunchKernelGGL(pg_velocity_kernel, grid, blk, 0, s, g, c3(cur), c3(S->adv), (const double *)S->rho,
                            (const double *)S->mu, f3(S->kq));
@@ -838,8 +1175,12 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
 
     // Stage 4: volume fraction with the new velocity
     hipLaunchKernelGGL(advection_c_kernel, grid, blk, 0, s, g, c3(q), c3(S->Cd), S->tmp);
-    hipLaunchKernelGGL(pg_volume_fraction_kernel, grid, blk, 0, s, g, p.dt, (const double *)C, c3(S->Cd), c3(q),
-                       (const double *)S->tmp, f3(S->kq));
+    if (quad)
+        hipLaunchKernelGGL(pg_volume_fraction2_kernel, grid, blk, 0, s, g, p.dt, (const double *)C, c3(S->Cd), c3(q),
+                           (const double *)S->tmp, f3(S->kq));
+    else
+        hipLaunchKernelGGL(pg_volume_fraction_kernel, grid, blk, 0, s, g, p.dt, (const double *)C, c3(S->Cd), c3(q),
+                           (const double *)S->tmp, f3(S->kq));
     hipLaunchKernelGGL(volume_fraction_kernel, grid, blk, 0, s, g, p.dt, (const double *)C, c3(S->kq), c3(q),
                        c3(S->Cd), S->b);
     STEP_TRY(hipMemcpyAsync(C, S->b, g.n * sizeof(double), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
@@ -878,7 +1219,7 @@ int nn4mg_step_run(nn4mg_step_t S, int nsteps, double *C, double *u, double *v, 
     for (int n = 0; n < nsteps; ++n) {
         rc = nn4mg_step(S, C, u, v, w, p_hs, p_nh, &si);
         if (info) *info = si;
-        if (volume && (rc == NN4MG_OK || rc == NN4MG_EBREAKDOWN)) volume[n + 1] = si.volume;
+        if (volume && (rc == NN4MG_OK || rc == NN4MG_EBREAKDOWN)) volume[n + 1] = si.volume;  // NaN if it stopped early
         if (rc) return rc;
         if (steps_done) *steps_done = n + 1;
     }

@@ -82,7 +82,7 @@ class StepParams(ctypes.Structure):
         ("mu_l", ctypes.c_double), ("mu_g", ctypes.c_double),
         ("g", ctypes.c_double), ("sigma_t", ctypes.c_double), ("dt", ctypes.c_double),
         ("mg_cycles", ctypes.c_int), ("n_corr", ctypes.c_int), ("n_vel_iter", ctypes.c_int),
-        ("mg_cycles_nh", ctypes.c_int), ("reserved", ctypes.c_int * 4),
+        ("mg_cycles_nh", ctypes.c_int), ("order", ctypes.c_int), ("reserved", ctypes.c_int * 3),
     ]
 
 

@@ -6,9 +6,15 @@ Reduced rising bubble (inputs.bubble_state: an air bubble of radius H/2 at
 height H in a 3H x 3H x 6H water tank, here 16 x 16 x 32 cells of a 6 mm wide
 tank) at density ratio 2, where the printed correction does not amplify
 interface velocities, for two of the paper's i-j strategies (i corrections,
-j cycles per correction solve).  Bar: every field after 3 steps within 1e-9 of
-its largest oracle value (the bar of the single-step parity tests), and the
-volume after every step within 1e-10 relative of the oracle's sum C h^3.
+j cycles per correction solve).  Bar: the volume after every step within
+1e-10 relative of the oracle's sum C h^3; C and the pressures after 3 steps
+within 1e-9 of their largest oracle values (the single-step bar); the
+velocities within 20 times what the oracle itself changes when its initial C
+is perturbed by 1e-15 relative noise (at least 1e-9).  The velocities are
+small differences of the pressure, buoyancy and Petrov-Galerkin terms, so
+input rounding alone moves the oracle's velocities by 3e-9 after one step and
+by up to 5e-8 after three at 2-20 (CPU measurement); the GPU and the oracle
+round differently and are held to that conditioning, not to a fixed figure.
 """
 import numpy as np
 import pytest
@@ -52,17 +58,27 @@ def test_three_steps_and_volume_match_oracle(mg, i, j):
     assert done == 3 and len(vols) == 4 and info.solves == 1 + i
     got = {k: dev[k].cpu().numpy().reshape(nz, ny, nx) for k in FIELDS}
     ref = {k: np.ascontiguousarray(st[k]).copy() for k in FIELDS}
+    pert = {k: np.ascontiguousarray(st[k]).copy() for k in FIELDS}
+    rng = np.random.default_rng(0)
+    pert["C"] = np.ascontiguousarray(pert["C"] * (1.0 + 1e-15 * rng.standard_normal(pert["C"].shape)))
     want_vol = [ref["C"].sum() * h ** 3]
     for _ in range(3):
         oracle.step(ref, h, oracle.step_params(**params))
+        oracle.step(pert, h, oracle.step_params(**params))
         want_vol.append(ref["C"].sum() * h ** 3)
+    print("  volume rel diff per step", [f"{abs(a - b) / b:.1e}" for a, b in zip(vols, want_vol)], flush=True)
+    np.testing.assert_allclose(vols, want_vol, rtol=1e-10, atol=0)
     vel = max(np.abs(ref[q]).max() for q in ("u", "v", "w"))
+    errs = {}
     for k in FIELDS:
         scale = max(np.abs(ref[k]).max(), vel if k in ("u", "v", "w") else 0.0, 1e-300)
-        err = np.abs(got[k] - ref[k]).max()
-        print(f"  {k}: max rel diff {err / scale:.2e}", flush=True)
-        assert err <= 1e-9 * scale, (k, err / scale)
-    np.testing.assert_allclose(vols, want_vol, rtol=1e-10, atol=0)
+        errs[k] = np.abs(got[k] - ref[k]).max() / scale
+        print(f"  {k}: max rel diff {errs[k]:.2e}", flush=True)
+    sens = max(np.abs(pert[q] - ref[q]).max() for q in ("u", "v", "w")) / vel
+    bar_vel = max(1e-9, 20.0 * sens)
+    print(f"  oracle velocity change from 1e-15 input noise {sens:.2e}; velocity bar {bar_vel:.2e}", flush=True)
+    for k in FIELDS:
+        assert errs[k] <= (bar_vel if k in ("u", "v", "w") else 1e-9), (k, errs[k])
 
 
 def test_run_reports_breakdown(mg):
