@@ -33,6 +33,8 @@
 #include "mg_device.h"
 #include "mg_internal.h"
 
+#include <type_traits>
+
 namespace nn4mg {
 
 namespace {
@@ -216,7 +218,7 @@ __device__ __forceinline__ T jacobi(const Run<T> &r, const PS<T> &p, T bb, T cw,
 }
 
 template <typename T, typename KT, int OUT, int TX, int RY>
-__global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
+__global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sweep2_kernel(const StencilArgs a)
 {
     if (a.done && *a.done) return;
     using TL = FTile<TX, RY>;
@@ -265,7 +267,14 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
     const T *ep = (const T *)a.ec;
     const KT *kp = (const KT *)a.k;
 
-    auto fetch = [&](FPre<T, KT, TX, RY, ADD> &p, int zi) {
+    // Loads of plane zi in two parts.  The coefficient and the coarse values
+    // are consumed by the LDS commit at the start of the step that uses them,
+    // so the next plane's loads can reuse their registers right after it; the
+    // right-hand sides (and the FP64 field) are consumed by the sweeps, so
+    // they are reloaded at the end of the step.  Either way no register still
+    // holding a load in flight is copied at the loop's back edge (a copy would
+    // wait for every outstanding load and undo the two-plane prefetch).
+    auto fetch_kc = [&](FPre<T, KT, TX, RY, ADD> &p, int zi) {
         int sk_ = 1;
         const size_t pz = plane * (size_t)fold(zi, nz, a.g.bc[4], a.g.bc[5], sk_);
         if constexpr (HK) {
@@ -281,13 +290,18 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
             p.c1[q] = ep[p1 + (size_t)G.coff[q]];
             p.c2[q] = ep[p2 + (size_t)G.coff[q]];
         }
-        if (zi - 1 >= z0 - 1 && zi - 1 <= z1) {
+    };
+    // ST (steady): the caller guarantees the plane conditions, so the loads
+    // are issued unconditionally
+    auto fetch_b = [&](auto st_tag, FPre<T, KT, TX, RY, ADD> &p, int zi) {
+        constexpr bool ST = decltype(st_tag)::value;
+        if (ST || (zi - 1 >= z0 - 1 && zi - 1 <= z1)) {
             int sb = 1;
             const size_t pb = plane * (size_t)fold(zi - 1, nz, a.g.bc[4], a.g.bc[5], sb);
 #pragma unroll
             for (int q = 0; q < TL::R1; ++q) p.b1[q] = bp[pb + (size_t)G.boff[q]];
         }
-        if (zi - 2 >= z0 && zi - 2 < z1) {
+        if (ST || (zi - 2 >= z0 && zi - 2 < z1)) {
             const size_t pl = plane * (size_t)(zi - 2);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
@@ -295,6 +309,10 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
                 if constexpr (ADD) p.xo[r] = a.x64[pl + gb[r]];
             }
         }
+    };
+    auto fetch = [&](FPre<T, KT, TX, RY, ADD> &p, int zi) {
+        fetch_kc(p, zi);
+        fetch_b(std::false_type{}, p, zi);
     };
 
     // P e of plane zi into sx[buf] (coarse footprint staged in LDS first),
@@ -329,24 +347,21 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
     };
 
     int buf = 0;  // sx/sk buffer of the plane being committed (rotates through 3)
-    auto step = [&](FPre<T, KT, TX, RY, ADD> &p, int zi) {
+    // One plane step.  The steady form (ST: planes z0 + 2 .. z1 - 2 of a tile
+    // that lies inside the grid) issues the same loads and stores on every
+    // path, so the compiler's wait counts let the loads of the next two planes
+    // stay in flight; the general form serves the first and last steps of the
+    // march and tiles that cross the grid's edge.
+    auto step = [&](auto st_tag, FPre<T, KT, TX, RY, ADD> &p, int zi) {
+        constexpr bool ST = decltype(st_tag)::value;
         commit(p, zi, buf);
-        T b1[TL::R1], b2[RY];
-        double xo[ADD ? RY : 1];
         bool bzneg = false;
         {
             int sb = 1;
             (void)fold(zi - 1, nz, a.g.bc[4], a.g.bc[5], sb);
             bzneg = sb < 0;
         }
-#pragma unroll
-        for (int q = 0; q < TL::R1; ++q) b1[q] = (G.bneg[q] != bzneg) ? -p.b1[q] : p.b1[q];
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            b2[r] = p.b2[r];
-            if constexpr (ADD) xo[r] = p.xo[r];
-        }
-        if (zi + 2 <= z1 + 1) fetch(p, zi + 2);
+        if (ST || zi + 2 <= z1 + 1) fetch_kc(p, zi + 2);
 
         // first sweep: absorb plane zi down the thread's strip, completing y1(zi - 1)
         const int yb = (zi - 1) & 1;
@@ -364,13 +379,15 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
                 const Row<T> w2 = wrow(q + 2);
                 const PS<T> ps = col_sums<T, HK>(w0, w1, w2);
                 const int qy = s1q * TL::R1 + q;
-                if (zi >= z0 && qy < TL::QY) sy[yb][qy * TL::QX + s1x] = jacobi<T, HK>(r1[q], ps, b1[q], cw, om_w0, om, icv);
+                const T bq = (G.bneg[q] != bzneg) ? -p.b1[q] : p.b1[q];
+                if ((ST || zi >= z0) && qy < TL::QY)
+                    sy[yb][qy * TL::QX + s1x] = jacobi<T, HK>(r1[q], ps, bq, cw, om_w0, om, icv);
                 absorb<T, HK>(r1[q], ps, zi == z0 - 2);
                 w0 = w1;
                 w1 = w2;
             }
         }
-        if (zi >= z0) {
+        if (ST || zi >= z0) {
             __syncthreads();
             // second sweep: absorb y1(zi - 1) with the coefficient plane zi - 1,
             // completing the output plane zi - 2
@@ -388,12 +405,12 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
                 const PS<T> ps = col_sums<T, HK>(w0, w1, w2);
                 w0 = w1;
                 w1 = w2;
-                if (zi >= z0 + 2) {
-                    const T y = jacobi<T, HK>(r2[r], ps, b2[r], cw, om_w0, om, icv);
-                    if (valid[r]) {
-                        const size_t g = gb[r] + plane * (size_t)(zi - 2);
+                if (ST || zi >= z0 + 2) {
+                    const T y = jacobi<T, HK>(r2[r], ps, p.b2[r], cw, om_w0, om, icv);
+                    const size_t g = gb[r] + plane * (size_t)(zi - 2);
+                    if (ST || valid[r]) {  // the steady march runs only on tiles inside the grid
                         if constexpr (ADD)
-                            a.x64[g] = xo[r] + (double)y;
+                            a.x64[g] = p.xo[r] + (double)y;
                         else
                             ((T *)a.yout)[g] = y;
                     }
@@ -401,14 +418,32 @@ __global__ __launch_bounds__(FT) void sweep2_kernel(const StencilArgs a)
                 absorb<T, HK>(r2[r], ps, zi == z0);
             }
         }
+        // right-hand sides of plane zi + 2's step, into the registers just consumed
+        if (ST || zi + 2 <= z1 + 1) fetch_b(st_tag, p, zi + 2);
         buf = (buf + 1) % 3;
     };
 
     fetch(pA, z0 - 2);
     fetch(pB, z0 - 1);
-    for (int zi = z0 - 2; zi <= z1 + 1; zi += 2) {
-        step(pA, zi);
-        if (zi + 1 <= z1 + 1) step(pB, zi + 1);
+    const std::false_type gen{};
+    const std::true_type steady{};
+    int zi = z0 - 2;
+    // the first four steps (no output plane yet) ...
+    for (; zi < z0 + 2 && zi <= z1 + 1; zi += 2) {
+        step(gen, pA, zi);
+        if (zi + 1 <= z1 + 1) step(gen, pB, zi + 1);
+    }
+    // ... the steady march, both steps of a pair with all their loads and stores
+    // (zi >= z0 + 2 stores; zi + 3 <= z1 + 1 keeps every fetched plane in the chunk) ...
+    const bool inside = i0 + TX <= nx && j0 + TL::TY <= ny;  // uniform over the workgroup
+    for (; inside && zi + 3 <= z1 + 1; zi += 2) {
+        step(steady, pA, zi);
+        step(steady, pB, zi + 1);
+    }
+    // ... and the last steps
+    for (; zi <= z1 + 1; zi += 2) {
+        step(gen, pA, zi);
+        if (zi + 1 <= z1 + 1) step(gen, pB, zi + 1);
     }
 }
 
