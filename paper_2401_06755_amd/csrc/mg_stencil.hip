@@ -129,22 +129,30 @@ struct Prefetch {
 // its z-interpolation (prolongation modes) and of the output-plane values of
 // z - 1.  Every address is in range (slots past the tile repeat the last
 // cell; rows past the grid read a clamped row), so the loads need no guards.
+// The output-plane values (right-hand side and FP64 field of plane z - 1) are
+// a part of their own: the step consumes them after it has issued the next
+// plane's field loads, so they are reloaded at the end of the step, into the
+// registers just read (see step below).
+template <typename T, typename KT, int TX, int RY, bool PRO, bool ADD>
+__device__ __forceinline__ void fetch_out(Prefetch<T, KT, TX, RY, PRO, ADD> &p, const StencilArgs &a, int z,
+                                          const size_t *gb)
+{
+    const size_t plane = (size_t)a.g.nx * a.g.ny;
+    const T *b = (const T *)a.b;  // NULL: a zero right-hand side
+    const size_t pl = plane * (size_t)(z - 1);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        p.bo[r] = b ? b[gb[r] + pl] : (T)0;
+        if constexpr (ADD) p.xo[r] = a.x64[gb[r] + pl];
+    }
+}
+
 template <typename T, typename KT, int IN, int TX, int RY, bool ADD>
-__device__ __forceinline__ void fetch(Prefetch<T, KT, TX, RY, IN != IN_PLAIN, ADD> &p,
-                                      const Geo<TX, RY, IN != IN_PLAIN> &G, const StencilArgs &a, int z, int z0,
-                                      const size_t *gb)
+__device__ __forceinline__ void fetch_in(Prefetch<T, KT, TX, RY, IN != IN_PLAIN, ADD> &p,
+                                         const Geo<TX, RY, IN != IN_PLAIN> &G, const StencilArgs &a, int z)
 {
     using TL = Tile<TX, RY>;
     const size_t plane = (size_t)a.g.nx * a.g.ny;
-    if (z - 1 >= z0) {
-        const T *b = (const T *)a.b;  // NULL: a zero right-hand side
-        const size_t pl = plane * (size_t)(z - 1);
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            p.bo[r] = b ? b[gb[r] + pl] : (T)0;
-            if constexpr (ADD) p.xo[r] = a.x64[gb[r] + pl];
-        }
-    }
     int sz = 1;
     const int fk = fold(z, a.g.nz, a.g.bc[4], a.g.bc[5], sz);
     p.zneg = sz < 0;
@@ -174,6 +182,15 @@ __device__ __forceinline__ void fetch(Prefetch<T, KT, TX, RY, IN != IN_PLAIN, AD
             p.c2[q] = e[g + p2];
         }
     }
+}
+
+template <typename T, typename KT, int IN, int TX, int RY, bool ADD>
+__device__ __forceinline__ void fetch(Prefetch<T, KT, TX, RY, IN != IN_PLAIN, ADD> &p,
+                                      const Geo<TX, RY, IN != IN_PLAIN> &G, const StencilArgs &a, int z, int z0,
+                                      const size_t *gb)
+{
+    if (z - 1 >= z0) fetch_out<T, KT, TX, RY, IN != IN_PLAIN, ADD>(p, a, z, gb);
+    fetch_in<T, KT, IN, TX, RY, ADD>(p, G, a, z);
 }
 
 // Write a prefetched plane to LDS (forming x + P e for the prolongation modes).
@@ -344,18 +361,18 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
     for (int q = 0; q < RP; ++q) zacc[q] = 0.0;
 
     // One output plane: commit plane z + 1 from slot p, refill the slot with
-    // plane z + 3 (two planes stay in flight), then finish plane z.
+    // plane z + 3 (two planes stay in flight), then finish plane z and load
+    // the output values of plane z + 2 into the registers it just read.
+    // The steady form (ST; PAR = z & 1 known) runs on tiles inside the grid
+    // with both residual outputs present: it issues the same loads and stores
+    // on every path, so the compiler's wait counts keep the next planes' loads
+    // in flight instead of waiting for every outstanding load.
     int buf = 0;
-    auto step = [&](Prefetch<T, KT, TX, RY, PRO, ADD> &p, int z) {
+    auto step = [&](auto st_tag, auto par_tag, Prefetch<T, KT, TX, RY, PRO, ADD> &p, int z) {
+        constexpr bool ST = decltype(st_tag)::value;
+        constexpr int PAR = decltype(par_tag)::value;
         commit<T, KT, IN, TX, RY, ADD>(p, G, sx[buf], sk[buf], sc);
-        T bcur[RY];
-        double xcur[ADD ? RY : 1];
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            bcur[r] = p.bo[r];
-            if constexpr (ADD) xcur[r] = p.xo[r];
-        }
-        if (z + 3 <= z1) fetch<T, KT, IN, TX, RY, ADD>(p, G, a, z + 3, z0, gb);
+        if (ST || z + 3 <= z1) fetch_in<T, KT, IN, TX, RY, ADD>(p, G, a, z + 3);
         plane_sums<T, HK, TX, RY>(sx[buf], sk[buf], lx, ly, ps);
         buf ^= 1;
         double rrow[RY];
@@ -363,7 +380,7 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
         for (int r = 0; r < RY; ++r) {
             const size_t g = g0 + (size_t)r * nx + plane * (size_t)z;
             const T y0 = run[r].xc;
-            const T bb = bcur[r] - bmT;
+            const T bb = p.bo[r] - bmT;
             T y = (T)0, Ay = (T)0;
             if constexpr (!HK) {
                 const T S = run[r].qx + ps[r].xo;
@@ -385,28 +402,30 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
             rrow[r] = 0.0;
             if constexpr (OUT == OUT_RESID) {
                 double rv = 0.0;
-                if (valid[r]) rv = ((double)bcur[r] - bm) - (double)Ay;
-                if (a.r && valid[r]) ((OT *)a.r)[g] = (OT)rv;
+                if (ST || valid[r]) rv = ((double)p.bo[r] - bm) - (double)Ay;
+                if (ST || (a.r && valid[r])) ((OT *)a.r)[g] = (OT)rv;
                 nacc += a.dot_x ? (double)y0 * rv : rv * rv;
                 rrow[r] = rv;
-            } else if (valid[r]) {
+            } else if (ST || valid[r]) {
                 if constexpr (OUT == OUT_STORE)
                     ((T *)a.yout)[g] = y;
                 else
-                    a.x64[g] = xcur[r] + (double)y;
+                    a.x64[g] = p.xo[r] + (double)y;
             }
         }
         absorb(false);
         if constexpr (OUT == OUT_RESID) {
-            if (a.rc) {
+            if (ST || a.rc) {
                 const int cx = nx >> 1, cy = ny >> 1;
 #pragma unroll
                 for (int q = 0; q < RP; ++q) {
                     double rs = rrow[2 * q] + rrow[2 * q + 1];
                     rs += __shfl_xor(rs, 1);
                     zacc[q] += rs;
-                    if (z & 1) {
-                        if (!(lx & 1) && valid[2 * q])
+                    if (ST ? (PAR == 1) : (z & 1)) {
+                        // both lanes of an x pair hold the same sum: in the steady form
+                        // both store it (one store instruction on every path)
+                        if (ST || (!(lx & 1) && valid[2 * q]))
                             ((OT *)a.rc)[(size_t)(gi >> 1) +
                                          (size_t)cx * ((size_t)((gj >> 1) + q) + (size_t)cy * (size_t)(z >> 1))] =
                                 (OT)zacc[q];
@@ -415,6 +434,8 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
                 }
             }
         }
+        // output values of plane z + 2 (its step comes two steps later)
+        if (ST || z + 3 <= z1) fetch_out<T, KT, TX, RY, PRO, ADD>(p, a, z + 3, gb);
     };
 
     // prologue: planes z0 - 1 and z0 into the running sums; planes z0 + 1 and
@@ -426,13 +447,32 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
     absorb(true);
     commit<T, KT, IN, TX, RY, ADD>(pA, G, sx[1], sk[1], sc);
     fetch<T, KT, IN, TX, RY, ADD>(pA, G, a, z0 + 1, z0, gb);
-    if (z0 + 2 <= z1) fetch<T, KT, IN, TX, RY, ADD>(pB, G, a, z0 + 2, z0, gb);
+    // plane z0 + 2 is fetched even when the chunk is shorter (its values are
+    // then unused; fold keeps the field plane in range and the output plane
+    // is clamped into the chunk), so that every path into the march below
+    // has the same loads in flight
+    fetch_out<T, KT, TX, RY, PRO, ADD>(pB, a, min(z0 + 2, z1), gb);
+    fetch_in<T, KT, IN, TX, RY, ADD>(pB, G, a, z0 + 2);
     plane_sums<T, HK, TX, RY>(sx[1], sk[1], lx, ly, ps);
     absorb(false);
 
-    for (int z = z0; z < z1; z += 2) {
-        step(pA, z);
-        if (z + 1 < z1) step(pB, z + 1);
+    const std::false_type gen{};
+    const std::true_type steady{};
+    const std::integral_constant<int, -1> anypar{};
+    const std::integral_constant<int, 0> even{};
+    const std::integral_constant<int, 1> odd{};
+    // the steady march: tiles inside the grid, chunks starting on an even plane
+    // (so the A steps are the even planes), both residual outputs present
+    const bool inside = i0 + TX <= nx && j0 + TL::TY <= ny && !(z0 & 1) &&
+                        (OUT != OUT_RESID || (a.r != nullptr && a.rc != nullptr));
+    int z = z0;
+    for (; inside && z + 4 <= z1; z += 2) {
+        step(steady, even, pA, z);
+        step(steady, odd, pB, z + 1);
+    }
+    for (; z < z1; z += 2) {
+        step(gen, anypar, pA, z);
+        if (z + 1 < z1) step(gen, anypar, pB, z + 1);
     }
 
     if constexpr (OUT == OUT_RESID) {
