@@ -70,8 +70,8 @@ KCLASS = {"resid": 0, "sweeps": 1, "sweep": 2}
 # change, the figure no longer describes the kernel and traffic is null.
 KERNEL_SOURCES = {"resid": ("mg_stencil.hip", "mg_device.h"),
                   "sweeps": ("mg_fused.hip", "mg_device.h")}
-MEASURED_TRAFFIC_FP64_256 = {"resid": (570.8e6, "85a0b1de8b285334"),
-                             "sweeps": (635.7e6, "4fae73de90d721fe")}
+MEASURED_TRAFFIC_FP64_256 = {"resid": (577.6e6, "222c5cd01dad4136"),
+                             "sweeps": (588.9e6, "64745bab8180d429")}
 
 
 def kernel_source_hash(cls):
@@ -379,9 +379,13 @@ def mass_study(nn4mg, torch, nx=32, steps=1000, ratio=2.0):
 
 def eq_speed_fit(nn4mg, torch, sizes=(64, 96, 128, 192, 256), steps=2):
     """Eq. speed on this GPU: the collapsing-column step timed at several grid
-    sizes, then M_s and H_s fitted by least squares through the origin
-    (explicit time = N M_s, pressure-solve time = N (N_h + N_I N_nh) H_s, p = 1),
-    with each size's deviation from the fitted model."""
+    sizes, then M_s and H_s fitted by least squares, p = 1.  The headline fit
+    is affine (explicit time = c_M + N M_s, pressure-solve time =
+    c_H + N (N_h + N_I N_nh) H_s): the fixed terms are the launch-bound cost of
+    the coarse levels and small kernels, which the paper's model (a line
+    through the origin) has no room for and which dominates small grids here.
+    The through-origin fit of the paper's form is reported beside it, with each
+    size's deviation from both."""
     import numpy as np
 
     pts = []
@@ -401,13 +405,17 @@ def eq_speed_fit(nn4mg, torch, sizes=(64, 96, 128, 192, 256), steps=2):
     # affine fits: a fixed per-step cost (launch-bound coarse levels, small grids) plus the per-node slope
     A = np.stack([np.ones_like(N), N], axis=1)
     (ex0, Ms_a), (mg0, mgs) = np.linalg.lstsq(A, ex, rcond=None)[0], np.linalg.lstsq(A, mg, rcond=None)[0]
+    model_a = (ex0 + N * Ms_a) + (mg0 + N * mgs)
     return {"sizes": [q[0] for q in pts], "ms_per_step": [q[2] for q in pts],
             "ms_pressure_solves": [q[3] for q in pts], "ms_explicit": [q[4] for q in pts],
-            "cycles_per_step": cycles, "M_s": Ms, "H_s": Hs,
-            "model_rel_error": [round(float(v), 3) for v in (model - meas) / meas],
-            "fit": "least squares through the origin over the sizes listed, p = 1",
-            "affine": {"M_s": float(Ms_a), "H_s": float(mgs / cycles), "explicit_fixed_ms": round(float(ex0) * 1e3, 3),
-                       "solves_fixed_ms": round(float(mg0) * 1e3, 3)},
+            "cycles_per_step": cycles,
+            "M_s": float(Ms_a), "H_s": float(mgs / cycles),
+            "explicit_fixed_ms": round(float(ex0) * 1e3, 3), "solves_fixed_ms": round(float(mg0) * 1e3, 3),
+            "model_rel_error": [round(float(v), 3) for v in (model_a - meas) / meas],
+            "fit": "affine least squares over the sizes listed (fixed per-step cost + per-node slope), p = 1",
+            "through_origin": {"M_s": Ms, "H_s": Hs,
+                               "model_rel_error": [round(float(v), 3) for v in (model - meas) / meas],
+                               "fit": "least squares through the origin, the paper's form"},
             "paper_context": {"A10": {"M_s": 1.2e-8, "H_s": 1.1e-10}, "RTX A5000": {"M_s": 1.37e-8, "H_s": 1.3e-10}}}
 
 
