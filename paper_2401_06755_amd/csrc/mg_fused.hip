@@ -291,18 +291,22 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
             p.c2[q] = ep[p2 + (size_t)G.coff[q]];
         }
     };
-    // ST (steady): the caller guarantees the plane conditions, so the loads
-    // are issued unconditionally
-    auto fetch_b = [&](auto st_tag, FPre<T, KT, TX, RY, ADD> &p, int zi) {
-        constexpr bool ST = decltype(st_tag)::value;
-        if (ST || (zi - 1 >= z0 - 1 && zi - 1 <= z1)) {
+    // MODE 0: general (every load conditional on the planes of the chunk);
+    // 1 (steady) and 2 (the first steps when the steady march follows): the
+    // loads are issued unconditionally, mode 2 clamping the planes into the
+    // chunk (values it loads for planes without an output are never used).
+    auto fetch_b = [&](auto mode_tag, FPre<T, KT, TX, RY, ADD> &p, int zi) {
+        constexpr int MODE = decltype(mode_tag)::value;
+        if (MODE != 0 || (zi - 1 >= z0 - 1 && zi - 1 <= z1)) {
+            const int zb = MODE == 2 ? min(max(zi - 1, z0 - 1), z1) : zi - 1;
             int sb = 1;
-            const size_t pb = plane * (size_t)fold(zi - 1, nz, a.g.bc[4], a.g.bc[5], sb);
+            const size_t pb = plane * (size_t)fold(zb, nz, a.g.bc[4], a.g.bc[5], sb);
 #pragma unroll
             for (int q = 0; q < TL::R1; ++q) p.b1[q] = bp[pb + (size_t)G.boff[q]];
         }
-        if (ST || (zi - 2 >= z0 && zi - 2 < z1)) {
-            const size_t pl = plane * (size_t)(zi - 2);
+        if (MODE != 0 || (zi - 2 >= z0 && zi - 2 < z1)) {
+            const int zo = MODE == 2 ? min(max(zi - 2, z0), z1 - 1) : zi - 2;
+            const size_t pl = plane * (size_t)zo;
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 p.b2[r] = bp[pl + gb[r]];
@@ -312,7 +316,7 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     };
     auto fetch = [&](FPre<T, KT, TX, RY, ADD> &p, int zi) {
         fetch_kc(p, zi);
-        fetch_b(std::false_type{}, p, zi);
+        fetch_b(std::integral_constant<int, 0>{}, p, zi);
     };
 
     // P e of plane zi into sx[buf] (coarse footprint staged in LDS first),
@@ -352,8 +356,10 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     // path, so the compiler's wait counts let the loads of the next two planes
     // stay in flight; the general form serves the first and last steps of the
     // march and tiles that cross the grid's edge.
-    auto step = [&](auto st_tag, FPre<T, KT, TX, RY, ADD> &p, int zi) {
-        constexpr bool ST = decltype(st_tag)::value;
+    auto step = [&](auto mode_tag, FPre<T, KT, TX, RY, ADD> &p, int zi) {
+        constexpr int MODE = decltype(mode_tag)::value;
+        constexpr bool ST = MODE == 1;  // steady: every condition below holds
+        constexpr bool FX = MODE != 0;  // fixed loads
         commit(p, zi, buf);
         bool bzneg = false;
         {
@@ -361,7 +367,7 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
             (void)fold(zi - 1, nz, a.g.bc[4], a.g.bc[5], sb);
             bzneg = sb < 0;
         }
-        if (ST || zi + 2 <= z1 + 1) fetch_kc(p, zi + 2);
+        if (FX || zi + 2 <= z1 + 1) fetch_kc(p, zi + 2);
 
         // first sweep: absorb plane zi down the thread's strip, completing y1(zi - 1)
         const int yb = (zi - 1) & 1;
@@ -405,7 +411,7 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
                 const PS<T> ps = col_sums<T, HK>(w0, w1, w2);
                 w0 = w1;
                 w1 = w2;
-                if (ST || zi >= z0 + 2) {
+                if (ST || (MODE == 0 && zi >= z0 + 2)) {  // mode 2 steps have no output plane
                     const T y = jacobi<T, HK>(r2[r], ps, p.b2[r], cw, om_w0, om, icv);
                     const size_t g = gb[r] + plane * (size_t)(zi - 2);
                     if (ST || valid[r]) {  // the steady march runs only on tiles inside the grid
@@ -419,28 +425,33 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
             }
         }
         // right-hand sides of plane zi + 2's step, into the registers just consumed
-        if (ST || zi + 2 <= z1 + 1) fetch_b(st_tag, p, zi + 2);
+        if (FX || zi + 2 <= z1 + 1) fetch_b(mode_tag, p, zi + 2);
         buf = (buf + 1) % 3;
     };
 
     fetch(pA, z0 - 2);
     fetch(pB, z0 - 1);
-    const std::false_type gen{};
-    const std::true_type steady{};
+    const std::integral_constant<int, 0> gen{};
+    const std::integral_constant<int, 1> steady{};
+    const std::integral_constant<int, 2> first{};
     int zi = z0 - 2;
-    // the first four steps (no output plane yet) ...
-    for (; zi < z0 + 2 && zi <= z1 + 1; zi += 2) {
-        step(gen, pA, zi);
-        if (zi + 1 <= z1 + 1) step(gen, pB, zi + 1);
+    // Tiles inside the grid with at least four planes in the chunk run the
+    // first four steps (no output plane yet) with fixed loads and then the
+    // steady march, both steps of a pair with all their loads and stores
+    // (zi >= z0 + 2 stores; zi + 3 <= z1 + 1 keeps every fetched plane in the
+    // chunk); every path into the steady loop then has the same loads in
+    // flight.  Other tiles, and the last steps, take the general form.
+    const bool inside = i0 + TX <= nx && j0 + TL::TY <= ny && z1 - z0 >= 4;  // uniform over the workgroup
+    if (inside) {
+        for (; zi < z0 + 2; zi += 2) {
+            step(first, pA, zi);
+            step(first, pB, zi + 1);
+        }
+        for (; zi + 3 <= z1 + 1; zi += 2) {
+            step(steady, pA, zi);
+            step(steady, pB, zi + 1);
+        }
     }
-    // ... the steady march, both steps of a pair with all their loads and stores
-    // (zi >= z0 + 2 stores; zi + 3 <= z1 + 1 keeps every fetched plane in the chunk) ...
-    const bool inside = i0 + TX <= nx && j0 + TL::TY <= ny;  // uniform over the workgroup
-    for (; inside && zi + 3 <= z1 + 1; zi += 2) {
-        step(steady, pA, zi);
-        step(steady, pB, zi + 1);
-    }
-    // ... and the last steps
     for (; zi <= z1 + 1; zi += 2) {
         step(gen, pA, zi);
         if (zi + 1 <= z1 + 1) step(gen, pB, zi + 1);
