@@ -42,11 +42,14 @@ HBM_PEAK_GBPS = 8000.0
 
 # Algorithmic bytes per finest cell of each finest-level kernel class: every
 # array the kernel needs is read once and every output written once.  With the
-# default two post-sweeps, both run in one pass ("sweeps") that smooths the
-# correction against the residual the residual kernel writes out.
+# default two post-sweeps, both run in one pass ("sweeps").  In FP64 that pass
+# smooths x + P e_1 against b and writes the new iterate to a second buffer, so
+# the residual kernel writes only the restricted residual; in mixed precision it
+# smooths the FP32 correction against the FP32 residual the residual kernel
+# writes out.
 BYTES_PER_CELL = {
-    "fp64": {"resid": 8 + 8 + 8 + 8 + 1,      # x, b, k; r, restricted residual (1/8 cell)
-             "sweeps": 1 + 8 + 8 + 8 + 8,     # e_1 (1/8), r, k; x read + write
+    "fp64": {"resid": 8 + 8 + 8 + 1,          # x, b, k; restricted residual (1/8 cell)
+             "sweeps": 1 + 8 + 8 + 8 + 8,     # e_1 (1/8), x, b, k; x' written
              "sweep": 8 + 8 + 8 + 8},         # (nu_post != 2 only) y, b, k; x
     "mixed": {"resid": 8 + 8 + 8 + 4 + 0.5,   # x, b, k (FP64); r32, restricted r32
               "sweeps": 0.5 + 4 + 4 + 8 + 8,  # e_1 (FP32, 1/8), r32, k32; x64 read + write
@@ -54,10 +57,29 @@ BYTES_PER_CELL = {
     "fp16": {"resid": 8 + 8 + 8 + 4 + 0.5,    # as mixed, smoothing with the FP16 copy of k
              "sweeps": 0.5 + 4 + 2 + 8 + 8,
              "sweep": 4 + 4 + 2 + 8 + 8},
-    "fp64c": {"resid": 8 + 8 + 8 + 1,         # constant coefficient: no k
+    "fp64c": {"resid": 8 + 8 + 1,             # constant coefficient: no k
               "sweeps": 1 + 8 + 8 + 8,
               "sweep": 8 + 8 + 8},
 }
+# FP64 with the finest sweeps in the 8^3 block form (an autotuner choice on
+# small grids): the correction is smoothed against the full residual r, which
+# the residual kernel writes out, and added into x.
+BYTES_PER_CELL_BLOCK = {
+    "fp64": {"resid": 8 + 8 + 8 + 8 + 1,      # x, b, k; r, restricted residual
+             "sweeps": 1 + 8 + 8 + 8 + 8,     # e_1, r, k; x read + write
+             "sweep": 8 + 8 + 8 + 8},
+    "fp64c": {"resid": 8 + 8 + 8 + 1,
+              "sweeps": 1 + 8 + 8 + 8,
+              "sweep": 8 + 8 + 8},
+}
+
+
+def fine_bytes(mode, res):
+    """Bytes per finest cell of each kernel class in the run `res`."""
+    tiles = res.get("tiles")
+    if mode in BYTES_PER_CELL_BLOCK and tiles and list(tiles[0][1]) == [8, 8, 8]:
+        return BYTES_PER_CELL_BLOCK[mode]
+    return BYTES_PER_CELL[mode]
 # bytes per cell of the coefficient on the coarse levels, per mode
 COARSE_K_BYTES = {"fp64": 8, "mixed": 4, "fp16": 2, "fp64c": 0}
 KCLASS = {"resid": 0, "sweeps": 1, "sweep": 2}
@@ -66,10 +88,11 @@ KCLASS = {"resid": 0, "sweeps": 1, "sweep": 2}
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for
 # a plain 256 MiB device copy (fetch x2.0, write x1.0); the commands and raw
 # counts are in profiles/dense_sphere_256_fp64_fine_kernels.md.  Each figure
-# carries a hash of the kernel's source files as profiled; once those files
-# change, the figure no longer describes the kernel and traffic is null.
-KERNEL_SOURCES = {"resid": ("mg_stencil.hip", "mg_device.h"),
-                  "sweeps": ("mg_fused.hip", "mg_device.h")}
+# carries a hash of the kernel's source files and of the host driver that
+# chooses its arguments, as profiled; once those files change, the figure no
+# longer describes the kernel and traffic is null.
+KERNEL_SOURCES = {"resid": ("mg_stencil.hip", "mg_device.h", "mg_api.hip"),
+                  "sweeps": ("mg_fused.hip", "mg_device.h", "mg_api.hip")}
 MEASURED_TRAFFIC_FP64_256 = {"resid": (577.6e6, "222c5cd01dad4136"),
                              "sweeps": (588.9e6, "64745bab8180d429")}
 
@@ -94,15 +117,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cycle_model_bytes(levels, mode):
+def cycle_model_bytes(res, mode):
     """Algorithmic bytes of one V(0,2) cycle over all levels (finest kernels as
     above; coarse level l: restriction w + w/8 B, both sweeps in one pass
     reading e_{l+1} (w/8), b, k and writing e (3w); FP32 on coarse levels in
     mixed mode; no k with a constant coefficient)."""
+    levels = res["levels"]
     w = 8 if mode in ("fp64", "fp64c") else 4
     kb = COARSE_K_BYTES[mode]
     n0 = levels[0][0] * levels[0][1] * levels[0][2]
-    tot = n0 * (BYTES_PER_CELL[mode]["resid"] + BYTES_PER_CELL[mode]["sweeps"])
+    fb = fine_bytes(mode, res)
+    tot = n0 * (fb["resid"] + fb["sweeps"])
     for l in range(1, len(levels) - 1):
         n = levels[l][0] * levels[l][1] * levels[l][2]
         tot += n * ((w + w / 8) + (w / 8 + 2 * w + kb))
@@ -194,14 +219,15 @@ def roofline(res, mode, traffic=None):
             best = name
     cnt, ms = res["kern"][best]
     avg_s = ms / cnt / 1e3
-    bytes_per_launch = BYTES_PER_CELL[mode][best] * res["n"]
+    fb = fine_bytes(mode, res)
+    bytes_per_launch = fb[best] * res["n"]
     achieved = bytes_per_launch / avg_s / 1e9
     per_kernel = {}
     for name, (c, m) in res["kern"].items():
         if c:
-            a = BYTES_PER_CELL[mode][name] * res["n"] / (m / c / 1e3) / 1e9
+            a = fb[name] * res["n"] / (m / c / 1e3) / 1e9
             per_kernel[name] = {"launches": c, "avg_us": round(m / c * 1e3, 2), "GBps": round(a, 1),
-                                "bytes_per_cell": BYTES_PER_CELL[mode][name]}
+                                "bytes_per_cell": fb[name]}
     tr = traffic.get(best) if traffic else None
     return best, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                   "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": tr}, per_kernel
@@ -449,7 +475,7 @@ def bubble_bench(nn4mg, torch, inputs, steps, rtol):
     x16, x64 = r16["x"], r64["x"]
     err = float(torch.linalg.vector_norm(x16 - x64) / torch.linalg.vector_norm(x64))
     best, roof, pk = roofline(r16, "fp16")
-    model = cycle_model_bytes(r16["levels"], "fp16")
+    model = cycle_model_bytes(r16, "fp16")
     return {"workload": "rising bubble 256x256x512 on a 1x1x2 box, air sphere r=0.25 at (0.5,0.5,0.5) in water "
                         "(rho 1/1000), zero pressure on top, Neumann elsewhere, Gaussian RHS",
             "dtype": "f16-stored k, f32 smoothing, f64 residual/coarsest/refinement",
@@ -612,7 +638,7 @@ def main():
     value = r64["n"] * r64["cycles"] / r64["dt"] / 1e9
     best, roof, per_kernel = roofline(r64, "fp64",
                                       measured_traffic(MEASURED_TRAFFIC_FP64_256) if args.n == 256 else None)
-    model_bytes = cycle_model_bytes(r64["levels"], "fp64")
+    model_bytes = cycle_model_bytes(r64, "fp64")
     out = {
         "metric": "V-cycle Gcell-updates/s (solve to relative residual 1e-8)",
         "value": round(value, 3),

@@ -272,8 +272,10 @@ struct nn4mg_hier {
     double *fcg_part = nullptr;  // FCG dot-product partials
     size_t bytes = 0;
     std::vector<void *> allocs;
-    // captured hipGraph of one stationary iteration (body + residual + stopping rule)
-    hipGraphExec_t graph = nullptr;
+    // captured hipGraphs of one stationary iteration (body + residual + stopping
+    // rule), from x into lv[0].t and back (one graph unless the finest sweeps
+    // take the direct form)
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
     const double *graph_b = nullptr;
     double *graph_x = nullptr;
     bool graphs_ok = true;  // cleared after a capture failure
@@ -311,8 +313,10 @@ int dalloc(nn4mg_hier *H, P **p, size_t count)
 void release(nn4mg_hier *H)
 {
     if (H->stream) (void)hipStreamSynchronize(H->stream);
-    if (H->graph) (void)hipGraphExecDestroy(H->graph);
-    H->graph = nullptr;
+    for (hipGraphExec_t &g : H->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
     for (hipEvent_t e : H->prof_ev) (void)hipEventDestroy(e);
     H->prof_ev.clear();
     for (void *p : H->allocs) (void)hipFree(p);
@@ -528,8 +532,10 @@ TileShape sweep2_tiles(const nn4mg_hier *H, int l)
 }
 
 // Both sweeps of level l from P e_{l+1} against the right-hand side b:
-// out_mode OUT_STORE into y, or OUT_ADD64 into x64.
-int enqueue_sweep2(nn4mg_hier *H, int l, const void *b, void *y, double *x64, int out_mode, const int *done)
+// out_mode OUT_STORE into y, or OUT_ADD64 into x64.  With xin (FP64, marching
+// form only): from xin + P e_{l+1} against b - bmean, stored into y != xin.
+int enqueue_sweep2(nn4mg_hier *H, int l, const void *b, void *y, double *x64, int out_mode, const int *done,
+                   const double *xin = nullptr, const double *bmean = nullptr)
 {
     const bool f64 = !H->mixed;
     StencilArgs a = base_args(H, l, NN4MG_KCLASS_FINE_SWEEP_PROLONG);
@@ -537,14 +543,18 @@ int enqueue_sweep2(nn4mg_hier *H, int l, const void *b, void *y, double *x64, in
     a.b = b;
     a.k = f64 ? (const void *)H->lv[l].k : H->lv[l].ks;
     a.ec = f64 ? (const void *)H->lv[l + 1].e : (const void *)H->lv[l + 1].e32;
+    a.yin = xin;
+    a.bmean = bmean;
     a.yout = y;
     a.x64 = x64;
     a.done = done;
     const long pr = prof_begin(H, NN4MG_KCLASS_FINE_SWEEP_PROLONG, l);
-    if (H->lv[l].block2)
+    if (xin)
+        HIP_TRY(launch_sweep2(1, H->kt64, IN_PROLONG_ADD, OUT_STORE, a, H->stream));
+    else if (H->lv[l].block2)
         HIP_TRY(launch_sweep2_block(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, out_mode, a, H->stream));
     else
-        HIP_TRY(launch_sweep2(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, out_mode, a, H->stream));
+        HIP_TRY(launch_sweep2(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, IN_PROLONG, out_mode, a, H->stream));
     prof_end(H, pr);
     return NN4MG_OK;
 }
@@ -556,6 +566,16 @@ bool level_fusable(const nn4mg_hier *H, int l)
 {
     const Level &V = H->lv[l];
     return H->fused && V.nx >= 4 && V.ny >= 4 && V.nz >= 4;
+}
+
+// FP64 cycles whose finest sweeps run in the marching two-sweep pass take the
+// direct form x' = S S (x + P e_1) against b - bmean: the finest residual
+// kernel then writes only R r and the norm partials (no full r), and the pass
+// reads x on its two-cell ring, so x' goes to a second buffer (lv[0].t) and
+// successive cycles alternate between x and lv[0].t.
+bool direct_fine(const nn4mg_hier *H)
+{
+    return !H->mixed && H->L > 1 && level_fusable(H, 0) && !H->lv[0].block2;
 }
 
 // nu_post Jacobi sweeps at level l >= 1 (first input: P e_{l+1}); result in e.
@@ -596,17 +616,21 @@ int enqueue_coarse_sweeps(nn4mg_hier *H, int l, const int *done)
 }
 
 // Finest-level sweeps: FP64: x <- smooth(x + P e_1) (x_zero: smooth(P e_1), x
-// not read); mixed: x += smooth(P e_1).
+// not read; direct form: the result goes to x_out); mixed: x += smooth(P e_1).
 int enqueue_fine_sweeps(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done,
-                        bool x_zero = false)
+                        bool x_zero = false, double *x_out = nullptr)
 {
     Level &F = H->lv[0];
     const int nu = H->cfg.nu_post;
     if (level_fusable(H, 0)) {
         if (H->mixed) return enqueue_sweep2(H, 0, F.b32, nullptr, x, OUT_ADD64, done);
-        // FP64: the correction is smoothed against the full residual (written by
-        // the residual kernel into F.t, or the preconditioner's own r)
         if (x_zero) return enqueue_sweep2(H, 0, b, x, nullptr, OUT_STORE, done);
+        if (direct_fine(H)) {
+            if (!x_out || x_out == x) return fail(NN4MG_EINVAL, "direct finest sweeps need a second buffer");
+            return enqueue_sweep2(H, 0, b, x_out, nullptr, OUT_STORE, done, x, bmean);
+        }
+        // the 8^3 block form: the correction is smoothed against the full
+        // residual the residual kernel wrote into F.t
         return enqueue_sweep2(H, 0, F.t, nullptr, x, OUT_ADD64, done);
     }
     if (!H->mixed) {
@@ -676,8 +700,9 @@ int resid_blocks(const nn4mg_hier *H) { return H->lv[0].tiles[NN4MG_KCLASS_FINE_
 // lv[0].b32).
 // stop_np > 0: the first restriction-chain launch also applies the stopping
 // rule to the stop_np norm partials in H->partials.
+// x_out: where the direct form of the finest sweeps puts the new iterate.
 int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done,
-                       bool x_zero = false, int stop_np = 0)
+                       bool x_zero = false, int stop_np = 0, double *x_out = nullptr)
 {
     const bool f64 = !H->mixed;
     const int L = H->L;
@@ -726,7 +751,7 @@ int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, doub
         HIP_TRY(launch_tail(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, ta, s));
         for (int l = T - 1; l >= 1; --l)
             if ((rc = enqueue_coarse_sweeps(H, l, done))) return rc;
-        return enqueue_fine_sweeps(H, b, bmean, x, done, x_zero);
+        return enqueue_fine_sweeps(H, b, bmean, x, done, x_zero, x_out);
     }
     for (int l = 1; l + 1 < L; ++l) {
         Level &V = H->lv[l];
@@ -738,7 +763,7 @@ int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, doub
                                 H->ainv, H->nc, H->singular, done, s));
     for (int l = L - 2; l >= 1; --l)
         if ((rc = enqueue_coarse_sweeps(H, l, done))) return rc;
-    return enqueue_fine_sweeps(H, b, bmean, x, done, x_zero);
+    return enqueue_fine_sweeps(H, b, bmean, x, done, x_zero, x_out);
 }
 
 // One outer iteration starting with the finest residual.  For a single-level
@@ -753,8 +778,10 @@ int enqueue_resid_for_cycle(nn4mg_hier *H, const double *b, const double *x, con
     }
     if (H->mixed)
         return enqueue_resid(H, x, b, bmean, H->lv[0].b32, H->lv[1].b32, true, with_norm, done);
-    // the fused finest sweeps smooth the correction against the full residual
-    return enqueue_resid(H, x, b, bmean, H->fused ? H->lv[0].t : nullptr, H->lv[1].b, false, with_norm, done);
+    // the 8^3 block form of the finest sweeps smooths the correction against
+    // the full residual; the direct form needs none
+    const bool full = H->fused && !direct_fine(H);
+    return enqueue_resid(H, x, b, bmean, full ? H->lv[0].t : nullptr, H->lv[1].b, false, with_norm, done);
 }
 
 int enqueue_single_level_body(nn4mg_hier *H, double *x, const int *done)
@@ -776,11 +803,32 @@ int enqueue_single_level_body(nn4mg_hier *H, double *x, const int *done)
 // the coarse end); otherwise as its own launch after each residual.
 bool stop_in_chain(const nn4mg_hier *H) { return H->L > 1 && H->tail > 2; }
 
+// One cycle body from x; the new iterate is in x, or (direct_fine) in x_out.
 int enqueue_body(nn4mg_hier *H, const double *b, const double *bmean, double *x, const int *done,
-                 bool with_stop = false)
+                 bool with_stop = false, double *x_out = nullptr)
 {
     if (H->L == 1) return enqueue_single_level_body(H, x, done);
-    return enqueue_cycle_body(H, b, bmean, x, done, false, with_stop && stop_in_chain(H) ? resid_blocks(H) : 0);
+    return enqueue_cycle_body(H, b, bmean, x, done, false, with_stop && stop_in_chain(H) ? resid_blocks(H) : 0,
+                              x_out);
+}
+
+// One cycle (finest residual, then the body) from x back into x, as the
+// one-cycle entry point and the autotuner's trials run it.  The direct form
+// goes through lv[0].t; `par` selects the way round (the autotuner alternates
+// and ends on x).
+int enqueue_cycle_inplace(nn4mg_hier *H, const double *b, double *x, int par = -1)
+{
+    int rc;
+    if (!direct_fine(H)) {
+        if ((rc = enqueue_resid_for_cycle(H, b, x, nullptr, false, nullptr))) return rc;
+        return enqueue_body(H, b, nullptr, x, nullptr);
+    }
+    double *t = H->lv[0].t;
+    double *src = par == 1 ? t : x, *dst = par == 1 ? x : t;
+    if ((rc = enqueue_resid_for_cycle(H, b, src, nullptr, false, nullptr))) return rc;
+    if ((rc = enqueue_body(H, b, nullptr, src, nullptr, false, dst))) return rc;
+    if (par < 0) HIP_TRY(launch_copy(x, t, H->lv[0].n, nullptr, H->stream));
+    return NN4MG_OK;
 }
 
 }  // namespace
@@ -1096,13 +1144,21 @@ int enqueue_b_norm(nn4mg_hier *H, const double *b)
     return NN4MG_OK;
 }
 
-int enqueue_stationary_iteration(nn4mg_hier *H, const double *b, double *x)
+// Iteration `par` (0 or 1, the parity of its index in the solve): with the
+// direct finest sweeps, even iterations take x to lv[0].t and odd ones back.
+int enqueue_stationary_iteration(nn4mg_hier *H, const double *b, double *x, int par)
 {
     int rc;
     H->cur_tag += 1;
     const int *done = &H->st->done;
-    if ((rc = enqueue_body(H, b, H->singular ? &H->st->bmean : nullptr, x, done, true))) return rc;
-    if ((rc = enqueue_resid_for_cycle(H, b, x, H->singular ? &H->st->bmean : nullptr, true, done))) return rc;
+    const double *bmean = H->singular ? &H->st->bmean : nullptr;
+    double *src = x, *dst = x;
+    if (direct_fine(H)) {
+        src = par ? H->lv[0].t : x;
+        dst = par ? x : H->lv[0].t;
+    }
+    if ((rc = enqueue_body(H, b, bmean, src, done, true, dst))) return rc;
+    if ((rc = enqueue_resid_for_cycle(H, b, dst, bmean, true, done))) return rc;
     // with the rule in the next cycle's chain, the residual is judged there
     // (or by the stand-alone launch that ends each batch)
     if (!stop_in_chain(H)) HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), H->stream));
@@ -1190,10 +1246,16 @@ int enqueue_fcg_iteration(nn4mg_hier *H, double *x)
     return NN4MG_OK;
 }
 
-int enqueue_iteration(nn4mg_hier *H, const double *b, double *x)
+int enqueue_iteration(nn4mg_hier *H, const double *b, double *x, int par)
 {
     if (H->cfg.outer == NN4MG_OUTER_FCG) return enqueue_fcg_iteration(H, x);
-    return enqueue_stationary_iteration(H, b, x);
+    return enqueue_stationary_iteration(H, b, x, par);
+}
+
+// Parity of iteration `index` of a solve: which graph (and buffer order) it uses.
+int iteration_parity(const nn4mg_hier *H, int index)
+{
+    return (H->cfg.outer != NN4MG_OUTER_FCG && direct_fine(H)) ? (index & 1) : 0;
 }
 
 int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady_clock::time_point t0)
@@ -1203,6 +1265,8 @@ int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady
     StateHeader hd;
     int rc;
     if ((rc = read_header(H, &hd))) return rc;
+    // an odd number of direct-form cycles leaves the iterate in lv[0].t
+    if (iteration_parity(H, hd.nres > 0 ? hd.nres - 1 : 0)) HIP_TRY(launch_copy(x, H->lv[0].t, n, nullptr, s));
     if (hd.nb == 0.0) {
         HIP_TRY(launch_fill(x, n, 0.0, s));
     } else if (H->singular && hd.status != -5) {
@@ -1231,16 +1295,23 @@ int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady
     return status;
 }
 
-// Capture one stationary iteration on the handle's stream as a graph bound to
-// (b, x).  Returns false (and launches nothing) if capture is not possible.
-bool capture_iteration(nn4mg_hier *H, const double *b, double *x)
+// Capture one stationary iteration of parity `par` on the handle's stream as
+// a graph bound to (b, x).  Returns false (and launches nothing) if capture is
+// not possible.
+bool capture_iteration(nn4mg_hier *H, const double *b, double *x, int par)
 {
     if (!H->graphs_ok || H->stream == nullptr || H->prof_on) return false;
-    if (H->graph && H->graph_b == b && H->graph_x == x && H->graph_epoch == H->tiles_epoch) return true;
-    if (H->graph) {
-        (void)hipGraphExecDestroy(H->graph);
-        H->graph = nullptr;
+    if (H->graph_b != b || H->graph_x != x || H->graph_epoch != H->tiles_epoch) {
+        for (hipGraphExec_t &ge : H->graph)
+            if (ge) {
+                (void)hipGraphExecDestroy(ge);
+                ge = nullptr;
+            }
+        H->graph_b = b;
+        H->graph_x = x;
+        H->graph_epoch = H->tiles_epoch;
     }
+    if (H->graph[par]) return true;
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(H->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
@@ -1248,7 +1319,7 @@ bool capture_iteration(nn4mg_hier *H, const double *b, double *x)
         return false;
     }
     const int saved_tag = H->cur_tag;
-    const int rc = enqueue_iteration(H, b, x);
+    const int rc = enqueue_iteration(H, b, x, par);
     H->cur_tag = saved_tag;
     const hipError_t e = hipStreamEndCapture(H->stream, &g);
     if (rc != NN4MG_OK || e != hipSuccess || !g) {
@@ -1265,10 +1336,7 @@ bool capture_iteration(nn4mg_hier *H, const double *b, double *x)
         H->graphs_ok = false;
         return false;
     }
-    H->graph = ex;
-    H->graph_b = b;
-    H->graph_x = x;
-    H->graph_epoch = H->tiles_epoch;
+    H->graph[par] = ex;
     return true;
 }
 
@@ -1305,12 +1373,14 @@ int solve_enqueue_next(nn4mg_hier *H, const double *b, double *x)
     int rc;
     const int n = H->solve_planned;
     if (n <= 0) return NN4MG_OK;
-    if (capture_iteration(H, b, x)) {
-        for (int c = 0; c < n; ++c) HIP_TRY(hipGraphLaunch(H->graph, H->stream));
+    const int p0 = iteration_parity(H, H->solve_enqueued), p1 = iteration_parity(H, H->solve_enqueued + 1);
+    if (capture_iteration(H, b, x, p0) && (n == 1 || capture_iteration(H, b, x, p1))) {
+        for (int c = 0; c < n; ++c)
+            HIP_TRY(hipGraphLaunch(H->graph[iteration_parity(H, H->solve_enqueued + c)], H->stream));
         H->cur_tag += n;
     } else {
         for (int c = 0; c < n; ++c)
-            if ((rc = enqueue_iteration(H, b, x))) return rc;
+            if ((rc = enqueue_iteration(H, b, x, iteration_parity(H, H->solve_enqueued + c)))) return rc;
     }
     // the last residual of the batch is judged before the host reads the state
     if (H->cfg.outer != NN4MG_OUTER_FCG && stop_in_chain(H))
@@ -1517,8 +1587,7 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
                     HIP_TRY(hipStreamSynchronize(H->stream));
                     clear();
                 }
-                if ((rc = enqueue_resid_for_cycle(H, b, x, nullptr, false, nullptr))) return rc;
-                if ((rc = enqueue_body(H, b, nullptr, x, nullptr))) return rc;
+                if ((rc = enqueue_cycle_inplace(H, b, x, r & 1))) return rc;
             }
             H->prof_on = false;
             for (int l = 0; l < L; ++l) {
@@ -1556,8 +1625,7 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
                     HIP_TRY(hipStreamSynchronize(H->stream));
                     clear();
                 }
-                if ((rc = enqueue_resid_for_cycle(H, b, x, nullptr, false, nullptr))) return rc;
-                if ((rc = enqueue_body(H, b, nullptr, x, nullptr))) return rc;
+                if ((rc = enqueue_cycle_inplace(H, b, x, r & 1))) return rc;
             }
             H->prof_on = false;
             for (int l = 0; l < L; ++l) {
@@ -1587,9 +1655,7 @@ int nn4mg_autotune(nn4mg_t H, const double *b, double *x, int *tiles_out, int ma
 int nn4mg_vcycle(nn4mg_t H, const double *b, double *x)
 {
     if (!H || !b || !x) return fail(NN4MG_EINVAL, "NULL argument");
-    int rc;
-    if ((rc = enqueue_resid_for_cycle(H, b, x, nullptr, false, nullptr))) return rc;
-    return enqueue_body(H, b, nullptr, x, nullptr);
+    return enqueue_cycle_inplace(H, b, x);
 }
 
 int nn4mg_solve(nn4mg_t H, const double *b, double *x, double rtol, int max_cycles, int fixed_cycles,

@@ -15,12 +15,14 @@
 // (Dirichlet -mirror, Neumann +mirror, periodic wrap), so they hold the halo
 // values of the first sweep's output.
 // The input of the first sweep is the prolongated correction P e of the
-// coarser level (no fine-level iterate is read), so the pair computes the
-// correction of this level for the right-hand side b: with b = r = b - A x
-// (the residual the finest residual kernel already forms) and x += e this is
-// exactly x <- S S (x + P e), since the Jacobi sweep is affine.  Output: the
+// coarser level, so the pair computes the correction of this level for the
+// right-hand side b: with b = r = b - A x and x += e this is exactly
+// x <- S S (x + P e), since the Jacobi sweep is affine.  Output: the
 // correction stored (coarse levels, preconditioner z) or added into an FP64
-// field (finest level).
+// field (mixed precision at the finest level).  In the XIN form (FP64 finest
+// level) the input is x + P e itself, x staged with the same two-cell ring,
+// against b - mean(b), and the new iterate is stored into a second buffer:
+// the finest residual kernel then has no full residual to write.
 // Each thread of the first sweep walks a vertical strip of cells and the
 // second sweep its RY output rows: every row of the 3-wide neighbourhood is
 // read from LDS once and reduced to the pair sum of its side cells and its
@@ -68,7 +70,8 @@ struct FTile {
 template <int TX, int RY>
 struct FGeo {
     using TL = FTile<TX, RY>;
-    int off[TL::NPRE];    // folded in-plane offset of each input slot (coefficient)
+    int off[TL::NPRE];    // folded in-plane offset of each input slot (coefficient, fine field)
+    bool xneg[TL::NPRE];  // the fine field's halo sign of each input slot
     int tap[TL::NPRE];    // prolongation: LDS tap | x-neighbour bit << 16 | y-neighbour bit << 17
     int coff[TL::NPREC];  // folded in-plane offset of each coarse slot
     bool cneg[TL::NPREC];
@@ -88,6 +91,7 @@ __device__ __forceinline__ void make_fgeo(FGeo<TX, RY> &G, const StencilArgs &a,
         const int ui = i0 + px - 2, uj = j0 + py - 2;  // unfolded fine position
         int s = 1;
         G.off[q] = fold(ui, a.g.nx, a.g.bc[0], a.g.bc[1], s) + a.g.nx * fold(uj, a.g.ny, a.g.bc[2], a.g.bc[3], s);
+        G.xneg[q] = s < 0;
         const int I = ui >> 1, J = uj >> 1;  // floor
         const int t0 = (J - cj0) * TL::CX + (I - ci0);
         G.tap[q] = t0 | ((ui & 1) << 16) | ((uj & 1) << 17);
@@ -116,15 +120,17 @@ __device__ __forceinline__ void make_fgeo(FGeo<TX, RY> &G, const StencilArgs &a,
 }
 
 // Loads of one input plane zi, as loaded (signs and weights applied later):
-// coefficient and coarse correction of plane zi, first-sweep right-hand side
-// of plane zi - 1 and second-sweep right-hand side (and FP64 field) of zi - 2.
-template <typename T, typename KT, int TX, int RY, bool ADD>
+// coefficient, coarse correction (and fine field, XIN) of plane zi,
+// first-sweep right-hand side of plane zi - 1 and (ADD) the FP64 field of
+// zi - 2.  The second sweep takes its right-hand side from LDS, where the
+// first sweep left it one plane earlier.
+template <typename T, typename KT, int TX, int RY, bool ADD, bool XIN>
 struct FPre {
     using TL = FTile<TX, RY>;
     typename KStore<T, KT>::type k[HasK<KT>::value ? TL::NPRE : 1];
+    T xs[XIN ? TL::NPRE : 1];
     T c1[TL::NPREC], c2[TL::NPREC];
     T b1[TL::R1];
-    T b2[RY];
     double xo[ADD ? RY : 1];
 };
 
@@ -217,16 +223,20 @@ __device__ __forceinline__ T jacobi(const Run<T> &r, const PS<T> &p, T bb, T cw,
     }
 }
 
-template <typename T, typename KT, int OUT, int TX, int RY>
+// XIN: the first sweep's input is x + P e (x = a.yin, the right-hand side
+// b - bmean, output stored into a.yout, which must not alias a.yin).
+template <typename T, typename KT, int OUT, bool XIN, int TX, int RY>
 __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sweep2_kernel(const StencilArgs a)
 {
     if (a.done && *a.done) return;
     using TL = FTile<TX, RY>;
     constexpr bool HK = HasK<KT>::value;
     constexpr bool ADD = OUT == OUT_ADD64;
+    static_assert(!(XIN && ADD), "the x + P e input form stores its result");
     __shared__ T sx[3][TL::PN];            // input planes (P e), three in rotation
     __shared__ T sk[3][HK ? TL::PN : 1];   // coefficient planes
     __shared__ T sy[2][TL::QN];            // first-sweep output planes
+    __shared__ T sb[2][TL::QN];            // first-sweep right-hand sides (signed), same planes
     __shared__ T sc[TL::CN];               // coarse footprint of the plane being committed
 
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
@@ -257,7 +267,7 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
 
     FGeo<TX, RY> G;
     make_fgeo<TX, RY>(G, a, i0, j0);
-    FPre<T, KT, TX, RY, ADD> pA, pB;
+    FPre<T, KT, TX, RY, ADD, XIN> pA, pB;
     Run<T> r1[TL::R1], r2[RY];
     const bool act1 = (int)threadIdx.x < TL::NT1;
     const int s1q = min((int)threadIdx.x, TL::NT1 - 1) / TL::QX;   // strip of this thread
@@ -266,6 +276,8 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     const T *bp = (const T *)a.b;
     const T *ep = (const T *)a.ec;
     const KT *kp = (const KT *)a.k;
+    const T *xp = (const T *)a.yin;
+    const T bm = (XIN && a.bmean) ? (T)*a.bmean : (T)0;
 
     // Loads of plane zi in two parts.  The coefficient and the coarse values
     // are consumed by the LDS commit at the start of the step that uses them,
@@ -274,12 +286,16 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     // they are reloaded at the end of the step.  Either way no register still
     // holding a load in flight is copied at the loop's back edge (a copy would
     // wait for every outstanding load and undo the two-plane prefetch).
-    auto fetch_kc = [&](FPre<T, KT, TX, RY, ADD> &p, int zi) {
+    auto fetch_kc = [&](FPre<T, KT, TX, RY, ADD, XIN> &p, int zi) {
         int sk_ = 1;
         const size_t pz = plane * (size_t)fold(zi, nz, a.g.bc[4], a.g.bc[5], sk_);
         if constexpr (HK) {
 #pragma unroll
             for (int q = 0; q < TL::NPRE; ++q) p.k[q] = kp[pz + (size_t)G.off[q]];
+        }
+        if constexpr (XIN) {
+#pragma unroll
+            for (int q = 0; q < TL::NPRE; ++q) p.xs[q] = xp[pz + (size_t)G.off[q]];
         }
         const int K = zi >> 1;
         int s1 = 1, s2 = 1;
@@ -295,7 +311,7 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     // 1 (steady) and 2 (the first steps when the steady march follows): the
     // loads are issued unconditionally, mode 2 clamping the planes into the
     // chunk (values it loads for planes without an output are never used).
-    auto fetch_b = [&](auto mode_tag, FPre<T, KT, TX, RY, ADD> &p, int zi) {
+    auto fetch_b = [&](auto mode_tag, FPre<T, KT, TX, RY, ADD, XIN> &p, int zi) {
         constexpr int MODE = decltype(mode_tag)::value;
         if (MODE != 0 || (zi - 1 >= z0 - 1 && zi - 1 <= z1)) {
             const int zb = MODE == 2 ? min(max(zi - 1, z0 - 1), z1) : zi - 1;
@@ -304,28 +320,28 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
 #pragma unroll
             for (int q = 0; q < TL::R1; ++q) p.b1[q] = bp[pb + (size_t)G.boff[q]];
         }
-        if (MODE != 0 || (zi - 2 >= z0 && zi - 2 < z1)) {
-            const int zo = MODE == 2 ? min(max(zi - 2, z0), z1 - 1) : zi - 2;
-            const size_t pl = plane * (size_t)zo;
+        if constexpr (ADD) {
+            if (MODE != 0 || (zi - 2 >= z0 && zi - 2 < z1)) {
+                const int zo = MODE == 2 ? min(max(zi - 2, z0), z1 - 1) : zi - 2;
+                const size_t pl = plane * (size_t)zo;
 #pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                p.b2[r] = bp[pl + gb[r]];
-                if constexpr (ADD) p.xo[r] = a.x64[pl + gb[r]];
+                for (int r = 0; r < RY; ++r) p.xo[r] = a.x64[pl + gb[r]];
             }
         }
     };
-    auto fetch = [&](FPre<T, KT, TX, RY, ADD> &p, int zi) {
+    auto fetch = [&](FPre<T, KT, TX, RY, ADD, XIN> &p, int zi) {
         fetch_kc(p, zi);
         fetch_b(std::integral_constant<int, 0>{}, p, zi);
     };
 
-    // P e of plane zi into sx[buf] (coarse footprint staged in LDS first),
-    // the coefficient into sk[buf].
-    auto commit = [&](const FPre<T, KT, TX, RY, ADD> &p, int zi, int buf) {
+    // P e (plus x, XIN) of plane zi into sx[buf] (coarse footprint staged in
+    // LDS first), the coefficient into sk[buf].
+    auto commit = [&](const FPre<T, KT, TX, RY, ADD, XIN> &p, int zi, int buf) {
         const int K = zi >> 1;
-        int s1 = 1, s2 = 1;
+        int s1 = 1, s2 = 1, sz = 1;
         (void)fold(K, a.cnz, a.g.bc[4], a.g.bc[5], s1);
         (void)fold(K + ((zi & 1) ? 1 : -1), a.cnz, a.g.bc[4], a.g.bc[5], s2);
+        if constexpr (XIN) (void)fold(zi, nz, a.g.bc[4], a.g.bc[5], sz);
         const T w1 = (T)(0.75 * s1), w2 = (T)(0.25 * s2);
 #pragma unroll
         for (int q = 0; q < TL::NPREC; ++q)
@@ -343,7 +359,11 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
                 const int tdy = ((G.tap[q] >> 17) & 1) ? TL::CX : -TL::CX;
                 const T w3 = (T)0.75, wq = (T)0.25;
                 const int t1 = t0 + tdy;
-                sx[buf][idx] = w3 * (w3 * sc[t0] + wq * sc[t0 + tdx]) + wq * (w3 * sc[t1] + wq * sc[t1 + tdx]);
+                const T pe = w3 * (w3 * sc[t0] + wq * sc[t0 + tdx]) + wq * (w3 * sc[t1] + wq * sc[t1 + tdx]);
+                if constexpr (XIN)
+                    sx[buf][idx] = ((G.xneg[q] != (sz < 0)) ? -p.xs[q] : p.xs[q]) + pe;
+                else
+                    sx[buf][idx] = pe;
                 if constexpr (HK) sk[buf][idx] = kconv<T, KT>(p.k[q]);
             }
         }
@@ -356,7 +376,7 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     // path, so the compiler's wait counts let the loads of the next two planes
     // stay in flight; the general form serves the first and last steps of the
     // march and tiles that cross the grid's edge.
-    auto step = [&](auto mode_tag, FPre<T, KT, TX, RY, ADD> &p, int zi) {
+    auto step = [&](auto mode_tag, FPre<T, KT, TX, RY, ADD, XIN> &p, int zi) {
         constexpr int MODE = decltype(mode_tag)::value;
         constexpr bool ST = MODE == 1;  // steady: every condition below holds
         constexpr bool FX = MODE != 0;  // fixed loads
@@ -385,7 +405,9 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
                 const Row<T> w2 = wrow(q + 2);
                 const PS<T> ps = col_sums<T, HK>(w0, w1, w2);
                 const int qy = s1q * TL::R1 + q;
-                const T bq = (G.bneg[q] != bzneg) ? -p.b1[q] : p.b1[q];
+                const T bv = XIN ? p.b1[q] - bm : p.b1[q];
+                const T bq = (G.bneg[q] != bzneg) ? -bv : bv;
+                if (qy < TL::QY) sb[yb][qy * TL::QX + s1x] = bq;
                 if ((ST || zi >= z0) && qy < TL::QY)
                     sy[yb][qy * TL::QX + s1x] = jacobi<T, HK>(r1[q], ps, bq, cw, om_w0, om, icv);
                 absorb<T, HK>(r1[q], ps, zi == z0 - 2);
@@ -412,7 +434,9 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
                 w0 = w1;
                 w1 = w2;
                 if (ST || (MODE == 0 && zi >= z0 + 2)) {  // mode 2 steps have no output plane
-                    const T y = jacobi<T, HK>(r2[r], ps, p.b2[r], cw, om_w0, om, icv);
+                    // right-hand side of output plane zi - 2, left by the previous step's first sweep
+                    const T bo = sb[yb ^ 1][(RY * ly + r + 1) * TL::QX + (lx + 1)];
+                    const T y = jacobi<T, HK>(r2[r], ps, bo, cw, om_w0, om, icv);
                     const size_t g = gb[r] + plane * (size_t)(zi - 2);
                     if (ST || valid[r]) {  // the steady march runs only on tiles inside the grid
                         if constexpr (ADD)
@@ -458,16 +482,16 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     }
 }
 
-template <typename T, typename KT, int OUT>
+template <typename T, typename KT, int OUT, bool XIN = false>
 hipError_t go2(const StencilArgs &a, hipStream_t s)
 {
     const dim3 grid(a.t.blocks()), block(FT);
     switch (a.t.tx * 10 + a.t.ry) {
-    case 642: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, 64, 2>), grid, block, 0, s, a); break;
-    case 641: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, 64, 1>), grid, block, 0, s, a); break;
-    case 322: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, 32, 2>), grid, block, 0, s, a); break;
-    case 321: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, 32, 1>), grid, block, 0, s, a); break;
-    case 162: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, 16, 2>), grid, block, 0, s, a); break;
+    case 642: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, XIN, 64, 2>), grid, block, 0, s, a); break;
+    case 641: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, XIN, 64, 1>), grid, block, 0, s, a); break;
+    case 322: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, XIN, 32, 2>), grid, block, 0, s, a); break;
+    case 321: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, XIN, 32, 1>), grid, block, 0, s, a); break;
+    case 162: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, XIN, 16, 2>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -477,10 +501,19 @@ hipError_t go2(const StencilArgs &a, hipStream_t s)
 
 bool sweep2_supports(int tx, int ry) { return (tx == 64 && ry <= 2) || (tx == 32 && ry <= 2) || (tx == 16 && ry == 2); }
 
-hipError_t launch_sweep2(int T_is_f64, int kt, int out_mode, const StencilArgs &a, hipStream_t s)
+hipError_t launch_sweep2(int T_is_f64, int kt, int in_mode, int out_mode, const StencilArgs &a, hipStream_t s)
 {
     if (a.t.blocks() <= 0 || (a.t.zc & 1)) return hipErrorInvalidValue;
-    if (a.bmean || !a.ec || !a.b) return hipErrorInvalidValue;
+    if (!a.ec || !a.b) return hipErrorInvalidValue;
+    if (in_mode == IN_PROLONG_ADD) {
+        // FP64 only; the pass reads x on a two-cell ring that other
+        // workgroups' outputs cover, so the output must be another buffer
+        if (!T_is_f64 || out_mode != OUT_STORE || !a.yin || !a.yout || a.yin == a.yout) return hipErrorInvalidValue;
+        if (kt == KT_NONE) return go2<double, NoK, OUT_STORE, true>(a, s);
+        if (kt == KT_F64) return go2<double, double, OUT_STORE, true>(a, s);
+        return hipErrorInvalidValue;
+    }
+    if (in_mode != IN_PROLONG || a.bmean) return hipErrorInvalidValue;
     if (T_is_f64) {
         if (out_mode == OUT_STORE) {
             if (kt == KT_NONE) return go2<double, NoK, OUT_STORE>(a, s);

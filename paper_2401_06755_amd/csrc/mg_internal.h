@@ -161,10 +161,12 @@ hipError_t launch_cast_f32(const double *src, float *dst, size_t n, const int *d
 hipError_t launch_zero(double *x, size_t n, const int *done, hipStream_t s);
 
 // ---- both post-smoothing sweeps in one pass (mg_fused.hip) ----
-// Input P e (a.ec, IN_PROLONG semantics), right-hand side a.b (no bmean),
+// in_mode IN_PROLONG: input P e (a.ec), right-hand side a.b (no bmean),
 // coefficient a.k; out_mode OUT_STORE (a.yout) or OUT_ADD64 (a.x64 += e).
+// in_mode IN_PROLONG_ADD (FP64, OUT_STORE only): input a.yin + P e,
+// right-hand side a.b - a.bmean, result in a.yout != a.yin.
 bool sweep2_supports(int tx, int ry);
-hipError_t launch_sweep2(int T_is_f64, int kt, int out_mode, const StencilArgs &a, hipStream_t s);
+hipError_t launch_sweep2(int T_is_f64, int kt, int in_mode, int out_mode, const StencilArgs &a, hipStream_t s);
 
 // ---- the same two sweeps as independent 8^3 blocks (mg_block.hip) ----
 // Same arguments and result as launch_sweep2 (a.t is not used); one

@@ -364,12 +364,14 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
     // plane z + 3 (two planes stay in flight), then finish plane z and load
     // the output values of plane z + 2 into the registers it just read.
     // The steady form (ST; PAR = z & 1 known) runs on tiles inside the grid
-    // with both residual outputs present: it issues the same loads and stores
-    // on every path, so the compiler's wait counts keep the next planes' loads
-    // in flight instead of waiting for every outstanding load.
+    // with the restricted residual output present (mode 1: and the full
+    // residual, mode 2: without it): it issues the same loads and stores on
+    // every path, so the compiler's wait counts keep the next planes' loads in
+    // flight instead of waiting for every outstanding load.
     int buf = 0;
     auto step = [&](auto st_tag, auto par_tag, Prefetch<T, KT, TX, RY, PRO, ADD> &p, int z) {
-        constexpr bool ST = decltype(st_tag)::value;
+        constexpr int MODE = decltype(st_tag)::value;
+        constexpr bool ST = MODE != 0;
         constexpr int PAR = decltype(par_tag)::value;
         commit<T, KT, IN, TX, RY, ADD>(p, G, sx[buf], sk[buf], sc);
         if (ST || z + 3 <= z1) fetch_in<T, KT, IN, TX, RY, ADD>(p, G, a, z + 3);
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
             if constexpr (OUT == OUT_RESID) {
                 double rv = 0.0;
                 if (ST || valid[r]) rv = ((double)p.bo[r] - bm) - (double)Ay;
-                if (ST || (a.r && valid[r])) ((OT *)a.r)[g] = (OT)rv;
+                if (MODE == 1 || (MODE == 0 && a.r && valid[r])) ((OT *)a.r)[g] = (OT)rv;
                 nacc += a.dot_x ? (double)y0 * rv : rv * rv;
                 rrow[r] = rv;
             } else if (ST || valid[r]) {
@@ -456,19 +458,29 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
     plane_sums<T, HK, TX, RY>(sx[1], sk[1], lx, ly, ps);
     absorb(false);
 
-    const std::false_type gen{};
-    const std::true_type steady{};
+    const std::integral_constant<int, 0> gen{};
+    const std::integral_constant<int, 1> steady{};
+    const std::integral_constant<int, 2> steady_rc{};
     const std::integral_constant<int, -1> anypar{};
     const std::integral_constant<int, 0> even{};
     const std::integral_constant<int, 1> odd{};
     // the steady march: tiles inside the grid, chunks starting on an even plane
-    // (so the A steps are the even planes), both residual outputs present
-    const bool inside = i0 + TX <= nx && j0 + TL::TY <= ny && !(z0 & 1) &&
-                        (OUT != OUT_RESID || (a.r != nullptr && a.rc != nullptr));
+    // (so the A steps are the even planes), the restricted residual output
+    // present (the full residual is optional: its own form of the march)
+    const bool inside = i0 + TX <= nx && j0 + TL::TY <= ny && !(z0 & 1) && (OUT != OUT_RESID || a.rc != nullptr);
     int z = z0;
-    for (; inside && z + 4 <= z1; z += 2) {
-        step(steady, even, pA, z);
-        step(steady, odd, pB, z + 1);
+    if (OUT != OUT_RESID || a.r != nullptr) {
+        for (; inside && z + 4 <= z1; z += 2) {
+            step(steady, even, pA, z);
+            step(steady, odd, pB, z + 1);
+        }
+    } else {
+        if constexpr (OUT == OUT_RESID) {
+            for (; inside && z + 4 <= z1; z += 2) {
+                step(steady_rc, even, pA, z);
+                step(steady_rc, odd, pB, z + 1);
+            }
+        }
     }
     for (; z < z1; z += 2) {
         step(gen, anypar, pA, z);

@@ -29,23 +29,38 @@ def test_more_than_one_gpu_is_refused():
 
 def test_finest_level_bytes_per_cell():
     f = bench.BYTES_PER_CELL
-    assert f["fp64"]["resid"] == 8 + 8 + 8 + 8 + 1
+    # FP64 direct form: the residual kernel reads x, b, k and writes R r only
+    assert f["fp64"]["resid"] == 8 + 8 + 8 + 1
     assert f["fp64"]["sweeps"] == 1 + 8 + 8 + 8 + 8
     assert f["fp64c"]["resid"] == f["fp64"]["resid"] - 8  # no coefficient
     assert f["mixed"]["sweeps"] - f["fp16"]["sweeps"] == 2  # FP32 vs FP16 coefficient
     for mode in f:
         assert set(f[mode]) == set(bench.KCLASS)
+    # the 8^3 block form writes and reads the full residual r
+    g = bench.BYTES_PER_CELL_BLOCK
+    for mode in g:
+        assert g[mode]["resid"] == f[mode]["resid"] + 8
+        assert g[mode]["sweeps"] == f[mode]["sweeps"]
+
+
+def test_fine_bytes_follows_the_finest_sweep_form():
+    march = {"tiles": [[[64, 2, 16], [32, 2, 16], [64, 2, 16]]]}
+    block = {"tiles": [[[64, 2, 16], [8, 8, 8], [64, 2, 16]]]}
+    assert bench.fine_bytes("fp64", march) is bench.BYTES_PER_CELL["fp64"]
+    assert bench.fine_bytes("fp64", {"tiles": None}) is bench.BYTES_PER_CELL["fp64"]
+    assert bench.fine_bytes("fp64", block) is bench.BYTES_PER_CELL_BLOCK["fp64"]
+    assert bench.fine_bytes("mixed", block) is bench.BYTES_PER_CELL["mixed"]
 
 
 def test_cycle_bytes_geometric_in_levels():
     levels = [(256 >> l,) * 3 for l in range(7)]
     n0 = 256 ** 3
     for mode in ("fp64", "mixed", "fp16", "fp64c"):
-        per_cell = bench.cycle_model_bytes(levels, mode) / n0
+        per_cell = bench.cycle_model_bytes({"levels": levels}, mode) / n0
         fine = bench.BYTES_PER_CELL[mode]["resid"] + bench.BYTES_PER_CELL[mode]["sweeps"]
         assert fine < per_cell < fine * 8.0 / 7.0
     # one level: the finest kernels only
-    assert bench.cycle_model_bytes(levels[:1], "fp64") == n0 * 66
+    assert bench.cycle_model_bytes({"levels": levels[:1]}, "fp64") == n0 * 58
 
 
 def test_roofline_fields():
