@@ -239,12 +239,15 @@ def percentile(v, p):
     return float(np.percentile(np.asarray(v), p)) if len(v) else None
 
 
-def serving_bench(nn4mg, torch, n_requests, budget_gib, slots, seed_base=4000):
+def serving_bench(nn4mg, torch, n_requests, budget_gib, slots, bound_budget_gib=1.0, seed_base=4000):
     """Served stream: n_requests variable-coefficient solves (cube edges drawn
     from {32, 48, 64, 96, 128}, random dense sphere, Neumann walls), FP32
-    smoothing + FP64 refinement to rtol 1e-8.  First closed loop (everything
-    submitted at once) for the capacity, then open loop with Poisson arrivals
-    at 0.7 x that capacity; latency = completion - arrival."""
+    smoothing + FP64 refinement to rtol 1e-8, up to `slots` running at once
+    (requests of one size run as copies of one batched group).  First closed
+    loop (everything submitted at once) for the capacity, then open loop with
+    Poisson arrivals at 0.7 x that capacity (latency = completion - arrival),
+    then the closed loop again under an HBM budget small enough to bind
+    (groups smaller, idle ones evicted)."""
     import numpy as np
 
     from paper_2401_06755_amd import inputs
@@ -262,8 +265,8 @@ def serving_bench(nn4mg, torch, n_requests, budget_gib, slots, seed_base=4000):
     log(f"  generated {n_requests} requests ({cells / n_requests:.0f} cells mean) in {time.perf_counter() - t0:.1f} s")
     budget = int(budget_gib * 2 ** 30)
 
-    def run(arrivals):
-        srv = nn4mg.Server(budget, slots)
+    def run(arrivals, bud):
+        srv = nn4mg.Server(bud, slots)
         xs = [torch.zeros_like(b) for _, _, b in reqs]
         torch.cuda.synchronize()
         results = []
@@ -292,12 +295,13 @@ def serving_bench(nn4mg, torch, n_requests, budget_gib, slots, seed_base=4000):
         cyc = [r.info.cycles for r in results]
         return dict(wall=wall, lat=lat, ok=ok, cycles=cyc, peak=st["peak_bytes"])
 
-    closed = run([0.0] * len(reqs))
+    closed = run([0.0] * len(reqs), budget)
     capacity = len(reqs) / closed["wall"]
     rate = 0.7 * capacity
     rng = np.random.default_rng(seed_base)
     arrivals = list(np.cumsum(rng.exponential(1.0 / rate, size=len(reqs))))
-    opened = run(arrivals)
+    opened = run(arrivals, budget)
+    bound = run([0.0] * len(reqs), int(bound_budget_gib * 2 ** 30))
     return {"requests": len(reqs), "mean_cells": round(cells / len(reqs)),
             "precision": "f32 smoothing + f64 residual/coarsest/refinement", "rtol": 1e-8,
             "hbm_budget_GiB": budget_gib, "slots": slots,
@@ -310,6 +314,10 @@ def serving_bench(nn4mg, torch, n_requests, budget_gib, slots, seed_base=4000):
                           "p50_ms": round(percentile(opened["lat"], 50), 2),
                           "p99_ms": round(percentile(opened["lat"], 99), 2), "converged": opened["ok"],
                           "peak_GiB": round(opened["peak"] / 2 ** 30, 3)},
+            "bound_budget": {"hbm_budget_GiB": bound_budget_gib,
+                             "solves_per_s": round(len(reqs) / bound["wall"], 2),
+                             "p99_ms": round(percentile(bound["lat"], 99), 2), "converged": bound["ok"],
+                             "peak_GiB": round(bound["peak"] / 2 ** 30, 3)},
             "mean_cycles": round(float(np.mean(closed["cycles"])), 1),
             "gcell_updates_per_s_closed": round(sum(c.nx * c.ny * c.nz * cy for (c, _, _), cy in
                                                     zip(reqs, closed["cycles"])) / closed["wall"] / 1e9, 3)}
@@ -600,7 +608,8 @@ def main():
     ap.add_argument("--no-fcg", action="store_true", help="skip the flexible-CG outer iteration legs")
     ap.add_argument("--serve-requests", type=int, default=512, help="served-stream requests (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-bound-budget-gib", type=float, default=1.0)
     ap.add_argument("--step-n", type=int, default=128, help="time-step grid edge (0: skip)")
     ap.add_argument("--step-steps", type=int, default=3)
     ap.add_argument("--mass-steps", type=int, default=1000,
@@ -704,7 +713,8 @@ def main():
         out["bubble"] = bubble_bench(nn4mg, torch, inputs, min(args.steps, 3), args.rtol)
     if args.serve_requests > 0:
         log(f"served stream: {args.serve_requests} requests")
-        out["serving"] = serving_bench(nn4mg, torch, args.serve_requests, args.serve_budget_gib, args.serve_slots)
+        out["serving"] = serving_bench(nn4mg, torch, args.serve_requests, args.serve_budget_gib, args.serve_slots,
+                                       args.serve_bound_budget_gib)
     if args.step_n > 0:
         log(f"time step: {args.step_n}^3 collapsing column")
         out["step"] = step_bench(nn4mg, torch, args.step_n, args.step_steps)

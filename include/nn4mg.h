@@ -216,23 +216,31 @@ int nn4mg_autotune(nn4mg_t h, const double *b_dev, double *x_dev, int *tiles_out
  * Serves the pressure solves of a time-stepping or ensemble workload, each with
  * its own grid size, coefficient and right-hand side (the paper's solver runs
  * one pressure solve per stage and per time step, Sec. 2.4).  A worker thread
- * admits queued requests in arrival order as soon as a slot and enough device
- * memory are free (the budget counts every resident hierarchy), keeps idle
- * hierarchies resident for reuse by later requests of the same configuration,
- * runs each admitted request on its own stream so that the cycles of all
- * active requests overlap on the device, launches each cycle as a captured
- * hipGraph, and checks every request's stopping rule asynchronously.  Results
- * do not depend on which other requests run: every kernel reads only its own
- * request's data, and reductions have a fixed order. */
+ * admits queued requests while fewer than max_slots run and the device memory
+ * fits (the budget counts every resident hierarchy).  Requests of one
+ * configuration are batched: they run as copies of one group (up to 16
+ * identical hierarchies at a fixed stride in one allocation), and each kernel
+ * of a cycle is one launch over the group's running copies, from a captured
+ * hipGraph; a request joins a free copy while the group runs (its coefficient
+ * and vectors are set up on a side stream) and leaves when its own stopping
+ * rule has fired, checked on the device and read back asynchronously.  Groups
+ * of different configurations run on their own streams and overlap; idle
+ * groups stay resident for later requests and are evicted, least recently
+ * used first, when memory is short.  Configurations with no batched form
+ * (flexible CG outer iteration, other than two post-sweeps, no one-workgroup
+ * coarse end) run one request per stream.  Results do not depend on which
+ * other requests run or on the group's size: every workgroup reads only its
+ * own request's data, launch shapes are fixed per configuration, and
+ * reductions have a fixed order. */
 typedef struct nn4mg_server *nn4mg_srv_t;
 
 typedef struct {
     unsigned long long tag;   /* the caller's tag */
     nn4mg_info info;          /* as from nn4mg_solve; info.status carries the request's status */
     double t_submit_ms;       /* host clock, ms since the server was created */
-    double t_start_ms;        /* admitted to a slot */
+    double t_start_ms;        /* admitted (to a group copy or a slot) */
     double t_done_ms;         /* x written back and the request completed */
-    size_t bytes;             /* device bytes of the request's hierarchy and work buffers */
+    size_t bytes;             /* device bytes of the request's hierarchy (its share of a group) and work buffers */
 } nn4mg_result;
 
 /* hbm_budget_bytes: device memory the server may hold for hierarchies and

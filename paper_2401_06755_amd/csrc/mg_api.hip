@@ -58,7 +58,7 @@ struct Level {
 // least (ties: the wider tile, for longer coalesced rows), and the longest
 // z-chunk that still gives >= 1024 workgroups.  (Used for the single-sweep
 // classes; the shapes below are what the autotuner picks on large levels.)
-TileShape default_tiles(int nx, int ny, int nz)
+TileShape default_tiles(int nx, int ny, int nz, int zmul = 1)
 {
     int best_tx = 64;
     double best_area = 1e300;
@@ -71,7 +71,7 @@ TileShape default_tiles(int nx, int ny, int nz)
         }
     }
     int zc = kDefaultZc;
-    while (zc > 2 && (double)nx * ny * nz / (512.0 * zc) < 1024.0) zc /= 2;
+    while (zc > 2 && (double)nx * ny * nz * zmul / (512.0 * zc) < 1024.0) zc /= 2;
     return make_tiles(nx, ny, nz, zc, best_tx);
 }
 
@@ -88,16 +88,18 @@ int zchunk_for(int nx, int ny, int nz, int tx, int ty)
 // Default shape per kernel class: the residual in 64-wide tiles of 2 rows per
 // thread; with the two-sweep pass (nu_post == 2) the first-sweep class in
 // 32-wide tiles, 2 rows per thread in FP64 and 1 with FP32 smoothing (the FP64
-// run state of 64-wide tiles leaves one wave per SIMD).
-TileShape default_tiles_for(int nx, int ny, int nz, int kclass, bool mixed, bool fused)
+// run state of 64-wide tiles leaves one wave per SIMD).  zmul: the launches
+// cover that many copies of the level (a batched group), so the z-chunk is
+// chosen for zmul times the workgroups.
+TileShape default_tiles_for(int nx, int ny, int nz, int kclass, bool mixed, bool fused, int zmul = 1)
 {
     if (kclass == NN4MG_KCLASS_FINE_RESID && nx >= 64)
-        return make_tiles(nx, ny, nz, zchunk_for(nx, ny, nz, 64, 8), 64, 2);
+        return make_tiles(nx, ny, nz, zchunk_for(nx, ny, nz * zmul, 64, 8), 64, 2);
     if (kclass == NN4MG_KCLASS_FINE_SWEEP_PROLONG && fused && nx >= 32) {
         const int ry = mixed ? 1 : 2;
-        return make_tiles(nx, ny, nz, zchunk_for(nx, ny, nz, 32, 8 * ry), 32, ry);
+        return make_tiles(nx, ny, nz, zchunk_for(nx, ny, nz * zmul, 32, 8 * ry), 32, ry);
     }
-    return default_tiles(nx, ny, nz);
+    return default_tiles(nx, ny, nz, zmul);
 }
 
 int count_levels(int nx, int ny, int nz, int min_coarse)
@@ -271,6 +273,26 @@ struct nn4mg_hier {
     double *fcg = nullptr;   // FCG vectors r, z, p, t = -A p at level 0, FP64
     double *fcg_part = nullptr;  // FCG dot-product partials
     size_t bytes = 0;
+    // Device fields are carved from one arena: dalloc records each field and
+    // its offset, place_fields makes one allocation of ncopy identical copies
+    // (bstride bytes apart) and points every field into copy 0.  A batched
+    // hierarchy (ncopy > 1) launches each cycle kernel once over all copies;
+    // a view (view_of != nullptr) is copy c of one, with its own pointers and
+    // single launches, owning nothing.
+    struct Field {
+        void **ptr;
+        size_t off;
+    };
+    std::vector<Field> fields;
+    size_t arena_used = 0;
+    void *arena = nullptr;
+    int ncopy = 1;
+    long long bstride = 0;
+    bool group = false;  // the server's batched form (per-copy fields, launched through batch_enqueue_cycles)
+    int cap = 1;         // group: copies allocated (ncopy is the count a launch covers)
+    std::vector<hipGraphExec_t> bgraph;  // group: captured cycle over copies 0 .. k - 1, by k
+    const nn4mg_hier *view_of = nullptr;
+    double *bw = nullptr, *xw = nullptr;  // batched: per-copy right-hand side and iterate
     std::vector<void *> allocs;
     // captured hipGraphs of one stationary iteration (body + residual + stopping
     // rule), from x into lv[0].t and back (one graph unless the finest sweeps
@@ -295,25 +317,56 @@ struct nn4mg_hier {
 
 namespace {
 
+constexpr size_t kArenaAlign = 256;
+// Running copies a group's default launch shapes are chosen for.
+constexpr int kGroupTileCopies = 4;
+
+size_t arena_round(size_t v) { return (v + kArenaAlign - 1) & ~(kArenaAlign - 1); }
+
+// Reserve a field of `bytes` in the arena; *p is set by place_fields.
+int dalloc_bytes(nn4mg_hier *H, void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 1;
+    const size_t off = arena_round(H->arena_used);
+    H->arena_used = off + bytes;
+    H->fields.push_back({p, off});
+    *p = nullptr;
+    return NN4MG_OK;
+}
+
 template <typename P>
 int dalloc(nn4mg_hier *H, P **p, size_t count)
 {
+    static_assert(sizeof(P *) == sizeof(void *), "pointer field");
+    return dalloc_bytes(H, reinterpret_cast<void **>(p), (count ? count : 1) * sizeof(P));
+}
+
+// One allocation for every reserved field, ncopy times.
+int place_fields(nn4mg_hier *H)
+{
+    const size_t A = arena_round(H->arena_used);
     void *q = nullptr;
-    if (count == 0) count = 1;
-    if (hipMalloc(&q, count * sizeof(P)) != hipSuccess) {
+    if (hipMalloc(&q, A * (size_t)H->ncopy) != hipSuccess) {
         (void)hipGetLastError();
         return fail(NN4MG_ENOMEM, "hipMalloc failed");
     }
+    H->arena = q;
     H->allocs.push_back(q);
-    H->bytes += count * sizeof(P);
-    *p = (P *)q;
+    H->bstride = (long long)A;
+    H->bytes = A * (size_t)H->ncopy;
+    for (const nn4mg_hier::Field &f : H->fields) *f.ptr = (char *)q + f.off;
     return NN4MG_OK;
 }
 
 void release(nn4mg_hier *H)
 {
+    if (H->view_of) return;  // a view owns nothing
     if (H->stream) (void)hipStreamSynchronize(H->stream);
     for (hipGraphExec_t &g : H->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    for (hipGraphExec_t &g : H->bgraph) {
         if (g) (void)hipGraphExecDestroy(g);
         g = nullptr;
     }
@@ -352,6 +405,7 @@ size_t bytes_for(const nn4mg_config *c)
     }
     const size_t nc = (size_t)(c->nx >> (L - 1)) * (c->ny >> (L - 1)) * (c->nz >> (L - 1));
     b += 8 * nc * nc + sizeof(SolveState) + 8 * maxblk + 64 + 4;
+    b += kArenaAlign * (size_t)(5 * L + 12);  // alignment of each field in the arena
     if (c->outer == NN4MG_OUTER_FCG) b += 4 * 8 * (size_t)c->nx * c->ny * c->nz + 8 * (size_t)fcg_partials_needed();
     return b;
 }
@@ -388,7 +442,9 @@ int choose_tail(const nn4mg_hier *H)
     return H->lv[H->L - 1].n <= kTailMaxCells ? H->L - 1 : 0;
 }
 
-int rebuild_coefficients(nn4mg_hier *H)
+// The coarse levels' coefficients from lv[0].k (nodal): coarsening, the
+// smoothing copies, the tail's padded copy.
+int enqueue_coef_kernels(nn4mg_hier *H)
 {
     hipStream_t s = H->stream;
     const nn4mg_config &c = H->cfg;
@@ -411,6 +467,16 @@ int rebuild_coefficients(nn4mg_hier *H)
             }
         }
     }
+    return NN4MG_OK;
+}
+
+int rebuild_coefficients(nn4mg_hier *H)
+{
+    hipStream_t s = H->stream;
+    const nn4mg_config &c = H->cfg;
+    const bool nodal = c.coef_mode == NN4MG_COEF_NODAL;
+    int rc0 = enqueue_coef_kernels(H);
+    if (rc0) return rc0;
     const Level &C = H->lv[H->L - 1];
     std::vector<double> hk;
     if (nodal) {
@@ -493,6 +559,8 @@ StencilArgs base_args(const nn4mg_hier *H, int l, int kclass)
     a.t = V.tiles[kclass];
     a.h = V.h;
     a.omega = H->cfg.omega;
+    a.ncopy = H->ncopy;
+    a.bstride = H->bstride;
     if (l + 1 < H->L) {
         a.cnx = H->lv[l + 1].nx;
         a.cny = H->lv[l + 1].ny;
@@ -575,6 +643,9 @@ bool level_fusable(const nn4mg_hier *H, int l)
 // successive cycles alternate between x and lv[0].t.
 bool direct_fine(const nn4mg_hier *H)
 {
+    // batched hierarchies and their views keep the correction form: the copies
+    // of a batch run from different cycle counts, so no common buffer order
+    if (H->group || H->view_of) return false;
     return !H->mixed && H->L > 1 && level_fusable(H, 0) && !H->lv[0].block2;
 }
 
@@ -723,7 +794,8 @@ int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, doub
             const bool stop_here = stop_np > 0 && l == 1;
             HIP_TRY(launch_restrict_chain(f64 ? 1 : 0, f64 ? (void *)V.b : (void *)V.b32, bof(l + 1), bof(l + 2),
                                           bof(l + 3), V.nx, V.ny, V.nz, depth, done, s, stop_here ? H->st : nullptr,
-                                          stop_here ? H->partials : nullptr, stop_here ? stop_np : 0));
+                                          stop_here ? H->partials : nullptr, stop_here ? stop_np : 0, H->ncopy,
+                                          H->bstride));
         }
         TailArgs ta;
         std::memset(&ta, 0, sizeof(ta));
@@ -748,6 +820,8 @@ int enqueue_cycle_body(nn4mg_hier *H, const double *b, const double *bmean, doub
         ta.omega = H->cfg.omega;
         ta.nu = H->cfg.nu_post;
         ta.done = done;
+        ta.ncopy = H->ncopy;
+        ta.bstride = H->bstride;
         HIP_TRY(launch_tail(f64 ? 1 : 0, f64 ? H->kt64 : H->kts, ta, s));
         for (int l = T - 1; l >= 1; --l)
             if ((rc = enqueue_coarse_sweeps(H, l, done))) return rc;
@@ -878,11 +952,29 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
     *out = nullptr;
     int rc = validate(cfg);
     if (rc) return rc;
+    if (cfg->coef_mode == NN4MG_COEF_NODAL && !k_dev) return fail(NN4MG_EINVAL, "nodal coefficient requires k");
+    return nn4mg::setup_hier(cfg, k_dev, (hipStream_t)hip_stream, 1, out);
+}
+
+}  // extern "C"
+
+// A hierarchy of ncopy identical copies (validated cfg).  With one copy the
+// coefficient is set up from k_dev; a batched hierarchy gets its per-copy
+// right-hand side and iterate fields, and each copy's coefficient is set up
+// through its view.
+int nn4mg::setup_hier(const nn4mg_config *cfg, const double *k_dev, hipStream_t stream, int ncopy, nn4mg_hier **out,
+                      bool group)
+{
+    *out = nullptr;
+    if (ncopy < 1 || (ncopy > 1 && !group)) return fail(NN4MG_EINVAL, "several copies are a batched group");
     const bool nodal = cfg->coef_mode == NN4MG_COEF_NODAL;
-    if (nodal && !k_dev) return fail(NN4MG_EINVAL, "nodal coefficient requires k");
     nn4mg_hier *H = new nn4mg_hier();
     H->cfg = *cfg;
-    H->stream = (hipStream_t)hip_stream;
+    H->stream = stream;
+    H->ncopy = ncopy;
+    H->cap = ncopy;
+    H->group = group;
+    if (group) H->bgraph.assign((size_t)ncopy + 1, nullptr);
     H->L = count_levels(cfg->nx, cfg->ny, cfg->nz, cfg->min_coarse);
     H->mixed = cfg->precision != NN4MG_PREC_FP64;
     H->singular = 1;
@@ -906,8 +998,12 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
         V.nz = cfg->nz >> l;
         V.h = cfg->h * (double)(1 << l);
         V.n = (size_t)V.nx * V.ny * V.nz;
+        // a group's launches usually cover several running copies (the same
+        // shapes whatever the group's size, so a request's result does not
+        // depend on the group it runs in)
+        const int zmul = group ? kGroupTileCopies : 1;
         for (int c = 0; c < 3; ++c)
-            V.tiles[c] = default_tiles_for(V.nx, V.ny, V.nz, c, H->mixed, cfg->nu_post == 2 && H->L >= 2);
+            V.tiles[c] = default_tiles_for(V.nx, V.ny, V.nz, c, H->mixed, cfg->nu_post == 2 && H->L >= 2, zmul);
         if (V.tiles[0].blocks() > maxblk) maxblk = V.tiles[0].blocks();
         if (nodal) TRY(dalloc(H, &V.k, V.n));
         const bool single = (H->L == 1);
@@ -922,17 +1018,7 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
             TRY(dalloc(H, &V.t32, V.n));
             if (l > 0 || single) TRY(dalloc(H, &V.e32, V.n));
             if (l == 0 && cfg->nu_post > 2) TRY(dalloc(H, &V.t32b, V.n));
-            if (nodal) {
-                if (H->kts == KT_F16) {
-                    __half *p;
-                    TRY(dalloc(H, &p, V.n));
-                    V.ks = p;
-                } else {
-                    float *p;
-                    TRY(dalloc(H, &p, V.n));
-                    V.ks = p;
-                }
-            }
+            if (nodal) TRY(dalloc_bytes(H, &V.ks, V.n * (H->kts == KT_F16 ? sizeof(__half) : sizeof(float))));
         }
     }
     for (int l = 0; l < H->L; ++l)
@@ -944,6 +1030,11 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
     H->nc = (int)C.n;
     H->tail = choose_tail(H);
     H->fused = cfg->nu_post == 2 && H->L >= 2;
+    if (group && (H->L < 2 || H->tail == 0 || !H->fused || cfg->outer != NN4MG_OUTER_STATIONARY)) {
+        nn4mg_destroy(H);
+        return fail(NN4MG_EINVAL, "no batched form: needs the stationary cycle, two post-sweeps and a one-workgroup "
+                                  "coarse end");
+    }
     // coarse levels of up to 64^3 cells: the block form of the two sweeps is
     // shorter than a march over z (the autotuner re-decides per level)
     for (int l = 1; l < H->L; ++l) H->lv[l].block2 = level_fusable(H, l) && H->lv[l].n <= kBlock2MaxCells;
@@ -951,15 +1042,7 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
         size_t cells = 0;
         for (int l = H->tail; l < H->L; ++l)
             cells += (size_t)(H->lv[l].nx + 2) * (H->lv[l].ny + 2) * (H->lv[l].nz + 2);
-        if (H->mixed) {
-            float *p;
-            TRY(dalloc(H, &p, cells));
-            H->ktail = p;
-        } else {
-            double *p;
-            TRY(dalloc(H, &p, cells));
-            H->ktail = p;
-        }
+        TRY(dalloc_bytes(H, &H->ktail, cells * (H->mixed ? sizeof(float) : sizeof(double))));
     }
     TRY(dalloc(H, &H->ainv, (size_t)H->nc * H->nc));
     TRY(dalloc(H, &H->st, 1));
@@ -971,19 +1054,28 @@ int nn4mg_setup(const nn4mg_config *cfg, const double *k_dev, void *hip_stream, 
         TRY(dalloc(H, &H->fcg, 4 * H->lv[0].n));
         TRY(dalloc(H, &H->fcg_part, (size_t)fcg_partials_needed()));
     }
-    if (hipHostMalloc((void **)&H->st_host, sizeof(SolveState), hipHostMallocDefault) != hipSuccess) {
+    if (group) {
+        TRY(dalloc(H, &H->bw, H->lv[0].n));
+        TRY(dalloc(H, &H->xw, H->lv[0].n));
+    }
+    TRY(place_fields(H));
+    if (hipHostMalloc((void **)&H->st_host, sizeof(SolveState) * (size_t)ncopy, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         nn4mg_destroy(H);
         return fail(NN4MG_ENOMEM, "pinned host allocation failed");
     }
-    if (nodal)
-        TRY(load_k(H, k_dev));
-    else
-        TRY(rebuild_coefficients(H));
+    if (!group) {
+        if (nodal)
+            TRY(load_k(H, k_dev));
+        else
+            TRY(rebuild_coefficients(H));
+    }
 #undef TRY
     *out = H;
     return NN4MG_OK;
 }
+
+extern "C" {
 
 int nn4mg_update_coef(nn4mg_t H, const double *k_dev)
 {
@@ -1161,7 +1253,8 @@ int enqueue_stationary_iteration(nn4mg_hier *H, const double *b, double *x, int 
     if ((rc = enqueue_resid_for_cycle(H, b, dst, bmean, true, done))) return rc;
     // with the rule in the next cycle's chain, the residual is judged there
     // (or by the stand-alone launch that ends each batch)
-    if (!stop_in_chain(H)) HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), H->stream));
+    if (!stop_in_chain(H))
+        HIP_TRY(launch_finish_norm(H->st, H->partials, resid_blocks(H), H->stream, 0, H->ncopy, H->bstride));
     return NN4MG_OK;
 }
 
@@ -1258,13 +1351,15 @@ int iteration_parity(const nn4mg_hier *H, int index)
     return (H->cfg.outer != NN4MG_OUTER_FCG && direct_fine(H)) ? (index & 1) : 0;
 }
 
-int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady_clock::time_point t0)
+// The end of a solve in two halves.  enqueue: from the state header hd (the
+// solve is over), move the iterate into x if the last direct-form cycle left
+// it in lv[0].t, zero it for a zero right-hand side or remove its mean for a
+// singular problem, and copy the whole state to H->st_host.  complete (once
+// that copy has arrived): the status and info.
+int finish_enqueue(nn4mg_hier *H, double *x, const StateHeader &hd)
 {
     hipStream_t s = H->stream;
     const size_t n = H->lv[0].n;
-    StateHeader hd;
-    int rc;
-    if ((rc = read_header(H, &hd))) return rc;
     // an odd number of direct-form cycles leaves the iterate in lv[0].t
     if (iteration_parity(H, hd.nres > 0 ? hd.nres - 1 : 0)) HIP_TRY(launch_copy(x, H->lv[0].t, n, nullptr, s));
     if (hd.nb == 0.0) {
@@ -1275,7 +1370,11 @@ int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady
         HIP_TRY(launch_sub_scalar(x, n, H->scal + 1, s));
     }
     HIP_TRY(hipMemcpyAsync(H->st_host, H->st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    return NN4MG_OK;
+}
+
+int finish_complete(nn4mg_hier *H, nn4mg_info *info, std::chrono::steady_clock::time_point t0)
+{
     const SolveState &S = *H->st_host;
     prof_close_solve(H, S.nres - 1, S.nb > 0.0);
     int status = NN4MG_OK;
@@ -1293,6 +1392,16 @@ int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady
         info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;
+}
+
+int finish_solve(nn4mg_hier *H, double *x, nn4mg_info *info, std::chrono::steady_clock::time_point t0)
+{
+    StateHeader hd;
+    int rc;
+    if ((rc = read_header(H, &hd))) return rc;
+    if ((rc = finish_enqueue(H, x, hd))) return rc;
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    return finish_complete(H, info, t0);
 }
 
 // Capture one stationary iteration of parity `par` on the handle's stream as
@@ -1423,6 +1532,176 @@ int hier_set_stream(nn4mg_hier *H, hipStream_t s)
     if (H->stream) HIP_TRY(hipStreamSynchronize(H->stream));
     H->stream = s;
     return NN4MG_OK;
+}
+
+void hier_use_stream(nn4mg_hier *H, hipStream_t s) { H->stream = s; }
+
+int solve_header_copy(nn4mg_hier *H)
+{
+    HIP_TRY(hipMemcpyAsync(H->st_host, H->st, sizeof(StateHeader), hipMemcpyDeviceToHost, H->stream));
+    return NN4MG_OK;
+}
+
+// ---- batched hierarchies ----
+
+int view_create(nn4mg_hier *G, int c, nn4mg_hier **out)
+{
+    *out = nullptr;
+    if (!G || !G->group || c < 0 || c >= G->cap) return fail(NN4MG_EINVAL, "view: not a batched hierarchy copy");
+    nn4mg_hier *V = new nn4mg_hier(*G);
+    V->view_of = G;
+    V->group = false;
+    V->ncopy = 1;
+    V->arena = nullptr;
+    V->allocs.clear();
+    V->fields.clear();
+    V->graph[0] = V->graph[1] = nullptr;
+    V->bgraph.clear();
+    V->cap = 1;
+    V->graph_b = nullptr;
+    V->graph_x = nullptr;
+    V->prof_on = false;
+    V->prof_ev.clear();
+    V->prof_cls.clear();
+    V->prof_tag.clear();
+    V->prof_valid.clear();
+    V->prof_lvl.clear();
+    V->bytes = 0;
+    V->st_host = G->st_host + c;
+    const long long off = (long long)c * G->bstride;
+    for (const nn4mg_hier::Field &f : G->fields) {
+        const size_t at = (size_t)((const char *)f.ptr - (const char *)G);
+        if (at + sizeof(void *) > sizeof(nn4mg_hier)) {
+            delete V;
+            return fail(NN4MG_EINVAL, "view: field outside the hierarchy");
+        }
+        void **pv = reinterpret_cast<void **>(reinterpret_cast<char *>(V) + at);
+        *pv = copy_ptr(*pv, off);
+    }
+    *out = V;
+    return NN4MG_OK;
+}
+
+void view_destroy(nn4mg_hier *V)
+{
+    if (!V || !V->view_of) return;
+    V->st_host = nullptr;
+    delete V;
+}
+
+double *hier_bw(nn4mg_hier *H) { return H->bw; }
+double *hier_xw(nn4mg_hier *H) { return H->xw; }
+
+int hier_load_coef(nn4mg_hier *H, const double *k_dev)
+{
+    if (H->cfg.coef_mode == NN4MG_COEF_NODAL) {
+        if (!k_dev) return fail(NN4MG_EINVAL, "nodal coefficient requires k");
+        return load_k(H, k_dev);
+    }
+    return rebuild_coefficients(H);
+}
+
+// The batched cycle over copies 0 .. k - 1, captured once per k.
+hipGraphExec_t batch_graph(nn4mg_hier *G, int k)
+{
+    if (G->bgraph[k]) return G->bgraph[k];
+    if (!G->graphs_ok || G->prof_on) return nullptr;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(G->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        G->graphs_ok = false;
+        return nullptr;
+    }
+    const int rc = enqueue_iteration(G, G->bw, G->xw, 0);
+    const hipError_t e = hipStreamEndCapture(G->stream, &g);
+    hipGraphExec_t ex = nullptr;
+    if (rc == NN4MG_OK && e == hipSuccess && g && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
+        G->bgraph[k] = ex;
+    } else {
+        (void)hipGetLastError();
+        G->graphs_ok = false;
+        ex = nullptr;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    return ex;
+}
+
+int batch_enqueue_cycles(nn4mg_hier *G, int n, int k)
+{
+    if (!G->group || k < 1 || k > G->cap) return fail(NN4MG_EINVAL, "batch: copy count outside the group");
+    if (n <= 0) return NN4MG_OK;
+    // launches below cover copies 0 .. k - 1 (the later ones have no solve)
+    G->ncopy = k;
+    int rc = NN4MG_OK;
+    if (hipGraphExec_t ex = batch_graph(G, k)) {
+        for (int c = 0; c < n && !rc; ++c)
+            if (hipGraphLaunch(ex, G->stream) != hipSuccess) rc = fail(NN4MG_EDEVICE, "hipGraphLaunch failed");
+    } else {
+        for (int c = 0; c < n && !rc; ++c) rc = enqueue_iteration(G, G->bw, G->xw, 0);
+    }
+    // the last residual of the batch is judged before the host reads the states
+    if (!rc && stop_in_chain(G) &&
+        launch_finish_norm(G->st, G->partials, resid_blocks(G), G->stream, 1, G->ncopy, G->bstride) != hipSuccess)
+        rc = fail(NN4MG_EDEVICE, "batch: stopping-rule launch failed");
+    G->ncopy = G->cap;
+    return rc;
+}
+
+// A copy with no solve: its stopping flag set, so the batched launches skip it.
+int hier_mark_idle(nn4mg_hier *H)
+{
+    static const int one = 1;
+    HIP_TRY(launch_init_state(H->st, 0.0, 0, 1, H->stream));
+    HIP_TRY(hipMemcpyAsync(&H->st->done, &one, sizeof(int), hipMemcpyHostToDevice, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    return NN4MG_OK;
+}
+
+int hier_coarse_cells(const nn4mg_hier *H) { return H->nc; }
+
+int coef_begin(nn4mg_hier *H, const double *k_dev, double *hk, int *bad)
+{
+    hipStream_t s = H->stream;
+    const Level &F = H->lv[0];
+    const Level &C = H->lv[H->L - 1];
+    HIP_TRY(hipMemcpyAsync(F.k, k_dev, F.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemsetAsync(H->flag, 0, sizeof(int), s));
+    HIP_TRY(launch_check_positive(F.k, F.n, H->flag, s));
+    HIP_TRY(hipMemcpyAsync(bad, H->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    const int rc = enqueue_coef_kernels(H);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(hk, C.k, C.n * sizeof(double), hipMemcpyDeviceToHost, s));
+    return NN4MG_OK;
+}
+
+int coef_end(nn4mg_hier *H, const double *hk, const int *bad, double *inv)
+{
+    if (*bad) return fail(NN4MG_EINVAL, "coefficient k must be positive and finite");
+    const Level &C = H->lv[H->L - 1];
+    std::vector<double> v;
+    const int rc = coarse_inverse(C.nx, C.ny, C.nz, C.h, H->cfg.bc, hk, H->singular, v);
+    if (rc) return rc;
+    std::memcpy(inv, v.data(), v.size() * sizeof(double));
+    HIP_TRY(hipMemcpyAsync(H->ainv, inv, v.size() * sizeof(double), hipMemcpyHostToDevice, H->stream));
+    return NN4MG_OK;
+}
+
+int solve_finish_enqueue(nn4mg_hier *H, double *x)
+{
+    StateHeader hd;
+    std::memcpy(&hd, H->st_host, sizeof(StateHeader));
+    return finish_enqueue(H, x, hd);
+}
+
+int solve_finish_complete(nn4mg_hier *H, nn4mg_info *info) { return finish_complete(H, info, H->solve_t0); }
+
+int hier_planned(const nn4mg_hier *H) { return H->solve_planned; }
+int hier_started(const nn4mg_hier *H) { return H->solve_enqueued > 0; }
+
+void hier_note_enqueued(nn4mg_hier *H, int n)
+{
+    H->solve_enqueued += n;
+    H->solve_planned = n;
 }
 
 }  // namespace nn4mg

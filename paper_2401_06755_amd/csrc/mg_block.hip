@@ -88,8 +88,10 @@ __device__ __forceinline__ T jacobi_at(const T *v, int c, const T *k, int ck, T 
 }
 
 template <typename T, typename KT, int OUT>
-__global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a)
+__global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a_)
 {
+    StencilArgs a = a_;
+    const int lb = enter_copy(a, xcd_remap(blockIdx.x, gridDim.x));
     constexpr bool HK = HasK<KT>::value;
     constexpr bool ADD = OUT == OUT_ADD64;
     __shared__ T sx[PN];                // P e on the staged region
@@ -101,7 +103,6 @@ __global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a)
     const int stop = a.done ? *a.done : 0;
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int bxn = (nx + BE - 1) / BE, byn = (ny + BE - 1) / BE;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = lb % bxn, rest = lb / bxn;
     const int by = rest % byn, bz = rest / byn;
     const int i0 = bx * BE, j0 = by * BE, k0 = bz * BE;
@@ -214,10 +215,11 @@ __global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a)
 }
 
 template <typename T, typename KT, int OUT>
-hipError_t goB(const StencilArgs &a, hipStream_t s)
+hipError_t goB(const StencilArgs &a_, hipStream_t s)
 {
-    const int nb = block2_blocks(a.g.nx, a.g.ny, a.g.nz);
-    hipLaunchKernelGGL((sweep2_block_kernel<T, KT, OUT>), dim3(nb), dim3(BT), 0, s, a);
+    StencilArgs a = a_;
+    const unsigned grid = batched_grid(a, block2_blocks(a.g.nx, a.g.ny, a.g.nz));
+    hipLaunchKernelGGL((sweep2_block_kernel<T, KT, OUT>), dim3(grid), dim3(BT), 0, s, a);
     return hipGetLastError();
 }
 

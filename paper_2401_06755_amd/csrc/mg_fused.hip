@@ -226,8 +226,10 @@ __device__ __forceinline__ T jacobi(const Run<T> &r, const PS<T> &p, T bb, T cw,
 // XIN: the first sweep's input is x + P e (x = a.yin, the right-hand side
 // b - bmean, output stored into a.yout, which must not alias a.yin).
 template <typename T, typename KT, int OUT, bool XIN, int TX, int RY>
-__global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sweep2_kernel(const StencilArgs a)
+__global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sweep2_kernel(const StencilArgs a_)
 {
+    StencilArgs a = a_;
+    const int lb = enter_copy(a, xcd_remap(blockIdx.x, gridDim.x));
     if (a.done && *a.done) return;
     using TL = FTile<TX, RY>;
     constexpr bool HK = HasK<KT>::value;
@@ -240,7 +242,6 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     __shared__ T sc[TL::CN];               // coarse footprint of the plane being committed
 
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int tile_x = lb % a.t.tiles_x;
     const int rest = lb / a.t.tiles_x;
     const int tile_y = rest % a.t.tiles_y;
@@ -483,9 +484,10 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
 }
 
 template <typename T, typename KT, int OUT, bool XIN = false>
-hipError_t go2(const StencilArgs &a, hipStream_t s)
+hipError_t go2(const StencilArgs &a_, hipStream_t s)
 {
-    const dim3 grid(a.t.blocks()), block(FT);
+    StencilArgs a = a_;
+    const dim3 grid(batched_grid(a, a.t.blocks())), block(FT);
     switch (a.t.tx * 10 + a.t.ry) {
     case 642: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, XIN, 64, 2>), grid, block, 0, s, a); break;
     case 641: hipLaunchKernelGGL((sweep2_kernel<T, KT, OUT, XIN, 64, 1>), grid, block, 0, s, a); break;

@@ -65,7 +65,48 @@ struct StencilArgs {
     double *partials;    // OUT_RESID: one sum of r^2 per block (x.r with dot_x), may be NULL
     int dot_x;           // OUT_RESID: partials of x.r instead of r.r
     const int *done;     // skip the launch when *done != 0 (may be NULL)
+    // batched launch: the same level of ncopy identical hierarchies whose
+    // fields lie bstride bytes apart (ncopy 0 or 1: one hierarchy)
+    int ncopy;
+    int bnb;             // blocks per copy (set by the launcher)
+    long long bstride;
 };
+
+// Move a field pointer to the copy `off` bytes further on (NULL stays NULL).
+template <typename P>
+__host__ __device__ __forceinline__ P *copy_ptr(P *p, long long off)
+{
+    return p ? reinterpret_cast<P *>(reinterpret_cast<unsigned long long>(p) + (unsigned long long)off) : p;
+}
+
+// Block lb (after the XCD remap) of a batched launch works on copy lb / bnb:
+// move every field pointer of a to that copy and return the block's index
+// within the copy.
+__device__ __forceinline__ int enter_copy(StencilArgs &a, int lb)
+{
+    if (a.ncopy <= 1) return lb;
+    const int c = lb / a.bnb;
+    const long long off = (long long)c * a.bstride;
+    a.yin = copy_ptr(a.yin, off);
+    a.ec = copy_ptr(a.ec, off);
+    a.b = copy_ptr(a.b, off);
+    a.k = copy_ptr(a.k, off);
+    a.yout = copy_ptr(a.yout, off);
+    a.x64 = copy_ptr(a.x64, off);
+    a.bmean = copy_ptr(a.bmean, off);
+    a.r = copy_ptr(a.r, off);
+    a.rc = copy_ptr(a.rc, off);
+    a.partials = copy_ptr(a.partials, off);
+    a.done = copy_ptr(a.done, off);
+    return lb - c * a.bnb;
+}
+
+// The launch grid of a with nb blocks per copy; sets a.bnb.
+inline unsigned batched_grid(StencilArgs &a, int nb)
+{
+    a.bnb = nb;
+    return (unsigned)nb * (unsigned)(a.ncopy > 1 ? a.ncopy : 1);
+}
 
 // Device-resident state of a solve; the host polls a copy of it.
 struct SolveState {
@@ -98,7 +139,8 @@ hipError_t launch_stencil(int T_is_f64, int kt, int in_mode, int out_mode, int o
 // partials (skipped when a stand-alone launch marked them taken).
 hipError_t launch_restrict_chain(int T_is_f64, const void *fine, void *c1, void *c2, void *c3, int nx, int ny, int nz,
                                  int depth, const int *done, hipStream_t s, SolveState *st = nullptr,
-                                 const double *partials = nullptr, int np = 0);
+                                 const double *partials = nullptr, int np = 0, int ncopy = 1,
+                                 long long bstride = 0);
 hipError_t launch_restrict(int T_is_f64, const void *fine, void *coarse, int nx, int ny, int nz, const int *done,
                            hipStream_t s);
 hipError_t launch_coarsen_k(const double *kf, double *kc, int nx, int ny, int nz, int harmonic, hipStream_t s);
@@ -118,7 +160,8 @@ hipError_t launch_set_nb(SolveState *st, const double *sumsq, hipStream_t s);
 // Stopping rule after a residual: consumes partials of r^2.
 // Stopping rule on the residual partials; mark_taken = 1 tells the stopping
 // workgroup of the next restriction chain that this residual is done.
-hipError_t launch_finish_norm(SolveState *st, const double *partials, int n, hipStream_t s, int mark_taken = 0);
+hipError_t launch_finish_norm(SolveState *st, const double *partials, int n, hipStream_t s, int mark_taken = 0,
+                              int ncopy = 1, long long bstride = 0);
 
 hipError_t launch_coarse_solve(int T_is_f64, const void *bc, void *ec, const double *ainv, int n, int singular,
                                const int *done, hipStream_t s);
@@ -140,6 +183,49 @@ int solve_header_async(nn4mg_hier *H, hipEvent_t ev);
 int solve_after_header(nn4mg_hier *H);
 int solve_finish(nn4mg_hier *H, double *x, nn4mg_info *info);
 int hier_set_stream(nn4mg_hier *H, hipStream_t s);
+// the stream of later work on H, with no wait for work already enqueued
+void hier_use_stream(nn4mg_hier *H, hipStream_t s);
+// copy the state header to pinned host memory (no event)
+int solve_header_copy(nn4mg_hier *H);
+
+// ---- batched hierarchies (mg_api.hip) ----
+// setup_hier: a hierarchy of a validated cfg (group false: one copy, as
+// nn4mg_setup), or a batched group of ncopy identical copies (the stationary
+// cycle with two post-sweeps and a one-workgroup coarse end, else
+// NN4MG_EINVAL) that launches every cycle kernel once over all copies; copy c is
+// driven through its view (the solve pieces above, single launches).  Each
+// copy has its own right-hand side and iterate fields (hier_bw / hier_xw) and
+// coefficient (hier_load_coef on its view).  batch_enqueue_cycles: n cycles of
+// every copy whose stopping rule has not fired, then the batch-end rule
+// (hier_mark_idle: set a copy's stopping flag, for copies with no solve).
+// hier_note_enqueued: record on a view that n cycles were enqueued for it.
+int setup_hier(const nn4mg_config *cfg, const double *k_dev, hipStream_t stream, int ncopy, nn4mg_hier **out,
+               bool group = false);
+int view_create(nn4mg_hier *G, int c, nn4mg_hier **out);
+void view_destroy(nn4mg_hier *V);
+double *hier_bw(nn4mg_hier *H);
+double *hier_xw(nn4mg_hier *H);
+int hier_load_coef(nn4mg_hier *H, const double *k_dev);
+// Asynchronous halves of the nodal coefficient set-up and of a solve's end
+// (no host wait; the caller waits for the enqueued work in between).
+// coef_begin: copy of k, its positivity check (flag into *bad, pinned), the
+// coarse levels' coefficients and the coarsest level's k into hk (pinned,
+// hier_coarse_cells doubles); coef_end (after those arrived): the flag, the
+// coarsest inverse formed on the host into inv (pinned, cells^2 doubles) and
+// its upload.  solve_finish_enqueue (the header in host memory says the solve
+// is over): the iterate's projection or zero fill and the copy of the whole
+// state to host memory; solve_finish_complete (after it arrived): info and
+// status, as solve_finish.
+int hier_coarse_cells(const nn4mg_hier *H);
+int coef_begin(nn4mg_hier *H, const double *k_dev, double *hk, int *bad);
+int coef_end(nn4mg_hier *H, const double *hk, const int *bad, double *inv);
+int solve_finish_enqueue(nn4mg_hier *H, double *x);
+int solve_finish_complete(nn4mg_hier *H, nn4mg_info *info);
+int hier_mark_idle(nn4mg_hier *H);
+int batch_enqueue_cycles(nn4mg_hier *G, int n, int k);  // over copies 0 .. k - 1
+int hier_planned(const nn4mg_hier *H);
+int hier_started(const nn4mg_hier *H);  // cycles have been enqueued for it
+void hier_note_enqueued(nn4mg_hier *H, int n);
 
 // ---- flexible CG vector kernels (mg_fcg.hip); t = -A p, q = A p = -t ----
 // dots: rho = z.r (mode 0), or rho = z.r and beta = -(z.q)/(p.q) (mode 2);
@@ -193,6 +279,8 @@ struct TailArgs {
     double omega;
     int nu;
     const int *done;                    // skip when *done != 0 (may be NULL)
+    int ncopy;                          // batched: one workgroup per copy, fields bstride bytes apart
+    long long bstride;
 };
 // LDS elements of the tail levels' fields: right-hand side, two iterates and
 // (nodal) the coefficient per level, the last three with a one-cell halo.

@@ -75,10 +75,26 @@ __device__ double reduce_512(const double *p, int n, double *red)
 template <typename T>
 __global__ __launch_bounds__(512) void restrict_chain_kernel(const T *f, T *c1, T *c2, T *c3, int nx, int ny, int nz,
                                                              int depth, const int *done, SolveState *st,
-                                                             const double *partials, int np)
+                                                             const double *partials, int np, int nbc,
+                                                             long long bstride)
 {
+    // batched (nbc > 0): workgroup g works on copy g / nbc, whose fields lie
+    // bstride bytes further on per copy
+    int g = (int)blockIdx.x;
+    if (nbc > 0) {
+        const int c = g / nbc;
+        g -= c * nbc;
+        const long long off = (long long)c * bstride;
+        f = copy_ptr(f, off);
+        c1 = copy_ptr(c1, off);
+        c2 = copy_ptr(c2, off);
+        c3 = copy_ptr(c3, off);
+        done = copy_ptr(done, off);
+        st = copy_ptr(st, off);
+        partials = copy_ptr(partials, off);
+    }
     if (done && *done) return;
-    if (st && blockIdx.x == 0) {
+    if (st && g == 0) {
         // the extra first workgroup (dispatched first, so its reduction is off
         // the chain's critical path): stopping rule of the residual the
         // previous cycle ended with, unless a stand-alone launch already took it
@@ -99,7 +115,7 @@ __global__ __launch_bounds__(512) void restrict_chain_kernel(const T *f, T *c1, 
     __shared__ T s1[512];  // the 8^3 block of the first coarse level
     __shared__ T s2[64];   // the 4^3 block of the second
     const int bxn = (nx + 15) / 16, byn = (ny + 15) / 16;
-    const int bid = st ? (int)blockIdx.x - 1 : (int)blockIdx.x;
+    const int bid = st ? g - 1 : g;
     const int bx = bid % bxn, rest = bid / bxn;
     const int by = rest % byn, bz = rest / byn;
     const int t = threadIdx.x;
@@ -232,9 +248,13 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double *p, int n, do
     if (threadIdx.x == 0) out[0] = scale * s;
 }
 
-__global__ __launch_bounds__(1024) void finish_norm_kernel(SolveState *st, const double *p, int n, int mark)
+__global__ __launch_bounds__(1024) void finish_norm_kernel(SolveState *st, const double *p, int n, int mark,
+                                                          long long bstride)
 {
     __shared__ double red[16];
+    // batched: workgroup c judges copy c
+    st = copy_ptr(st, (long long)blockIdx.x * bstride);
+    p = copy_ptr(p, (long long)blockIdx.x * bstride);
     if (st->done) return;
     const double s = reduce_1024(p, n, red);
     if (threadIdx.x == 0) {
@@ -360,18 +380,21 @@ hipError_t launch_restrict(int T_is_f64, const void *fine, void *coarse, int nx,
 
 hipError_t launch_restrict_chain(int T_is_f64, const void *fine, void *c1, void *c2, void *c3, int nx, int ny, int nz,
                                  int depth, const int *done, hipStream_t s, SolveState *st, const double *partials,
-                                 int np)
+                                 int np, int ncopy, long long bstride)
 {
     if (depth < 1 || depth > 3) return hipErrorInvalidValue;
     if (st && (!partials || np < 1)) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)(((nx + 15) / 16) * ((ny + 15) / 16) * ((nz + 15) / 16));
-    const dim3 grid(st ? nb + 1 : nb);
+    const unsigned per = st ? nb + 1 : nb;
+    const bool batched = ncopy > 1;
+    const dim3 grid(batched ? per * (unsigned)ncopy : per);
+    const int nbc = batched ? (int)per : 0;
     if (T_is_f64)
         hipLaunchKernelGGL(restrict_chain_kernel<double>, grid, dim3(512), 0, s, (const double *)fine, (double *)c1,
-                           (double *)c2, (double *)c3, nx, ny, nz, depth, done, st, partials, np);
+                           (double *)c2, (double *)c3, nx, ny, nz, depth, done, st, partials, np, nbc, bstride);
     else
         hipLaunchKernelGGL(restrict_chain_kernel<float>, grid, dim3(512), 0, s, (const float *)fine, (float *)c1,
-                           (float *)c2, (float *)c3, nx, ny, nz, depth, done, st, partials, np);
+                           (float *)c2, (float *)c3, nx, ny, nz, depth, done, st, partials, np, nbc, bstride);
     return hipGetLastError();
 }
 
@@ -432,9 +455,11 @@ hipError_t launch_set_nb(SolveState *st, const double *sumsq, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_finish_norm(SolveState *st, const double *partials, int n, hipStream_t s, int mark_taken)
+hipError_t launch_finish_norm(SolveState *st, const double *partials, int n, hipStream_t s, int mark_taken,
+                              int ncopy, long long bstride)
 {
-    hipLaunchKernelGGL(finish_norm_kernel, dim3(1), dim3(1024), 0, s, st, partials, n, mark_taken);
+    hipLaunchKernelGGL(finish_norm_kernel, dim3(ncopy > 1 ? ncopy : 1), dim3(1024), 0, s, st, partials, n, mark_taken,
+                       ncopy > 1 ? bstride : 0LL);
     return hipGetLastError();
 }
 

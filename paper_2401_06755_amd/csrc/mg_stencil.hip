@@ -292,8 +292,10 @@ struct Run {
 #endif
 
 template <typename T, typename KT, int IN, int OUT, typename OT, int TX, int RY>
-__global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const StencilArgs a)
+__global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const StencilArgs a_)
 {
+    StencilArgs a = a_;
+    const int lb = enter_copy(a, xcd_remap(blockIdx.x, gridDim.x));
     if (a.done && *a.done) return;
     using TL = Tile<TX, RY>;
     constexpr bool HK = HasK<KT>::value;
@@ -306,7 +308,6 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
     __shared__ double red[NT / 64];
 
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int tile_x = lb % a.t.tiles_x;
     const int rest = lb / a.t.tiles_x;
     const int tile_y = rest % a.t.tiles_y;
@@ -492,15 +493,18 @@ __global__ __launch_bounds__(NT, NN4MG_MIN_WAVES) void stencil_kernel(const Sten
             for (int off = 32; off > 0; off >>= 1) nacc += __shfl_down(nacc, off);
             if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
             __syncthreads();
-            if (threadIdx.x == 0) a.partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+            // slot = the tile's index within its copy, so a batched launch
+            // sums each copy's partials in the order of a single launch
+            if (threadIdx.x == 0) a.partials[lb] = (red[0] + red[1]) + (red[2] + red[3]);
         }
     }
 }
 
 template <typename T, typename KT, int IN, int OUT, typename OT>
-hipError_t go(const StencilArgs &a, hipStream_t s)
+hipError_t go(const StencilArgs &a_, hipStream_t s)
 {
-    const dim3 grid(a.t.blocks()), block(NT);
+    StencilArgs a = a_;
+    const dim3 grid(batched_grid(a, a.t.blocks())), block(NT);
     const int key = a.t.tx * 10 + a.t.ry;
     if constexpr (OUT != OUT_RESID) {  // one row per thread: sweeps only (the restriction pairs rows)
         switch (key) {

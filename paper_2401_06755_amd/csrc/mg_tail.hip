@@ -232,6 +232,14 @@ constexpr int kTailARegs = 4;
 template <typename T, typename KT>
 __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
 {
+    // batched: workgroup c runs copy c (its fields bstride bytes further on)
+    const long long coff = a.ncopy > 1 ? (long long)blockIdx.x * a.bstride : 0;
+    const int *done_p = copy_ptr(a.done, coff);
+    const T *kpad_p = copy_ptr((const T *)a.kpad, coff);
+    const T *b_above_p = copy_ptr((const T *)a.b_above, coff);
+    const T *b_first_p = copy_ptr((const T *)a.b_first, coff);
+    const double *ainv_p = copy_ptr(a.ainv, coff);
+    T *e_first_p = copy_ptr((T *)a.e_first, coff);
     constexpr bool HK = !std::is_same<KT, NoK>::value;
     extern __shared__ __align__(16) unsigned char smem[];
     T *sm = (T *)smem;
@@ -240,7 +248,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
     __shared__ int s_total;
     const int nl = a.levels;
     // the stopping flag is read with the first loads and tested before any write
-    const int stop = a.done ? *a.done : 0;
+    const int stop = done_p ? *done_p : 0;
     if (threadIdx.x == 0) {
         int off = 0;
 #pragma unroll
@@ -284,18 +292,18 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
     T rb = (T)0;
     if ((int)threadIdx.x < n0) {
         const int c = threadIdx.x;
-        if (a.b_above) {
+        if (b_above_p) {
             const int cx = a.nx[0], cy = a.ny[0];
             const int I = c % cx, t = c / cx;
             const int J = t % cy, K = t / cy;
             const int fx = 2 * cx, fy = 2 * cy, sy = fx, sz = fx * fy;
-            const T *in = (const T *)a.b_above;
+            const T *in = b_above_p;
             const int g = 2 * I + fx * (2 * J + fy * 2 * K);
             const T v0 = in[g], v1 = in[g + 1], v2 = in[g + sy], v3 = in[g + sy + 1];
             const T v4 = in[g + sz], v5 = in[g + sz + 1], v6 = in[g + sz + sy], v7 = in[g + sz + sy + 1];
             rb = ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7));
         } else {
-            rb = ((const T *)a.b_first)[c];
+            rb = b_first_p[c];
         }
     }
     // padded coefficients (contiguous) and the coarsest inverse, first parts in registers
@@ -312,7 +320,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
 #pragma unroll
         for (int q = 0; q < kTailKRegs; ++q) {
             const int f = (int)threadIdx.x + q * TT;
-            kr[q] = f < ktot ? ((const T *)a.kpad)[f] : (T)0;
+            kr[q] = f < ktot ? kpad_p[f] : (T)0;
         }
     }
     const int ncl = a.nx[nl - 1] * a.ny[nl - 1] * a.nz[nl - 1];
@@ -320,7 +328,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
 #pragma unroll
     for (int q = 0; q < kTailARegs; ++q) {
         const int f = (int)threadIdx.x + q * TT;
-        ar[q] = (a.ainv_in_lds && f < ncl * ncl) ? a.ainv[f] : 0.0;
+        ar[q] = (a.ainv_in_lds && f < ncl * ncl) ? ainv_p[f] : 0.0;
     }
     if (stop) return;  // uniform over the workgroup
     __syncthreads();   // level table
@@ -337,7 +345,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
             const int f = (int)threadIdx.x + q * TT;
             if (f < ktot) sm[kbase + f] = kr[q];
         }
-        for (int f = threadIdx.x + kTailKRegs * TT; f < ktot; f += TT) sm[kbase + f] = ((const T *)a.kpad)[f];
+        for (int f = threadIdx.x + kTailKRegs * TT; f < ktot; f += TT) sm[kbase + f] = kpad_p[f];
     }
     if (a.ainv_in_lds) {
 #pragma unroll
@@ -345,7 +353,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
             const int f = (int)threadIdx.x + q * TT;
             if (f < nc * nc) ainv_s[f] = ar[q];
         }
-        for (int c = threadIdx.x + kTailARegs * TT; c < nc * nc; c += TT) ainv_s[c] = a.ainv[c];
+        for (int c = threadIdx.x + kTailARegs * TT; c < nc * nc; c += TT) ainv_s[c] = ainv_p[c];
     }
     __syncthreads();
     for (int l = 0; l + 1 < nl; ++l) {
@@ -371,7 +379,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
                 sg[r] = pc[r].sg;
                 // four interleaved partial sums keep the loads in flight
                 double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-                const double *col = a.ainv_in_lds ? (const double *)ainv_s : a.ainv;
+                const double *col = a.ainv_in_lds ? (const double *)ainv_s : ainv_p;
                 int j = 0;
                 if (a.ainv_in_lds) {
                     for (; j + 3 < nc; j += 4) {
@@ -428,7 +436,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
     }
 
     // the first tail level's correction back to HBM
-    T *e_out = (T *)a.e_first;
+    T *e_out = e_first_p;
     for (int c = threadIdx.x; c < lv[0].n; c += TT) e_out[c] = sm[lv[0].oya + padded_of(lv[0], c)];
 }
 
@@ -509,7 +517,7 @@ hipError_t launch_tail(int T_is_f64, int kt, const TailArgs &a, hipStream_t s)
     auto go = [&](auto kernel) -> hipError_t {
         hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kernel, dim3(1), dim3(TT), lds, s, a);
+        hipLaunchKernelGGL(kernel, dim3(a.ncopy > 1 ? a.ncopy : 1), dim3(TT), lds, s, a);
         return hipGetLastError();
     };
     if (T_is_f64) {

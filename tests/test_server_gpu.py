@@ -135,3 +135,51 @@ def test_shared_tag_keeps_every_request_alive(mg):
         bb = w["b"] - w["b"].mean()
         r = bb - oracle.apply(x, w["h"], w["bc"], w["k"])
         assert np.linalg.norm(r) <= 1.05e-8 * np.linalg.norm(bb)
+
+
+def solve_alone(mg, cfg, k, b, rtol=1e-8, max_cycles=2000):
+    import torch
+
+    H = mg.Hierarchy(cfg, k)
+    x = torch.zeros_like(b)
+    info = H.solve(b, x, rtol=rtol, max_cycles=max_cycles)
+    torch.cuda.synchronize()
+    H.close()
+    return x.cpu().numpy(), info
+
+
+def test_batched_group_matches_standalone_solves(mg):
+    """Requests of one configuration run as copies of one batched group (one
+    launch per kernel over every running copy).  Each result equals the
+    stand-alone hierarchy's solve of the same system: the same cycle count and
+    the same iterate (per-cell arithmetic does not depend on the batch), and
+    the residual history to rounding (the norm's per-tile partial sums follow
+    the group's launch shape)."""
+    reqs = make_requests(mg, 12, edges=(48,)) + make_requests(mg, 4, edges=(32,))
+    xs, res, stats = serve(mg, reqs, budget=8 << 30, slots=16)
+    for i, (cfg, k, b, w) in enumerate(reqs):
+        x1, info1 = solve_alone(mg, cfg, k, b)
+        r = res[i]
+        assert r.info.status == 0 and info1.status == 0
+        assert r.info.cycles == info1.cycles, i
+        assert np.array_equal(xs[i], x1), i
+        h_s, h_1 = np.array(r.info.history()), np.array(info1.history())
+        assert np.all(np.abs(h_s - h_1) <= 1e-12 * h_1), i
+
+
+def test_group_member_with_bad_coefficient_fails_alone(mg):
+    """A request whose coefficient is not positive fails with EINVAL inside a
+    running group; the other copies of the group finish normally."""
+    reqs = make_requests(mg, 5, edges=(32,))
+    cfg, k, b, w = reqs[2]
+    kb = k.clone()
+    kb[123] = -1.0
+    reqs[2] = (cfg, kb, b, w)
+    xs, res, stats = serve(mg, reqs, budget=8 << 30, slots=8)
+    assert res[2].info.status == mg.NN4MG_EINVAL
+    for i in (0, 1, 3, 4):
+        assert res[i].info.status == 0
+        x = xs[i].reshape(reqs[i][3]["b"].shape)
+        bb = reqs[i][3]["b"] - reqs[i][3]["b"].mean()
+        r = bb - oracle.apply(x, reqs[i][3]["h"], reqs[i][3]["bc"], reqs[i][3]["k"])
+        assert np.linalg.norm(r) <= 1.05e-8 * np.linalg.norm(bb)
