@@ -88,13 +88,14 @@ KCLASS = {"resid": 0, "sweeps": 1, "sweep": 2}
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for
 # a plain 256 MiB device copy (fetch x2.0, write x1.0); the commands and raw
 # counts are in profiles/dense_sphere_256_fp64_fine_kernels.md.  Each figure
-# carries a hash of the kernel's source files and of the host driver that
-# chooses its arguments, as profiled; once those files change, the figure no
-# longer describes the kernel and traffic is null.
-KERNEL_SOURCES = {"resid": ("mg_stencil.hip", "mg_device.h", "mg_api.hip"),
-                  "sweeps": ("mg_fused.hip", "mg_device.h", "mg_api.hip")}
-MEASURED_TRAFFIC_FP64_256 = {"resid": (577.6e6, "222c5cd01dad4136"),
-                             "sweeps": (588.9e6, "64745bab8180d429")}
+# carries a hash of the kernel's source files and the algorithmic bytes per
+# cell of the form it ran in (which outputs the launch writes), as profiled;
+# once either differs, the figure no longer describes the kernel and traffic
+# is null.
+KERNEL_SOURCES = {"resid": ("mg_stencil.hip", "mg_device.h", "mg_internal.h"),
+                  "sweeps": ("mg_fused.hip", "mg_device.h", "mg_internal.h")}
+MEASURED_TRAFFIC_FP64_256 = {"resid": (429.0e6, "e89450636717dbb6", 25),
+                             "sweeps": (595.8e6, "e9d9146969281c9e", 33)}
 
 
 def kernel_source_hash(cls):
@@ -107,10 +108,11 @@ def kernel_source_hash(cls):
     return m.hexdigest()[:16]
 
 
-def measured_traffic(table):
+def measured_traffic(table, bytes_per_cell):
     """Counter-measured bytes per launch of each kernel class whose sources
-    still hash to the profiled ones."""
-    return {cls: val for cls, (val, hsh) in table.items() if kernel_source_hash(cls) == hsh}
+    still hash to the profiled ones and that ran in the profiled form."""
+    return {cls: val for cls, (val, hsh, bpc) in table.items()
+            if kernel_source_hash(cls) == hsh and bytes_per_cell.get(cls) == bpc}
 
 
 def log(msg):
@@ -646,7 +648,8 @@ def main():
                      autotune=not args.no_autotune)
     value = r64["n"] * r64["cycles"] / r64["dt"] / 1e9
     best, roof, per_kernel = roofline(r64, "fp64",
-                                      measured_traffic(MEASURED_TRAFFIC_FP64_256) if args.n == 256 else None)
+                                      measured_traffic(MEASURED_TRAFFIC_FP64_256, fine_bytes("fp64", r64))
+                                      if args.n == 256 else None)
     model_bytes = cycle_model_bytes(r64, "fp64")
     out = {
         "metric": "V-cycle Gcell-updates/s (solve to relative residual 1e-8)",

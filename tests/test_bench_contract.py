@@ -77,10 +77,17 @@ def test_roofline_fields():
 
 
 def test_measured_traffic_tied_to_kernel_sources():
-    # the counter figures hold only for the kernel sources they were taken on
+    # the counter figures hold only for the kernel sources and the launch form
+    # (bytes per cell) they were taken on
     cur = {cls: bench.kernel_source_hash(cls) for cls in bench.KERNEL_SOURCES}
-    table = {cls: (1.0e9, cur[cls]) for cls in cur}
-    assert bench.measured_traffic(table) == {cls: 1.0e9 for cls in cur}
-    stale = dict(table, sweeps=(1.0e9, "0" * 16))
-    got = bench.measured_traffic(stale)
+    bpc = bench.BYTES_PER_CELL["fp64"]
+    table = {cls: (1.0e9, cur[cls], bpc[cls]) for cls in cur}
+    assert bench.measured_traffic(table, bpc) == {cls: 1.0e9 for cls in cur}
+    stale = dict(table, sweeps=(1.0e9, "0" * 16, bpc["sweeps"]))
+    got = bench.measured_traffic(stale, bpc)
     assert "sweeps" not in got and got["resid"] == 1.0e9
+    other_form = dict(table, resid=(1.0e9, cur["resid"], bpc["resid"] + 8))
+    got = bench.measured_traffic(other_form, bpc)
+    assert "resid" not in got and got["sweeps"] == 1.0e9
+    # the committed figures name classes the bench knows
+    assert set(bench.MEASURED_TRAFFIC_FP64_256) <= set(bench.KERNEL_SOURCES)
