@@ -5,6 +5,8 @@
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -73,10 +75,13 @@ struct StencilArgs {
 };
 
 // Move a field pointer to the copy `off` bytes further on (NULL stays NULL).
+// Byte-pointer arithmetic, not integer casts: the compiler then still knows
+// that the result points to global memory and keeps global (not flat) loads.
 template <typename P>
 __host__ __device__ __forceinline__ P *copy_ptr(P *p, long long off)
 {
-    return p ? reinterpret_cast<P *>(reinterpret_cast<unsigned long long>(p) + (unsigned long long)off) : p;
+    using B = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+    return p ? (P *)((B *)p + off) : p;
 }
 
 // Block lb (after the XCD remap) of a batched launch works on copy lb / bnb:
