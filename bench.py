@@ -94,8 +94,8 @@ KCLASS = {"resid": 0, "sweeps": 1, "sweep": 2}
 # is null.
 KERNEL_SOURCES = {"resid": ("mg_stencil.hip", "mg_device.h", "mg_internal.h"),
                   "sweeps": ("mg_fused.hip", "mg_device.h", "mg_internal.h")}
-MEASURED_TRAFFIC_FP64_256 = {"resid": (429.0e6, "e89450636717dbb6", 25),
-                             "sweeps": (595.8e6, "e9d9146969281c9e", 33)}
+MEASURED_TRAFFIC_FP64_256 = {"resid": (430.9e6, "709d85d8a64f9915", 25),
+                             "sweeps": (607.4e6, "ee32ba851f6aac9c", 33)}
 
 
 def kernel_source_hash(cls):
