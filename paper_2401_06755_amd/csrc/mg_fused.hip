@@ -239,7 +239,7 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     __shared__ T sk[3][HK ? TL::PN : 1];   // coefficient planes
     __shared__ T sy[2][TL::QN];            // first-sweep output planes
     __shared__ T sb[2][TL::QN];            // first-sweep right-hand sides (signed), same planes
-    __shared__ T sc[TL::CN];               // coarse footprint of the plane being committed
+    __shared__ T sc[2][TL::CN];            // coarse footprint of the next plane to commit (by plane parity)
 
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int tile_x = lb % a.t.tiles_x;
@@ -287,7 +287,17 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     // they are reloaded at the end of the step.  Either way no register still
     // holding a load in flight is copied at the loop's back edge (a copy would
     // wait for every outstanding load and undo the two-plane prefetch).
+    // (coarse values first: they are staged one step before the rest)
     auto fetch_kc = [&](FPre<T, KT, TX, RY, ADD, XIN> &p, int zi) {
+        const int K = zi >> 1;
+        int s1 = 1, s2 = 1;
+        const size_t p1 = cplane * (size_t)fold(K, a.cnz, a.g.bc[4], a.g.bc[5], s1);
+        const size_t p2 = cplane * (size_t)fold(K + ((zi & 1) ? 1 : -1), a.cnz, a.g.bc[4], a.g.bc[5], s2);
+#pragma unroll
+        for (int q = 0; q < TL::NPREC; ++q) {
+            p.c1[q] = ep[p1 + (size_t)G.coff[q]];
+            p.c2[q] = ep[p2 + (size_t)G.coff[q]];
+        }
         int sk_ = 1;
         const size_t pz = plane * (size_t)fold(zi, nz, a.g.bc[4], a.g.bc[5], sk_);
         if constexpr (HK) {
@@ -297,15 +307,6 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
         if constexpr (XIN) {
 #pragma unroll
             for (int q = 0; q < TL::NPRE; ++q) p.xs[q] = xp[pz + (size_t)G.off[q]];
-        }
-        const int K = zi >> 1;
-        int s1 = 1, s2 = 1;
-        const size_t p1 = cplane * (size_t)fold(K, a.cnz, a.g.bc[4], a.g.bc[5], s1);
-        const size_t p2 = cplane * (size_t)fold(K + ((zi & 1) ? 1 : -1), a.cnz, a.g.bc[4], a.g.bc[5], s2);
-#pragma unroll
-        for (int q = 0; q < TL::NPREC; ++q) {
-            p.c1[q] = ep[p1 + (size_t)G.coff[q]];
-            p.c2[q] = ep[p2 + (size_t)G.coff[q]];
         }
     };
     // MODE 0: general (every load conditional on the planes of the chunk);
@@ -335,22 +336,29 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
         fetch_b(std::integral_constant<int, 0>{}, p, zi);
     };
 
-    // P e (plus x, XIN) of plane zi into sx[buf] (coarse footprint staged in
-    // LDS first), the coefficient into sk[buf].
-    auto commit = [&](const FPre<T, KT, TX, RY, ADD, XIN> &p, int zi, int buf) {
+    // The coarse footprint of plane zi, interpolated in z, into sc[zi & 1].
+    // Staged one step ahead (before the barrier that precedes the second
+    // sweep), so the commit needs no barrier of its own before reading it.
+    auto stage_c = [&](const FPre<T, KT, TX, RY, ADD, XIN> &p, int zi) {
         const int K = zi >> 1;
-        int s1 = 1, s2 = 1, sz = 1;
+        int s1 = 1, s2 = 1;
         (void)fold(K, a.cnz, a.g.bc[4], a.g.bc[5], s1);
         (void)fold(K + ((zi & 1) ? 1 : -1), a.cnz, a.g.bc[4], a.g.bc[5], s2);
-        if constexpr (XIN) (void)fold(zi, nz, a.g.bc[4], a.g.bc[5], sz);
         const T w1 = (T)(0.75 * s1), w2 = (T)(0.25 * s2);
 #pragma unroll
         for (int q = 0; q < TL::NPREC; ++q)
             if (q * FT + (int)threadIdx.x < TL::CN) {
                 const T v = w1 * p.c1[q] + w2 * p.c2[q];
-                sc[q * FT + threadIdx.x] = G.cneg[q] ? -v : v;
+                sc[zi & 1][q * FT + threadIdx.x] = G.cneg[q] ? -v : v;
             }
-        __syncthreads();
+    };
+
+    // P e (plus x, XIN) of plane zi into sx[buf] from its staged coarse
+    // footprint, the coefficient into sk[buf].
+    auto commit = [&](const FPre<T, KT, TX, RY, ADD, XIN> &p, int zi, int buf) {
+        int sz = 1;
+        if constexpr (XIN) (void)fold(zi, nz, a.g.bc[4], a.g.bc[5], sz);
+        const T *scp = sc[zi & 1];
 #pragma unroll
         for (int q = 0; q < TL::NPRE; ++q) {
             const int idx = q * FT + threadIdx.x;
@@ -360,7 +368,7 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
                 const int tdy = ((G.tap[q] >> 17) & 1) ? TL::CX : -TL::CX;
                 const T w3 = (T)0.75, wq = (T)0.25;
                 const int t1 = t0 + tdy;
-                const T pe = w3 * (w3 * sc[t0] + wq * sc[t0 + tdx]) + wq * (w3 * sc[t1] + wq * sc[t1 + tdx]);
+                const T pe = w3 * (w3 * scp[t0] + wq * scp[t0 + tdx]) + wq * (w3 * scp[t1] + wq * scp[t1 + tdx]);
                 if constexpr (XIN)
                     sx[buf][idx] = ((G.xneg[q] != (sz < 0)) ? -p.xs[q] : p.xs[q]) + pe;
                 else
@@ -377,7 +385,9 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     // path, so the compiler's wait counts let the loads of the next two planes
     // stay in flight; the general form serves the first and last steps of the
     // march and tiles that cross the grid's edge.
-    auto step = [&](auto mode_tag, FPre<T, KT, TX, RY, ADD, XIN> &p, int zi) {
+    // pn: the other prefetch set, holding plane zi + 1's loads.
+    auto step = [&](auto mode_tag, FPre<T, KT, TX, RY, ADD, XIN> &p, const FPre<T, KT, TX, RY, ADD, XIN> &pn,
+                    int zi) {
         constexpr int MODE = decltype(mode_tag)::value;
         constexpr bool ST = MODE == 1;  // steady: every condition below holds
         constexpr bool FX = MODE != 0;  // fixed loads
@@ -416,8 +426,10 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
                 w1 = w2;
             }
         }
+        // the next plane's coarse footprint (its commit reads it after the barrier below)
+        if (FX || zi + 1 <= z1 + 1) stage_c(pn, zi + 1);
+        __syncthreads();
         if (ST || zi >= z0) {
-            __syncthreads();
             // second sweep: absorb y1(zi - 1) with the coefficient plane zi - 1,
             // completing the output plane zi - 2
             const int kb = (buf + 2) % 3;
@@ -456,6 +468,8 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
 
     fetch(pA, z0 - 2);
     fetch(pB, z0 - 1);
+    stage_c(pA, z0 - 2);
+    __syncthreads();
     const std::integral_constant<int, 0> gen{};
     const std::integral_constant<int, 1> steady{};
     const std::integral_constant<int, 2> first{};
@@ -469,17 +483,17 @@ __global__ __launch_bounds__(FT) __attribute__((amdgpu_waves_per_eu(2))) void sw
     const bool inside = i0 + TX <= nx && j0 + TL::TY <= ny && z1 - z0 >= 4;  // uniform over the workgroup
     if (inside) {
         for (; zi < z0 + 2; zi += 2) {
-            step(first, pA, zi);
-            step(first, pB, zi + 1);
+            step(first, pA, pB, zi);
+            step(first, pB, pA, zi + 1);
         }
         for (; zi + 3 <= z1 + 1; zi += 2) {
-            step(steady, pA, zi);
-            step(steady, pB, zi + 1);
+            step(steady, pA, pB, zi);
+            step(steady, pB, pA, zi + 1);
         }
     }
     for (; zi <= z1 + 1; zi += 2) {
-        step(gen, pA, zi);
-        if (zi + 1 <= z1 + 1) step(gen, pB, zi + 1);
+        step(gen, pA, pB, zi);
+        if (zi + 1 <= z1 + 1) step(gen, pB, pA, zi + 1);
     }
 }
 
