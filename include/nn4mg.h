@@ -314,7 +314,7 @@ typedef struct {
  * 20 cycles, 2 corrections, 2 predictor iterations. */
 void nn4mg_step_params_default(nn4mg_step_params *p);
 /* Workspace for an nx x ny x nz grid of spacing h (each dim >= 4, even and
- * coarsenable like nn4mg_setup's grids).  The launch shapes of its pressure
+ * coarsenable like nn4mg_setup's grids, fewer than 2^31 cells).  The launch shapes of its pressure
  * hierarchy are autotuned once here (a few cycles on zeroed work fields,
  * synchronous on hip_stream).  Errors: EINVAL, ENOMEM, EDEVICE. */
 int nn4mg_step_create(int nx, int ny, int nz, double h, const nn4mg_step_params *p, void *hip_stream,

@@ -587,27 +587,38 @@ __global__ __launch_bounds__(256) void copy3_kernel(size_t n, C3 src, F3 dst)
 // advection (Table disc_combinations, "linear/quadratic"); the volume-fraction
 // diffusion and the two pressure equations keep the linear filters.  Each
 // kernel sums its 125 taps straight from global memory (L1/L2 carry the
-// re-reads), rows first, so no neighbourhood is held in registers.
+// re-reads), rows first, so no neighbourhood is held in registers; the folded
+// indices of the cell's 5 x 5 x 5 neighbourhood and the faces each offset
+// crosses are worked out once per cell (Nb5) and shared by every field, whose
+// boundary rule then only picks which crossings flip the sign.
 
 struct V5 {
     double w[5];
 };
 
+__constant__ double kQuadM[5] = {-1.0, 4.0, 24.0, 4.0, -1.0};
+__constant__ double kQuadG[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
+__constant__ double kQuadK[5] = {1.0, -16.0, 30.0, -16.0, 1.0};
+
+// Weights of the three 1D filters; Mz / Gz / Kz give the weight of a runtime
+// offset (the filters' outer z loop) from the constant tables with the same
+// arithmetic, so no weight array is indexed at run time.
 struct Filt2 {
     V5 M, G, K;
-    double ml;
-    __device__ explicit Filt2(double h)
+    double ml, h;
+    __device__ explicit Filt2(double h_) : h(h_)
     {
-        const double m[5] = {-1.0, 4.0, 24.0, 4.0, -1.0}, g[5] = {1.0, -8.0, 0.0, 8.0, -1.0},
-                     k[5] = {1.0, -16.0, 30.0, -16.0, 1.0};
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            M.w[q] = h * m[q] / 30.0;
-            G.w[q] = g[q] / 12.0;
-            K.w[q] = k[q] / (12.0 * h);
+            M.w[q] = h * kQuadM[q] / 30.0;
+            G.w[q] = kQuadG[q] / 12.0;
+            K.w[q] = kQuadK[q] / (12.0 * h);
         }
         ml = h * h * h;
     }
+    __device__ double Mz(int c) const { return h * kQuadM[c] / 30.0; }
+    __device__ double Gz(int c) const { return kQuadG[c] / 12.0; }
+    __device__ double Kz(int c) const { return kQuadK[c] / (12.0 * h); }
 };
 
 // Index up to two cells outside folded onto the cell it mirrors; s flips on a
@@ -640,24 +651,88 @@ struct Tap2 {
     }
 };
 
-// p_hs: +mirror on the sides, -mirror on top, and below the bottom the mirror
-// plus (2m + 1) g h rho of the mirrored cell (rho +mirror on the sides).
-struct TapPhs2 {
-    const double *p, *rho;
-    Grid g;
-    double gh;
-    __device__ double operator()(int i, int j, int k) const
+
+// The folded neighbourhood of one cell: for offsets o = -2 .. 2 (index o + 2)
+// along x and y, the folded index (times the axis stride); along z (the
+// filters' outer loop, not unrolled) the fold is redone per plane.  Bit o + 2
+// of l* / h* marks an offset that crossed the low / high face.
+struct Nb5 {
+    unsigned xo[5], yo[5];
+    unsigned lx, hx, ly, hy, lz, hz;
+    int k, nz;    // the cell's own z index and the grid's depth
+    unsigned sz;  // z stride
+    __device__ unsigned zo(int c) const
     {
         double s = 1.0;
-        i = fold2(i, g.nx, kOddTop, 1u, 2u, s);
-        j = fold2(j, g.ny, kOddTop, 4u, 8u, s);
-        if (k < 0) {
-            const int m = -1 - k;
-            const size_t c = at(g, i, j, m);
-            return p[c] + (double)(2 * m + 1) * gh * rho[c];
+        return sz * (unsigned)fold2(k + c - 2, nz, 0u, 16u, 32u, s);
+    }
+};
+
+__device__ inline Nb5 nb5(const Grid &g, int i, int j, int k)
+{
+    Nb5 N;
+    N.lx = N.hx = N.ly = N.hy = N.lz = N.hz = 0u;
+    N.k = k;
+    N.nz = g.nz;
+    const unsigned sy = (unsigned)g.nx;
+    N.sz = (unsigned)g.nx * (unsigned)g.ny;
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+        double s = 1.0;
+        const int ii = i + o - 2, jj = j + o - 2, kk = k + o - 2;
+        N.xo[o] = (unsigned)fold2(ii, g.nx, 0u, 1u, 2u, s);
+        N.yo[o] = sy * (unsigned)fold2(jj, g.ny, 0u, 4u, 8u, s);
+        N.lx |= (ii < 0 ? 1u : 0u) << o;
+        N.hx |= (ii >= g.nx ? 1u : 0u) << o;
+        N.ly |= (jj < 0 ? 1u : 0u) << o;
+        N.hy |= (jj >= g.ny ? 1u : 0u) << o;
+        N.lz |= (kk < 0 ? 1u : 0u) << o;
+        N.hz |= (kk >= g.nz ? 1u : 0u) << o;
+    }
+    return N;
+}
+
+// A field on the folded neighbourhood: the value at offset index (a, b, c)
+// with the sign of its boundary rule (flip masks per axis).  Holds the
+// neighbourhood by value, so it stays in registers.
+struct Tap5 {
+    const double *u;
+    Nb5 N;
+    unsigned fx, fy, fz;
+    __device__ double operator()(int a, int b, int c) const
+    {
+        const double v = u[N.zo(c) + N.yo[b] + N.xo[a]];
+        return (((fx >> a) ^ (fy >> b) ^ (fz >> c)) & 1u) ? -v : v;
+    }
+};
+
+__device__ inline Tap5 tap5(const double *u, unsigned odd, const Nb5 &N)
+{
+    Tap5 t;
+    t.u = u;
+    t.N = N;
+    t.fx = ((odd & 1u) ? N.lx : 0u) | ((odd & 2u) ? N.hx : 0u);
+    t.fy = ((odd & 4u) ? N.ly : 0u) | ((odd & 8u) ? N.hy : 0u);
+    t.fz = ((odd & 16u) ? N.lz : 0u) | ((odd & 32u) ? N.hz : 0u);
+    return t;
+}
+
+// p_hs on the folded neighbourhood: +mirror on the sides, -mirror on top, and
+// below the bottom the mirror plus (2m + 1) g h rho of the mirrored cell (rho
+// +mirror on the sides).
+struct TapPhs5 {
+    const double *p, *rho;
+    Nb5 N;
+    double gh;
+    __device__ double operator()(int a, int b, int c) const
+    {
+        const unsigned idx = N.zo(c) + N.yo[b] + N.xo[a];
+        if ((N.lz >> c) & 1u) {
+            const int m = -1 - (N.k + c - 2);
+            return p[idx] + (double)(2 * m + 1) * gh * rho[idx];
         }
-        k = fold2(k, g.nz, kOddTop, 16u, 32u, s);
-        return s * p[at(g, i, j, k)];
+        const double v = p[idx];
+        return ((N.hz >> c) & 1u) ? -v : v;
     }
 };
 
@@ -671,8 +746,9 @@ struct TapMul {
 
 // The three derivative filters and the mass filter of one field at a cell:
 // d[0..2] = f(u; w_d), d[3] = f(u; w_m).
+// tap(a, b, c): the value at offset index (a, b, c), offsets a - 2 etc.
 template <typename T>
-__device__ inline void deriv_mass2(const Filt2 &F, const T &tap, int i, int j, int k, double d[4])
+__device__ inline void deriv_mass2(const Filt2 &F, const T &tap, double d[4])
 {
     double dx = 0.0, dy = 0.0, dz = 0.0, mm = 0.0;
 #pragma unroll 1
@@ -683,7 +759,7 @@ __device__ inline void deriv_mass2(const Filt2 &F, const T &tap, int i, int j, i
             double rG = 0.0, rM = 0.0;
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
-                const double v = tap(i + a - 2, j + b - 2, k + c - 2);
+                const double v = tap(a, b, c);
                 rG += F.G.w[a] * v;
                 rM += F.M.w[a] * v;
             }
@@ -691,10 +767,11 @@ __device__ inline void deriv_mass2(const Filt2 &F, const T &tap, int i, int j, i
             pMG += F.G.w[b] * rM;
             pMM += F.M.w[b] * rM;
         }
-        dx += F.M.w[c] * pGM;
-        dy += F.M.w[c] * pMG;
-        dz += F.G.w[c] * pMM;
-        mm += F.M.w[c] * pMM;
+        const double Mc = F.Mz(c);
+        dx += Mc * pGM;
+        dy += Mc * pMG;
+        dz += F.Gz(c) * pMM;
+        mm += Mc * pMM;
     }
     d[0] = dx;
     d[1] = dy;
@@ -704,7 +781,7 @@ __device__ inline void deriv_mass2(const Filt2 &F, const T &tap, int i, int j, i
 
 // f(u; w_lap) = f(u; K M M + M K M + M M K).
 template <typename T>
-__device__ inline double lap2(const Filt2 &F, const T &tap, int i, int j, int k)
+__device__ inline double lap2(const Filt2 &F, const T &tap)
 {
     double out = 0.0;
 #pragma unroll 1
@@ -715,7 +792,7 @@ __device__ inline double lap2(const Filt2 &F, const T &tap, int i, int j, int k)
             double rK = 0.0, rM = 0.0;
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
-                const double v = tap(i + a - 2, j + b - 2, k + c - 2);
+                const double v = tap(a, b, c);
                 rK += F.K.w[a] * v;
                 rM += F.M.w[a] * v;
             }
@@ -723,7 +800,7 @@ __device__ inline double lap2(const Filt2 &F, const T &tap, int i, int j, int k)
             pMK += F.K.w[b] * rM;
             pMM += F.M.w[b] * rM;
         }
-        out += F.M.w[c] * (pKM + pMK) + F.K.w[c] * pMM;
+        out += F.Mz(c) * (pKM + pMK) + F.Kz(c) * pMM;
     }
     return out;
 }
@@ -737,8 +814,9 @@ __global__ __launch_bounds__(256) void props2_kernel(Grid g, Phys P, const doubl
         const double c0 = C[id];
         rho[id] = P.rho_l * c0 + P.rho_g * (1.0 - c0);
         mu[id] = P.mu_l * c0 + P.mu_g * (1.0 - c0);
+        const Nb5 N = nb5(g, i, j, k);
         double d[4];
-        deriv_mass2(F, Tap2{C, kEven, g}, i, j, k, d);
+        deriv_mass2(F, tap5(C, kEven, N), d);
         double gd[3];
         for (int e = 0; e < 3; ++e) gd[e] = d[e] / F.ml;
         const double l = sqrt(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
@@ -755,10 +833,11 @@ __global__ __launch_bounds__(256) void surface2_kernel(Grid g, double sigma, C3 
 {
     cell_of(g, [&](size_t id, int i, int j, int k) {
         const Filt2 F(g.h);
+        const Nb5 N = nb5(g, i, j, k);
         double kap = 0.0;
         for (int e = 0; e < 3; ++e) {
             double d[4];
-            deriv_mass2(F, Tap2{nrm.p[e], rule_grad(e), g}, i, j, k, d);
+            deriv_mass2(F, tap5(nrm.p[e], rule_grad(e), N), d);
             kap += d[e];
         }
         kap /= F.ml;
@@ -772,9 +851,10 @@ __global__ __launch_bounds__(256) void advection2_kernel(Grid g, C3 q, F3 adv)
     cell_of(g, [&](size_t id, int i, int j, int k) {
         const Filt2 F(g.h);
         const double q0[3] = {q.p[0][id], q.p[1][id], q.p[2][id]};
+        const Nb5 N = nb5(g, i, j, k);
         for (int c = 0; c < 3; ++c) {
             double d[4];
-            deriv_mass2(F, Tap2{q.p[c], rule_vel(c), g}, i, j, k, d);
+            deriv_mass2(F, tap5(q.p[c], rule_vel(c), N), d);
             adv.p[c][id] = q0[0] * (d[0] / F.ml) + q0[1] * (d[1] / F.ml) + q0[2] * (d[2] / F.ml);
         }
     });
@@ -789,11 +869,12 @@ __global__ __launch_bounds__(256) void pg_velocity2_kernel(Grid g, C3 q, C3 adv,
         const Filt2 F(g.h);
         const double eps_k = 1e-7, a_kabs = 1.0 / 16.0, a_ksq = 4.0, h = g.h;
         const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
+        const Nb5 N = nb5(g, i, j, k);
         for (int c = 0; c < 3; ++c) {
             double d[4], am[4];
-            deriv_mass2(F, Tap2{q.p[c], rule_vel(c), g}, i, j, k, d);
+            deriv_mass2(F, tap5(q.p[c], rule_vel(c), N), d);
             const double px = d[0] / F.ml, py = d[1] / F.ml, pz = d[2] / F.ml;
-            deriv_mass2(F, Tap2{adv.p[c], kEven, g}, i, j, k, am);
+            deriv_mass2(F, tap5(adv.p[c], kEven, N), am);
             const double a = 2.0 * (am[3] / F.ml - adv.p[c][id]);
             const double G = fabs(px) + fabs(py) + fabs(pz);
             const double kabs = a_kabs * h * fabs(a) / (eps_k + G / 3.0);
@@ -817,21 +898,21 @@ __global__ __launch_bounds__(256) void momentum2_kernel(Grid g, Phys P, C3 qn, c
     cell_of(g, [&](size_t id, int i, int j, int k) {
         const Filt2 F(g.h);
         const double r0 = rho[id];
+        const Nb5 N = nb5(g, i, j, k);
         double ghs[4], gnh[4], rm[4];
-        deriv_mass2(F, TapPhs2{p_hs, rho, g, P.g * g.h}, i, j, k, ghs);
-        deriv_mass2(F, Tap2{p_nh, kOddTop, g}, i, j, k, gnh);
-        deriv_mass2(F, Tap2{rho, kEven, g}, i, j, k, rm);
+        deriv_mass2(F, TapPhs5{p_hs, rho, N, P.g * g.h}, ghs);
+        deriv_mass2(F, tap5(p_nh, kOddTop, N), gnh);
+        deriv_mass2(F, tap5(rho, kEven, N), rm);
         const double buoy = -P.g * rm[3];  // f(-g rho; w_m)
         for (int c = 0; c < 3; ++c) {
-            const Tap2 tq{qh.p[c], rule_vel(c), g}, tk{kq.p[c], kEven, g};
+            const Tap5 tq = tap5(qh.p[c], rule_vel(c), N), tk = tap5(kq.p[c], kEven, N);
             const double q0 = qh.p[c][id], k0 = kq.p[c][id];
             // Eq. k-T: 1/2 [f(k q; w) + k f(q; w) - q f(k; w)]
-            double s = 0.5 * (lap2(F, TapMul<Tap2, Tap2>{tk, tq}, i, j, k) + k0 * lap2(F, tq, i, j, k) -
-                              q0 * lap2(F, tk, i, j, k));
+            double s = 0.5 * (lap2(F, TapMul<Tap5, Tap5>{tk, tq}) + k0 * lap2(F, tq) - q0 * lap2(F, tk));
             s += ghs[c];
             s += gnh[c];
             double t4[4];
-            deriv_mass2(F, Tap2{st.p[c], rule_grad(c), g}, i, j, k, t4);
+            deriv_mass2(F, tap5(st.p[c], rule_grad(c), N), t4);
             s += t4[3];
             if (c == 2) s -= buoy;
             s += r0 * F.ml * adv.p[c][id];
@@ -854,7 +935,10 @@ __global__ __launch_bounds__(256) void pg_volume_fraction2_kernel(Grid g, double
         const double Kp = 300.0, Km = 300.0, beta = 0.1, eps_x = 1e-4, Kpos = 3.0, eps_k = 1e-7, h = g.h;
         const double kmin = 1e-4 / dt * h * h, kclamp = 0.05 / dt * h * h;
         double am[4];
-        deriv_mass2(F, Tap2{advc, kEven, g}, i, j, k, am);
+        {
+            const Nb5 N = nb5(g, i, j, k);
+            deriv_mass2(F, tap5(advc, kEven, N), am);
+        }
         const double a = 2.0 * (am[3] / F.ml - advc[id]);
         const Tap2 tc{C, kEven, g};
         const double c0 = C[id];
@@ -1015,6 +1099,8 @@ int nn4mg_step_create(int nx, int ny, int nz, double h, const nn4mg_step_params 
     int rc = check_params(p);
     if (rc) return rc;
     if (nx < 4 || ny < 4 || nz < 4) return set_error(NN4MG_EINVAL, "grid dims must be >= 4");
+    // the quadratic filters index a cell's neighbourhood with 32-bit offsets
+    if ((double)nx * ny * nz >= 2147483648.0) return set_error(NN4MG_EINVAL, "grid must have fewer than 2^31 cells");
     if (!(h > 0.0)) return set_error(NN4MG_EINVAL, "h must be > 0");
     // pressure: zero-normal-derivative walls, zero pressure on the top outlet
     nn4mg_config cfg;
