@@ -5,12 +5,13 @@
 // weighted-Jacobi sweeps.  On the coarse levels the z-marching two-sweep kernel
 // takes about as long as its chain of plane steps (loads, LDS commits and
 // barriers, one plane after another), whatever the level size.  Here each
-// workgroup owns one 8^3 output block and stages everything it needs at once:
-//   * the coarse correction under the block (8^3 coarse cells, halos by the
-//     boundary rules) and, for a nodal coefficient, k on the block plus a
-//     two-cell ring (12^3), in one round of global loads;
-//   * P e on the 12^3 region, cell-centred trilinear from the staged coarse cells;
-//   * the first sweep on the block plus a one-cell ring (10^3);
+// workgroup owns one E^3 output block (E = 8; 4 on levels with too few 8^3
+// blocks to fill the chip) and stages everything it needs at once:
+//   * the coarse correction under the block ((E/2 + 4)^3 coarse cells, halos
+//     by the boundary rules) and, for a nodal coefficient, k on the block plus
+//     a two-cell ring ((E + 4)^3), in one round of global loads;
+//   * P e on the (E + 4)^3 region, cell-centred trilinear from the staged coarse cells;
+//   * the first sweep on the block plus a one-cell ring ((E + 2)^3);
 //   * the second sweep on the block, written out.
 // Ring cells outside the grid are computed from halo-synthesised inputs like
 // any other cell: the sweep commutes with the boundary reflections, so they
@@ -26,15 +27,6 @@
 namespace nn4mg {
 
 namespace {
-
-constexpr int BE = 8;                              // output block edge
-constexpr int BT = BE * BE * BE;                   // threads: one output cell each
-constexpr int PE = BE + 4, PN = PE * PE * PE;      // staged input region (two-cell ring)
-constexpr int QE = BE + 2, QN = QE * QE * QE;      // first-sweep region (one-cell ring)
-constexpr int CE = BE / 2 + 4, CN = CE * CE * CE;  // coarse footprint
-constexpr int NP = (PN + BT - 1) / BT;
-constexpr int NQ = (QN + BT - 1) / BT;
-static_assert(CN == BT, "one coarse cell per thread");
 
 // Corner and cross sums of the 3x3 neighbourhood of o in a plane with row stride W.
 template <typename T, int W>
@@ -87,9 +79,27 @@ __device__ __forceinline__ T jacobi_at(const T *v, int c, const T *k, int ck, T 
     }
 }
 
-template <typename T, typename KT, int OUT>
-__global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a_)
+// Shape of a single-level block pass: output block edge E (8, or 4 for levels
+// with too few 8^3 blocks to fill the chip), NT threads.  Every output cell's
+// arithmetic is the same whatever E, so both edges give identical results.
+template <int E>
+struct BlockShape {
+    static constexpr int NT = E == 8 ? 512 : 256;
+    static constexpr int PE = E + 4, PN = PE * PE * PE;      // staged input region (two-cell ring)
+    static constexpr int QE = E + 2, QN = QE * QE * QE;      // first-sweep region (one-cell ring)
+    static constexpr int CE = E / 2 + 4, CN = CE * CE * CE;  // coarse footprint
+    static constexpr int ON = E * E * E;                     // output cells
+    static constexpr int NP = (PN + NT - 1) / NT;
+    static constexpr int NQ = (QN + NT - 1) / NT;
+    static_assert(CN <= NT && ON <= NT, "one coarse cell and at most one output cell per thread");
+};
+
+template <typename T, typename KT, int OUT, int E>
+__global__ __launch_bounds__(BlockShape<E>::NT) void sweep2_block_kernel(const StencilArgs a_)
 {
+    using S = BlockShape<E>;
+    constexpr int NT = S::NT, PE = S::PE, PN = S::PN, QE = S::QE, QN = S::QN, CE = S::CE, CN = S::CN;
+    constexpr int NP = S::NP, NQ = S::NQ;
     StencilArgs a = a_;
     const int lb = enter_copy(a, xcd_remap(blockIdx.x, gridDim.x));
     constexpr bool HK = HasK<KT>::value;
@@ -102,10 +112,10 @@ __global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a_)
     // the stopping flag is read with the first loads and tested before any write
     const int stop = a.done ? *a.done : 0;
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const int bxn = (nx + BE - 1) / BE, byn = (ny + BE - 1) / BE;
+    const int bxn = (nx + E - 1) / E, byn = (ny + E - 1) / E;
     const int bx = lb % bxn, rest = lb / bxn;
     const int by = rest % byn, bz = rest / byn;
-    const int i0 = bx * BE, j0 = by * BE, k0 = bz * BE;
+    const int i0 = bx * E, j0 = by * E, k0 = bz * E;
     const int t = threadIdx.x;
 
     const T h = (T)a.h, om = (T)a.omega;
@@ -119,7 +129,8 @@ __global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a_)
     // one round of global loads: coarse footprint, coefficient, right-hand sides
     T cval;
     {
-        const int cx = t % CE, cy = (t / CE) % CE, cz = t / (CE * CE);
+        const int ct = min(t, CN - 1);
+        const int cx = ct % CE, cy = (ct / CE) % CE, cz = ct / (CE * CE);
         int s = 1;
         const int fI = fold((i0 >> 1) - 2 + cx, a.cnx, a.g.bc[0], a.g.bc[1], s);
         const int fJ = fold((j0 >> 1) - 2 + cy, a.cny, a.g.bc[2], a.g.bc[3], s);
@@ -131,7 +142,7 @@ __global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a_)
     if constexpr (HK) {
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            const int idx = min(q * BT + t, PN - 1);
+            const int idx = min(q * NT + t, PN - 1);
             const int px = idx % PE, py = (idx / PE) % PE, pz = idx / (PE * PE);
             int s = 1;
             const int fi = fold(i0 + px - 2, nx, a.g.bc[0], a.g.bc[1], s);
@@ -143,7 +154,7 @@ __global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a_)
     T bq[NQ];  // first-sweep right-hand side, signed by the halo rule
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int idx = min(q * BT + t, QN - 1);
+        const int idx = min(q * NT + t, QN - 1);
         const int qx = idx % QE, qy = (idx / QE) % QE, qz = idx / (QE * QE);
         int s = 1;
         const int fi = fold(i0 + qx - 1, nx, a.g.bc[0], a.g.bc[1], s);
@@ -152,27 +163,29 @@ __global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a_)
         const T v = bp[(size_t)fi + (size_t)nx * ((size_t)fj + (size_t)ny * (size_t)fk)];
         bq[q] = s < 0 ? -v : v;
     }
-    const int ox = t % BE, oy = (t / BE) % BE, oz = t / (BE * BE);
+    // this thread's output cell (threads beyond the block's cells only stage)
+    const int ot = min(t, S::ON - 1);
+    const int ox = ot % E, oy = (ot / E) % E, oz = ot / (E * E);
     const int gi = i0 + ox, gj = j0 + oy, gk = k0 + oz;
-    const bool valid = gi < nx && gj < ny && gk < nz;
+    const bool valid = t < S::ON && gi < nx && gj < ny && gk < nz;
     const size_t g = (size_t)min(gi, nx - 1) + (size_t)nx * ((size_t)min(gj, ny - 1) + (size_t)ny * (size_t)min(gk, nz - 1));
     const T b2 = bp[g];
     double xo = 0.0;
     if constexpr (ADD) xo = a.x64[g];
     if (stop) return;  // uniform over the workgroup
 
-    sc[t] = cval;
+    if (t < CN) sc[t] = cval;
     if constexpr (HK) {
 #pragma unroll
         for (int q = 0; q < NP; ++q)
-            if (q * BT + t < PN) sk[q * BT + t] = kconv<T, KT>(kr[q]);
+            if (q * NT + t < PN) sk[q * NT + t] = kconv<T, KT>(kr[q]);
     }
     __syncthreads();
 
     // P e on the staged region: z first, then the x-y bilinear weights
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-        const int idx = q * BT + t;
+        const int idx = q * NT + t;
         if (idx < PN) {
             const int px = idx % PE, py = (idx / PE) % PE, pz = idx / (PE * PE);
             const int ui = i0 + px - 2, uj = j0 + py - 2, uk = k0 + pz - 2;  // unfolded fine position
@@ -193,7 +206,7 @@ __global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a_)
     // first sweep on the block plus its one-cell ring
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int idx = q * BT + t;
+        const int idx = q * NT + t;
         if (idx < QN) {
             const int qx = idx % QE, qy = (idx / QE) % QE, qz = idx / (QE * QE);
             const int c = (qz + 1) * PE * PE + (qy + 1) * PE + (qx + 1);
@@ -203,10 +216,10 @@ __global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a_)
     __syncthreads();
 
     // second sweep on the block
-    const int cyy = (oz + 1) * QE * QE + (oy + 1) * QE + (ox + 1);
-    const int ckk = (oz + 2) * PE * PE + (oy + 2) * PE + (ox + 2);
-    const T y = jacobi_at<T, HK, QE, QE * QE, PE, PE * PE>(sy, cyy, sk, ckk, b2, cw, om_w0, om, icv);
     if (valid) {
+        const int cyy = (oz + 1) * QE * QE + (oy + 1) * QE + (ox + 1);
+        const int ckk = (oz + 2) * PE * PE + (oy + 2) * PE + (ox + 2);
+        const T y = jacobi_at<T, HK, QE, QE * QE, PE, PE * PE>(sy, cyy, sk, ckk, b2, cw, om_w0, om, icv);
         if constexpr (ADD)
             a.x64[g] = xo + (double)y;
         else
@@ -214,12 +227,24 @@ __global__ __launch_bounds__(BT) void sweep2_block_kernel(const StencilArgs a_)
     }
 }
 
+// Launches with fewer 8^3 blocks than this (over all copies) use 4^3 blocks:
+// a block pass is bound by its workgroup's LDS reads, so a level that leaves
+// most compute units idle runs faster as more, smaller blocks.
+constexpr int kSmallBlockBelow = 256;
+
 template <typename T, typename KT, int OUT>
 hipError_t goB(const StencilArgs &a_, hipStream_t s)
 {
     StencilArgs a = a_;
-    const unsigned grid = batched_grid(a, block2_blocks(a.g.nx, a.g.ny, a.g.nz));
-    hipLaunchKernelGGL((sweep2_block_kernel<T, KT, OUT>), dim3(grid), dim3(BT), 0, s, a);
+    const int nb8 = block2_blocks(a.g.nx, a.g.ny, a.g.nz);
+    if ((long long)nb8 * (a.ncopy > 1 ? a.ncopy : 1) < kSmallBlockBelow) {
+        const int nb4 = ((a.g.nx + 3) / 4) * ((a.g.ny + 3) / 4) * ((a.g.nz + 3) / 4);
+        const unsigned grid = batched_grid(a, nb4);
+        hipLaunchKernelGGL((sweep2_block_kernel<T, KT, OUT, 4>), dim3(grid), dim3(BlockShape<4>::NT), 0, s, a);
+    } else {
+        const unsigned grid = batched_grid(a, nb8);
+        hipLaunchKernelGGL((sweep2_block_kernel<T, KT, OUT, 8>), dim3(grid), dim3(BlockShape<8>::NT), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -227,7 +252,7 @@ hipError_t goB(const StencilArgs &a_, hipStream_t s)
 
 int block2_blocks(int nx, int ny, int nz)
 {
-    return ((nx + BE - 1) / BE) * ((ny + BE - 1) / BE) * ((nz + BE - 1) / BE);
+    return ((nx + 7) / 8) * ((ny + 7) / 8) * ((nz + 7) / 8);
 }
 
 hipError_t launch_sweep2_block(int T_is_f64, int kt, int out_mode, const StencilArgs &a, hipStream_t s)
