@@ -67,7 +67,6 @@ __device__ __forceinline__ T kval(const KT *k, int g)
 struct Lv {
     int nx, ny, nz, n;
     int px, pxy, pn;   // padded row, plane and cell counts
-    double rpx, rpxy;  // their reciprocals
     double h;
     int ob, oya, oyb, ok;
 };
@@ -86,10 +85,14 @@ __device__ __forceinline__ void padded_cells(const Lv &V, const int *bc, PCell (
     for (int r = 0; r < 2; ++r) {
         const int p = (int)threadIdx.x + r * TT;
         if (p < V.pn) {
-            // p / px and p / pxy through a double reciprocal: exact for these small indices
-            const int pk = (int)(((double)p + 0.5) * V.rpxy);
+            // p / pxy and rem / px through FP32 reciprocals: (p + 0.5) / pxy lies at
+            // least 0.5 / pxy from an integer, far above the rounding error while
+            // pn < 2^21 (here pn <= 2 * 1024); FP32 keeps this off the slower FP64
+            // conversions, which cost the most in this one-workgroup kernel
+            const float rpxy = __builtin_amdgcn_rcpf((float)V.pxy), rpx = __builtin_amdgcn_rcpf((float)V.px);
+            const int pk = (int)(((float)p + 0.5f) * rpxy);
             const int rem = p - pk * V.pxy;
-            const int pj = (int)(((double)rem + 0.5) * V.rpx);
+            const int pj = (int)(((float)rem + 0.5f) * rpx);
             const int pi = rem - pj * V.px;
             int sg = 1;
             const int i = tfold(pi - 1, V.nx, bc[0], bc[1], sg);
@@ -104,8 +107,11 @@ __device__ __forceinline__ void padded_cells(const Lv &V, const int *bc, PCell (
 
 __device__ __forceinline__ int padded_of(const Lv &V, int c)
 {
-    const int i = c % V.nx, t = c / V.nx;
-    const int j = t % V.ny, k = t / V.ny;
+    // c / nx and t / ny through FP32 reciprocals, exact for these indices (as in padded_cells)
+    const int t = (int)(((float)c + 0.5f) * __builtin_amdgcn_rcpf((float)V.nx));
+    const int i = c - t * V.nx;
+    const int k = (int)(((float)t + 0.5f) * __builtin_amdgcn_rcpf((float)V.ny));
+    const int j = t - k * V.ny;
     return (k + 1) * V.pxy + (j + 1) * V.px + (i + 1);
 }
 
@@ -263,8 +269,6 @@ __global__ __launch_bounds__(TT) void tail_kernel(const TailArgs a)
                 lv[l].px = a.nx[l] + 2;
                 lv[l].pxy = (a.nx[l] + 2) * (a.ny[l] + 2);
                 lv[l].pn = pn;
-                lv[l].rpx = 1.0 / (double)(a.nx[l] + 2);
-                lv[l].rpxy = 1.0 / (double)((a.nx[l] + 2) * (a.ny[l] + 2));
                 lv[l].h = a.h[l];
                 lv[l].ob = off;
                 lv[l].oya = off + n;
