@@ -585,40 +585,18 @@ __global__ __launch_bounds__(256) void copy3_kernel(size_t n, C3 src, F3 dst)
 // (2m + 1) g h rho (the gradient -rho g extrapolated over (2m + 1) h).  They
 // serve the momentum terms, the interface geometry and the volume-fraction
 // advection (Table disc_combinations, "linear/quadratic"); the volume-fraction
-// diffusion and the two pressure equations keep the linear filters.  Each
-// kernel sums its 125 taps straight from global memory (L1/L2 carry the
-// re-reads), rows first, so no neighbourhood is held in registers; the folded
-// indices of the cell's 5 x 5 x 5 neighbourhood and the faces each offset
-// crosses are worked out once per cell (Nb5) and shared by every field, whose
-// boundary rule then only picks which crossings flip the sign.
+// diffusion and the two pressure equations keep the linear filters.
+//
+// Each kernel runs one workgroup per 8^3 block of cells.  A filter factors
+// into three 5-tap passes, along x, then y, then z, so the block stages a
+// field once on its cells plus the two-cell halo (12^3, the field's boundary
+// rule applied while staging) and runs the passes through LDS: about 5 fused
+// multiply-adds per tap and output instead of 15, and one global load per
+// staged cell instead of one per tap.  Every sum keeps the x-then-y-then-z
+// order with the same weights.
 
 struct V5 {
     double w[5];
-};
-
-__constant__ double kQuadM[5] = {-1.0, 4.0, 24.0, 4.0, -1.0};
-__constant__ double kQuadG[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
-__constant__ double kQuadK[5] = {1.0, -16.0, 30.0, -16.0, 1.0};
-
-// Weights of the three 1D filters; Mz / Gz / Kz give the weight of a runtime
-// offset (the filters' outer z loop) from the constant tables with the same
-// arithmetic, so no weight array is indexed at run time.
-struct Filt2 {
-    V5 M, G, K;
-    double ml, h;
-    __device__ explicit Filt2(double h_) : h(h_)
-    {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            M.w[q] = h * kQuadM[q] / 30.0;
-            G.w[q] = kQuadG[q] / 12.0;
-            K.w[q] = kQuadK[q] / (12.0 * h);
-        }
-        ml = h * h * h;
-    }
-    __device__ double Mz(int c) const { return h * kQuadM[c] / 30.0; }
-    __device__ double Gz(int c) const { return kQuadG[c] / 12.0; }
-    __device__ double Kz(int c) const { return kQuadK[c] / (12.0 * h); }
 };
 
 // Index up to two cells outside folded onto the cell it mirrors; s flips on a
@@ -652,126 +630,179 @@ struct Tap2 {
 };
 
 
-// The folded neighbourhood of one cell: for offsets o = -2 .. 2 (index o + 2)
-// along x and y, the folded index (times the axis stride); along z (the
-// filters' outer loop, not unrolled) the fold is redone per plane.  Bit o + 2
-// of l* / h* marks an offset that crossed the low / high face.
-struct Nb5 {
-    unsigned xo[5], yo[5];
-    unsigned lx, hx, ly, hy, lz, hz;
-    int k, nz;    // the cell's own z index and the grid's depth
-    unsigned sz;  // z stride
-    __device__ unsigned zo(int c) const
-    {
-        double s = 1.0;
-        return sz * (unsigned)fold2(k + c - 2, nz, 0u, 16u, 32u, s);
-    }
-};
+constexpr int QB = 8;                 // output block edge
+constexpr int QT = QB * QB * QB;      // threads: one output cell each
+constexpr int QS = QB + 4;            // staged edge
+constexpr int QSN = QS * QS * QS;     // staged cells
+constexpr int QRN = QB * QS * QS;     // x-pass outputs per filter (8 x 12 x 12)
+constexpr int QPN = QB * QB * QS;     // y-pass outputs per filter (8 x 8 x 12)
 
-__device__ inline Nb5 nb5(const Grid &g, int i, int j, int k)
+// The 1D weights of the quadratic filters and the mass of a cell, computed on
+// the host and passed by value so they stay in scalar registers.
+struct QW {
+    V5 M, G, K;
+    double ml;
+};
+QW quad_weights(double h)
 {
-    Nb5 N;
-    N.lx = N.hx = N.ly = N.hy = N.lz = N.hz = 0u;
-    N.k = k;
-    N.nz = g.nz;
-    const unsigned sy = (unsigned)g.nx;
-    N.sz = (unsigned)g.nx * (unsigned)g.ny;
-#pragma unroll
-    for (int o = 0; o < 5; ++o) {
-        double s = 1.0;
-        const int ii = i + o - 2, jj = j + o - 2, kk = k + o - 2;
-        N.xo[o] = (unsigned)fold2(ii, g.nx, 0u, 1u, 2u, s);
-        N.yo[o] = sy * (unsigned)fold2(jj, g.ny, 0u, 4u, 8u, s);
-        N.lx |= (ii < 0 ? 1u : 0u) << o;
-        N.hx |= (ii >= g.nx ? 1u : 0u) << o;
-        N.ly |= (jj < 0 ? 1u : 0u) << o;
-        N.hy |= (jj >= g.ny ? 1u : 0u) << o;
-        N.lz |= (kk < 0 ? 1u : 0u) << o;
-        N.hz |= (kk >= g.nz ? 1u : 0u) << o;
+    const double m[5] = {-1.0, 4.0, 24.0, 4.0, -1.0}, gw[5] = {1.0, -8.0, 0.0, 8.0, -1.0},
+                 kw[5] = {1.0, -16.0, 30.0, -16.0, 1.0};
+    QW w;
+    for (int q = 0; q < 5; ++q) {
+        w.M.w[q] = h * m[q] / 30.0;
+        w.G.w[q] = gw[q] / 12.0;
+        w.K.w[q] = kw[q] / (12.0 * h);
     }
-    return N;
+    w.ml = h * h * h;
+    return w;
 }
 
-// A field on the folded neighbourhood: the value at offset index (a, b, c)
-// with the sign of its boundary rule (flip masks per axis).  Holds the
-// neighbourhood by value, so it stays in registers.
-struct Tap5 {
+struct QLds {
+    double s[QSN];    // the staged field
+    double r[2][QRN]; // x pass: the derivative (or K) filter and M
+    double p[3][QPN]; // y pass: M on r[0], the derivative (or K) filter on r[1], M on r[1]
+};
+
+// Index up to two cells outside folded as fold2; indices further out (the
+// halo of a ragged block's cells beyond the grid, which feed no output) are
+// clamped into range.
+__device__ inline int qfold(int i, int n, unsigned odd, unsigned lo_bit, unsigned hi_bit, double &s)
+{
+    const int f = fold2(i, n, odd, lo_bit, hi_bit, s);
+    return min(max(f, 0), n - 1);
+}
+
+// A field at unfolded (i, j, k) with the two-cell halo of rule odd.
+struct QTap {
     const double *u;
-    Nb5 N;
-    unsigned fx, fy, fz;
-    __device__ double operator()(int a, int b, int c) const
+    unsigned odd;
+    Grid g;
+    __device__ double operator()(int i, int j, int k) const
     {
-        const double v = u[N.zo(c) + N.yo[b] + N.xo[a]];
-        return (((fx >> a) ^ (fy >> b) ^ (fz >> c)) & 1u) ? -v : v;
+        double s = 1.0;
+        const int fi = qfold(i, g.nx, odd, 1u, 2u, s);
+        const int fj = qfold(j, g.ny, odd, 4u, 8u, s);
+        const int fk = qfold(k, g.nz, odd, 16u, 32u, s);
+        const double v = u[at(g, fi, fj, fk)];
+        return s < 0.0 ? -v : v;
     }
 };
 
-__device__ inline Tap5 tap5(const double *u, unsigned odd, const Nb5 &N)
-{
-    Tap5 t;
-    t.u = u;
-    t.N = N;
-    t.fx = ((odd & 1u) ? N.lx : 0u) | ((odd & 2u) ? N.hx : 0u);
-    t.fy = ((odd & 4u) ? N.ly : 0u) | ((odd & 8u) ? N.hy : 0u);
-    t.fz = ((odd & 16u) ? N.lz : 0u) | ((odd & 32u) ? N.hz : 0u);
-    return t;
-}
-
-// p_hs on the folded neighbourhood: +mirror on the sides, -mirror on top, and
-// below the bottom the mirror plus (2m + 1) g h rho of the mirrored cell (rho
-// +mirror on the sides).
-struct TapPhs5 {
+// p_hs at unfolded (i, j, k): +mirror on the sides, -mirror on top, and below
+// the bottom the mirror plus (2m + 1) g h rho of the mirrored cell (rho +mirror
+// on the sides).
+struct QPhs {
     const double *p, *rho;
-    Nb5 N;
+    Grid g;
     double gh;
-    __device__ double operator()(int a, int b, int c) const
+    __device__ double operator()(int i, int j, int k) const
     {
-        const unsigned idx = N.zo(c) + N.yo[b] + N.xo[a];
-        if ((N.lz >> c) & 1u) {
-            const int m = -1 - (N.k + c - 2);
+        double s = 1.0;
+        const int fi = qfold(i, g.nx, 0u, 1u, 2u, s);
+        const int fj = qfold(j, g.ny, 0u, 4u, 8u, s);
+        const int fk = qfold(k, g.nz, 0u, 16u, 32u, s);
+        const size_t idx = at(g, fi, fj, fk);
+        if (k < 0) {
+            const int m = -1 - k;
             return p[idx] + (double)(2 * m + 1) * gh * rho[idx];
         }
         const double v = p[idx];
-        return ((N.hz >> c) & 1u) ? -v : v;
+        return k >= g.nz ? -v : v;
     }
 };
 
-// Product of two padded fields (the halo of k q is the product of the halos).
 template <typename A, typename B>
-struct TapMul {
+struct QMul {
     A a;
     B b;
     __device__ double operator()(int i, int j, int k) const { return a(i, j, k) * b(i, j, k); }
 };
 
-// The three derivative filters and the mass filter of one field at a cell:
-// d[0..2] = f(u; w_d), d[3] = f(u; w_m).
-// tap(a, b, c): the value at offset index (a, b, c), offsets a - 2 etc.
-template <typename T>
-__device__ inline void deriv_mass2(const Filt2 &F, const T &tap, double d[4])
+// Stage field v on the block at (i0, j0, k0) plus its two-cell halo.
+template <typename V>
+__device__ inline void qstage(QLds &L, const V &v, int i0, int j0, int k0)
 {
-    double dx = 0.0, dy = 0.0, dz = 0.0, mm = 0.0;
-#pragma unroll 1
-    for (int c = 0; c < 5; ++c) {
-        double pGM = 0.0, pMG = 0.0, pMM = 0.0;
+    const int t = threadIdx.x;
 #pragma unroll
-        for (int b = 0; b < 5; ++b) {
-            double rG = 0.0, rM = 0.0;
+    for (int r = 0; r < (QSN + QT - 1) / QT; ++r) {
+        const int idx = t + r * QT;
+        if (idx < QSN) {
+            const int x = idx % QS, y = (idx / QS) % QS, z = idx / (QS * QS);
+            L.s[idx] = v(i0 + x - 2, j0 + y - 2, k0 + z - 2);
+        }
+    }
+}
+
+// The x and y passes of the staged field: wa is G (derivatives) or K
+// (Laplacian); DER: also the passes only the derivatives or the Laplacian
+// need (else the mass filter alone).  Barrier before each pass.
+template <bool DER>
+__device__ inline void qpasses(QLds &L, const V5 &wa, const V5 &wm)
+{
+    const int t = threadIdx.x;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < (QRN + QT - 1) / QT; ++r) {
+        const int idx = t + r * QT;
+        if (idx < QRN) {
+            const int x = idx % QB, yz = idx / QB;  // y + QS z
+            const double *row = L.s + x + QS * yz;
+            double ra = 0.0, rm = 0.0;
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
-                const double v = tap(a, b, c);
-                rG += F.G.w[a] * v;
-                rM += F.M.w[a] * v;
+                const double v = row[a];
+                if (DER) ra += wa.w[a] * v;
+                rm += wm.w[a] * v;
             }
-            pGM += F.M.w[b] * rG;
-            pMG += F.G.w[b] * rM;
-            pMM += F.M.w[b] * rM;
+            if (DER) L.r[0][idx] = ra;
+            L.r[1][idx] = rm;
         }
-        const double Mc = F.Mz(c);
-        dx += Mc * pGM;
-        dy += Mc * pMG;
-        dz += F.Gz(c) * pMM;
-        mm += Mc * pMM;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < (QPN + QT - 1) / QT; ++r) {
+        const int idx = t + r * QT;
+        if (idx < QPN) {
+            const int x = idx % QB, y = (idx / QB) % QB, z = idx / (QB * QB);
+            const int o = x + QB * (y + QS * z);
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                if (DER) {
+                    p0 += wm.w[b] * L.r[0][o + QB * b];
+                    p1 += wa.w[b] * L.r[1][o + QB * b];
+                }
+                p2 += wm.w[b] * L.r[1][o + QB * b];
+            }
+            if (DER) {
+                L.p[0][idx] = p0;
+                L.p[1][idx] = p1;
+            }
+            L.p[2][idx] = p2;
+        }
+    }
+    __syncthreads();
+}
+
+// The derivative filters d[0..2] = f(u; w_x, w_y, w_z) (DER) and the mass
+// filter d[3] = f(u; w_m) of the staged field at this thread's cell.
+template <bool DER>
+__device__ inline void qderiv(QLds &L, const QW &F, double d[4])
+{
+    qpasses<DER>(L, F.G, F.M);
+    const int t = threadIdx.x;
+    const int o = (t % QB) + QB * ((t / QB) % QB + QB * (t / (QB * QB)));  // z-plane stride QB * QB
+    double dx = 0.0, dy = 0.0, dz = 0.0, mm = 0.0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const int q = o + QB * QB * c;
+        const double Mc = F.M.w[c];
+        if (DER) {
+            dx += Mc * L.p[0][q];
+            dy += Mc * L.p[1][q];
+            dz += F.G.w[c] * L.p[2][q];
+        }
+        mm += Mc * L.p[2][q];
     }
     d[0] = dx;
     d[1] = dy;
@@ -779,195 +810,224 @@ __device__ inline void deriv_mass2(const Filt2 &F, const T &tap, double d[4])
     d[3] = mm;
 }
 
-// f(u; w_lap) = f(u; K M M + M K M + M M K).
-template <typename T>
-__device__ inline double lap2(const Filt2 &F, const T &tap)
+// f(u; w_lap) = f(u; K M M + M K M + M M K) of the staged field at this thread's cell.
+__device__ inline double qlap(QLds &L, const QW &F)
 {
+    qpasses<true>(L, F.K, F.M);
+    const int t = threadIdx.x;
+    const int o = (t % QB) + QB * ((t / QB) % QB + QB * (t / (QB * QB)));
     double out = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int c = 0; c < 5; ++c) {
-        double pKM = 0.0, pMK = 0.0, pMM = 0.0;
-#pragma unroll
-        for (int b = 0; b < 5; ++b) {
-            double rK = 0.0, rM = 0.0;
-#pragma unroll
-            for (int a = 0; a < 5; ++a) {
-                const double v = tap(a, b, c);
-                rK += F.K.w[a] * v;
-                rM += F.M.w[a] * v;
-            }
-            pKM += F.M.w[b] * rK;
-            pMK += F.K.w[b] * rM;
-            pMM += F.M.w[b] * rM;
-        }
-        out += F.Mz(c) * (pKM + pMK) + F.Kz(c) * pMM;
+        const int q = o + QB * QB * c;
+        out += F.M.w[c] * (L.p[0][q] + L.p[1][q]) + F.K.w[c] * L.p[2][q];
     }
     return out;
 }
 
-// rho, mu, grad C in derivative units and the unit normals, quadratic filters.
-__global__ __launch_bounds__(256) void props2_kernel(Grid g, Phys P, const double *C, double *rho, double *mu, F3 Cd,
-                                                     F3 nrm)
+// This thread's cell of the workgroup's 8^3 block (the block at (i0, j0, k0));
+// a ragged block's threads beyond the grid read their cell clamped into it
+// and write nothing.
+struct QCell {
+    int i0, j0, k0, i, j, k;
+    bool valid;
+    size_t id;
+};
+__device__ inline QCell qcell(const Grid &g)
 {
-    cell_of(g, [&](size_t id, int i, int j, int k) {
-        const Filt2 F(g.h);
-        const double c0 = C[id];
-        rho[id] = P.rho_l * c0 + P.rho_g * (1.0 - c0);
-        mu[id] = P.mu_l * c0 + P.mu_g * (1.0 - c0);
-        const Nb5 N = nb5(g, i, j, k);
-        double d[4];
-        deriv_mass2(F, tap5(C, kEven, N), d);
-        double gd[3];
-        for (int e = 0; e < 3; ++e) gd[e] = d[e] / F.ml;
-        const double l = sqrt(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
-        const double eps = 1e-7 / g.h;
-        for (int e = 0; e < 3; ++e) {
-            Cd.p[e][id] = gd[e];
-            nrm.p[e][id] = gd[e] / (eps + l);
-        }
-    });
+    QCell c;
+    const int bxn = (g.nx + QB - 1) / QB, byn = (g.ny + QB - 1) / QB;
+    const int lb = blockIdx.x, t = threadIdx.x;
+    c.i0 = (lb % bxn) * QB;
+    c.j0 = ((lb / bxn) % byn) * QB;
+    c.k0 = (lb / bxn / byn) * QB;
+    const int i = c.i0 + t % QB, j = c.j0 + (t / QB) % QB, k = c.k0 + t / (QB * QB);
+    c.valid = i < g.nx && j < g.ny && k < g.nz;
+    c.i = min(i, g.nx - 1);
+    c.j = min(j, g.ny - 1);
+    c.k = min(k, g.nz - 1);
+    c.id = at(g, c.i, c.j, c.k);
+    return c;
+}
+
+// rho, mu, grad C in derivative units and the unit normals, quadratic filters.
+__global__ __launch_bounds__(QT) void props2_kernel(Grid g, Phys P, const QW F, const double *C, double *rho,
+                                                    double *mu, F3 Cd, F3 nrm)
+{
+    __shared__ QLds L;
+    const QCell X = qcell(g);
+    const size_t id = X.id;
+    double d[4];
+    qstage(L, QTap{C, kEven, g}, X.i0, X.j0, X.k0);
+    qderiv<true>(L, F, d);
+    if (!X.valid) return;
+    const double c0 = C[id];
+    rho[id] = P.rho_l * c0 + P.rho_g * (1.0 - c0);
+    mu[id] = P.mu_l * c0 + P.mu_g * (1.0 - c0);
+    double gd[3];
+    for (int e = 0; e < 3; ++e) gd[e] = d[e] / F.ml;
+    const double l = sqrt(gd[0] * gd[0] + gd[1] * gd[1] + gd[2] * gd[2]);
+    const double eps = 1e-7 / g.h;
+    for (int e = 0; e < 3; ++e) {
+        Cd.p[e][id] = gd[e];
+        nrm.p[e][id] = gd[e] / (eps + l);
+    }
 }
 
 // Curvature div n and the surface-tension vectors, quadratic filters.
-__global__ __launch_bounds__(256) void surface2_kernel(Grid g, double sigma, C3 nrm, C3 Cd, F3 st)
+__global__ __launch_bounds__(QT) void surface2_kernel(Grid g, const QW F, double sigma, C3 nrm, C3 Cd, F3 st)
 {
-    cell_of(g, [&](size_t id, int i, int j, int k) {
-        const Filt2 F(g.h);
-        const Nb5 N = nb5(g, i, j, k);
-        double kap = 0.0;
-        for (int e = 0; e < 3; ++e) {
-            double d[4];
-            deriv_mass2(F, tap5(nrm.p[e], rule_grad(e), N), d);
-            kap += d[e];
-        }
-        kap /= F.ml;
-        for (int e = 0; e < 3; ++e) st.p[e][id] = sigma * kap * Cd.p[e][id];
-    });
+    __shared__ QLds L;
+    const QCell X = qcell(g);
+    double kap = 0.0;
+    for (int e = 0; e < 3; ++e) {
+        double d[4];
+        qstage(L, QTap{nrm.p[e], rule_grad(e), g}, X.i0, X.j0, X.k0);
+        qderiv<true>(L, F, d);
+        kap += d[e];
+    }
+    kap /= F.ml;
+    if (!X.valid) return;
+    for (int e = 0; e < 3; ++e) st.p[e][X.id] = sigma * kap * Cd.p[e][X.id];
 }
 
 // adv_c = q . grad q_c, quadratic filters.
-__global__ __launch_bounds__(256) void advection2_kernel(Grid g, C3 q, F3 adv)
+__global__ __launch_bounds__(QT) void advection2_kernel(Grid g, const QW F, C3 q, F3 adv)
 {
-    cell_of(g, [&](size_t id, int i, int j, int k) {
-        const Filt2 F(g.h);
-        const double q0[3] = {q.p[0][id], q.p[1][id], q.p[2][id]};
-        const Nb5 N = nb5(g, i, j, k);
-        for (int c = 0; c < 3; ++c) {
-            double d[4];
-            deriv_mass2(F, tap5(q.p[c], rule_vel(c), N), d);
-            adv.p[c][id] = q0[0] * (d[0] / F.ml) + q0[1] * (d[1] / F.ml) + q0[2] * (d[2] / F.ml);
-        }
-    });
+    __shared__ QLds L;
+    const QCell X = qcell(g);
+    const size_t id = X.id;
+    const double q0[3] = {q.p[0][id], q.p[1][id], q.p[2][id]};
+    for (int c = 0; c < 3; ++c) {
+        double d[4];
+        qstage(L, QTap{q.p[c], rule_vel(c), g}, X.i0, X.j0, X.k0);
+        qderiv<true>(L, F, d);
+        if (X.valid) adv.p[c][id] = q0[0] * (d[0] / F.ml) + q0[1] * (d[1] / F.ml) + q0[2] * (d[2] / F.ml);
+    }
 }
 
 // Isotropic PG diffusivity of each component, quadratic filters (the residual
 // filter of Eq. a_psi is w_m / m_l - E with the quadratic mass).
-__global__ __launch_bounds__(256) void pg_velocity2_kernel(Grid g, C3 q, C3 adv, const double *rho,
-                                                           const double *mu, F3 kq)
+__global__ __launch_bounds__(QT) void pg_velocity2_kernel(Grid g, const QW F, C3 q, C3 adv, const double *rho,
+                                                          const double *mu, F3 kq)
 {
-    cell_of(g, [&](size_t id, int i, int j, int k) {
-        const Filt2 F(g.h);
-        const double eps_k = 1e-7, a_kabs = 1.0 / 16.0, a_ksq = 4.0, h = g.h;
-        const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
-        const Nb5 N = nb5(g, i, j, k);
-        for (int c = 0; c < 3; ++c) {
-            double d[4], am[4];
-            deriv_mass2(F, tap5(q.p[c], rule_vel(c), N), d);
-            const double px = d[0] / F.ml, py = d[1] / F.ml, pz = d[2] / F.ml;
-            deriv_mass2(F, tap5(adv.p[c], kEven, N), am);
-            const double a = 2.0 * (am[3] / F.ml - adv.p[c][id]);
-            const double G = fabs(px) + fabs(py) + fabs(pz);
-            const double kabs = a_kabs * h * fabs(a) / (eps_k + G / 3.0);
-            const double g2 = px * px + py * py + pz * pz;
-            const double advabs = fabs(u * px) + fabs(v * py) + fabs(w * pz);
-            const double ksq = a_ksq * a * a * h / (eps_k + advabs / 3.0 * g2);
-            const double kmax = h * (fabs(u) + fabs(v) + fabs(w));
-            const double m = fmin(kmax, fmin(kabs, ksq));
-            kq.p[c][id] = rho[id] * m + mu[id];
-        }
-    });
+    __shared__ QLds L;
+    const QCell X = qcell(g);
+    const size_t id = X.id;
+    const double eps_k = 1e-7, a_kabs = 1.0 / 16.0, a_ksq = 4.0, h = g.h;
+    const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
+    for (int c = 0; c < 3; ++c) {
+        double d[4], am[4];
+        qstage(L, QTap{q.p[c], rule_vel(c), g}, X.i0, X.j0, X.k0);
+        qderiv<true>(L, F, d);
+        const double px = d[0] / F.ml, py = d[1] / F.ml, pz = d[2] / F.ml;
+        qstage(L, QTap{adv.p[c], kEven, g}, X.i0, X.j0, X.k0);
+        qderiv<false>(L, F, am);
+        const double a = 2.0 * (am[3] / F.ml - adv.p[c][id]);
+        const double G = fabs(px) + fabs(py) + fabs(pz);
+        const double kabs = a_kabs * h * fabs(a) / (eps_k + G / 3.0);
+        const double g2 = px * px + py * py + pz * pz;
+        const double advabs = fabs(u * px) + fabs(v * py) + fabs(w * pz);
+        const double ksq = a_ksq * a * a * h / (eps_k + advabs / 3.0 * g2);
+        const double kmax = h * (fabs(u) + fabs(v) + fabs(w));
+        const double m = fmin(kmax, fmin(kabs, ksq));
+        if (X.valid) kq.p[c][id] = rho[id] * m + mu[id];
+    }
 }
 
-// One predictor iteration with the quadratic filters (the same residual as
-// momentum_lds_kernel: s_c = rho m_l adv_c + f_lap(q_c, k_c) + f(p_hs + p_nh; w_c)
-// + f(s_t,c; w_m) [- f(-g rho; w_m) for c = z]).
-__global__ __launch_bounds__(256) void momentum2_kernel(Grid g, Phys P, C3 qn, const double *p_hs, const double *p_nh,
-                                                        const double *rho, C3 qh, C3 kq, C3 st, C3 adv, F3 qt,
-                                                        F3 qnext)
+// One predictor iteration with the quadratic filters: s_c = rho m_l adv_c +
+// f_lap(q_c, k_c) + f(p_hs + p_nh; w_c) + f(s_t,c; w_m) [- f(-g rho; w_m) for
+// c = z], the same residual as momentum_lds_kernel; 15 filters per cell.
+__global__ __launch_bounds__(QT) void momentum2_kernel(Grid g, Phys P, const QW F, C3 qn, const double *p_hs,
+                                                       const double *p_nh, const double *rho, C3 qh, C3 kq, C3 st,
+                                                       C3 adv, F3 qt, F3 qnext)
 {
-    cell_of(g, [&](size_t id, int i, int j, int k) {
-        const Filt2 F(g.h);
-        const double r0 = rho[id];
-        const Nb5 N = nb5(g, i, j, k);
-        double ghs[4], gnh[4], rm[4];
-        deriv_mass2(F, TapPhs5{p_hs, rho, N, P.g * g.h}, ghs);
-        deriv_mass2(F, tap5(p_nh, kOddTop, N), gnh);
-        deriv_mass2(F, tap5(rho, kEven, N), rm);
-        const double buoy = -P.g * rm[3];  // f(-g rho; w_m)
-        for (int c = 0; c < 3; ++c) {
-            const Tap5 tq = tap5(qh.p[c], rule_vel(c), N), tk = tap5(kq.p[c], kEven, N);
-            const double q0 = qh.p[c][id], k0 = kq.p[c][id];
-            // Eq. k-T: 1/2 [f(k q; w) + k f(q; w) - q f(k; w)]
-            double s = 0.5 * (lap2(F, TapMul<Tap5, Tap5>{tk, tq}) + k0 * lap2(F, tq) - q0 * lap2(F, tk));
-            s += ghs[c];
-            s += gnh[c];
-            double t4[4];
-            deriv_mass2(F, tap5(st.p[c], rule_grad(c), N), t4);
-            s += t4[3];
-            if (c == 2) s -= buoy;
-            s += r0 * F.ml * adv.p[c][id];
-            const double qnc = qn.p[c][id];
-            const double t = (-s / F.ml + r0 * qnc / P.dt) / (r0 / P.dt);
-            qt.p[c][id] = t;
-            qnext.p[c][id] = 0.5 * (qnc + t);
+    __shared__ QLds L;
+    const QCell X = qcell(g);
+    const size_t id = X.id;
+    const int i0 = X.i0, j0 = X.j0, k0 = X.k0;
+    const double r0 = rho[id];
+    double ghs[4], gnh[4], rm[4];
+    qstage(L, QPhs{p_hs, rho, g, P.g * g.h}, i0, j0, k0);
+    qderiv<true>(L, F, ghs);
+    qstage(L, QTap{p_nh, kOddTop, g}, i0, j0, k0);
+    qderiv<true>(L, F, gnh);
+    qstage(L, QTap{rho, kEven, g}, i0, j0, k0);
+    qderiv<false>(L, F, rm);
+    const double buoy = -P.g * rm[3];  // f(-g rho; w_m)
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+        const QTap tq{qh.p[c], rule_vel(c), g}, tk{kq.p[c], kEven, g};
+        const double q0 = qh.p[c][id], kc = kq.p[c][id];
+        // Eq. k-T: 1/2 [f(k q; w) + k f(q; w) - q f(k; w)]
+        qstage(L, QMul<QTap, QTap>{tk, tq}, i0, j0, k0);
+        const double lkq = qlap(L, F);
+        qstage(L, tq, i0, j0, k0);
+        const double lq = qlap(L, F);
+        qstage(L, tk, i0, j0, k0);
+        const double lk = qlap(L, F);
+        double s = 0.5 * (lkq + kc * lq - q0 * lk);
+        s += ghs[c];
+        s += gnh[c];
+        double t4[4];
+        qstage(L, QTap{st.p[c], rule_grad(c), g}, i0, j0, k0);
+        qderiv<false>(L, F, t4);
+        s += t4[3];
+        if (c == 2) s -= buoy;
+        s += r0 * F.ml * adv.p[c][id];
+        const double qnc = qn.p[c][id];
+        const double tt = (-s / F.ml + r0 * qnc / P.dt) / (r0 / P.dt);
+        if (X.valid) {
+            qt.p[c][id] = tt;
+            qnext.p[c][id] = 0.5 * (qnc + tt);
         }
-    });
+    }
 }
 
 // Volume-fraction diffusivities with the quadratic advection residual and the
 // detectors of Eqs. Sx-quad..Sz-quad (the smallest of three products of
 // successive differences along each axis).
-__global__ __launch_bounds__(256) void pg_volume_fraction2_kernel(Grid g, double dt, const double *C, C3 Cd, C3 q,
-                                                                  const double *advc, F3 kd)
+__global__ __launch_bounds__(QT) void pg_volume_fraction2_kernel(Grid g, const QW F, double dt, const double *C,
+                                                                 C3 Cd, C3 q, const double *advc, F3 kd)
 {
-    cell_of(g, [&](size_t id, int i, int j, int k) {
-        const Filt2 F(g.h);
-        const double Kp = 300.0, Km = 300.0, beta = 0.1, eps_x = 1e-4, Kpos = 3.0, eps_k = 1e-7, h = g.h;
-        const double kmin = 1e-4 / dt * h * h, kclamp = 0.05 / dt * h * h;
-        double am[4];
-        {
-            const Nb5 N = nb5(g, i, j, k);
-            deriv_mass2(F, tap5(advc, kEven, N), am);
-        }
-        const double a = 2.0 * (am[3] / F.ml - advc[id]);
-        const Tap2 tc{C, kEven, g};
-        const double c0 = C[id];
-        double S[3];
-        for (int d = 0; d < 3; ++d) {
-            double c[5];
-            for (int o = -2; o <= 2; ++o)
-                c[o + 2] = tc(i + (d == 0 ? o : 0), j + (d == 1 ? o : 0), k + (d == 2 ? o : 0));
-            S[d] = (c[2] - c[1]) * (c[3] - c[2]);
-            const double s1 = (c[1] - c[0]) * (c[2] - c[1]), s3 = (c[3] - c[2]) * (c[4] - c[3]);
-            if (s1 < S[d]) S[d] = s1;
-            if (s3 < S[d]) S[d] = s3;
-        }
-        if (c0 > 0.95 || c0 < 0.05) S[0] = S[1] = S[2] = -1.0;
-        const double cx = Cd.p[0][id], cy = Cd.p[1][id], cz = Cd.p[2][id];
-        const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
-        const double g2 = cx * cx + cy * cy + cz * cz;
-        const double proj = (u * cx + v * cy + w * cz) / (eps_x + g2);
-        const double us = cx * proj, vs = cy * proj, ws = cz * proj;
-        const double kneg = -beta * (u * u + v * v + w * w) / (eps_x + g2 * (fabs(us) + fabs(vs) + fabs(ws)) / 3.0);
-        const double G = fabs(cx) + fabs(cy) + fabs(cz);
-        const double kabs = (1.0 / 16.0) * h * fabs(a) / (eps_k + G / 3.0);
-        for (int d = 0; d < 3; ++d) {
-            const double wp = -fmax(-1.0, fmin(0.0, Kp * S[d]));
-            const double wm = fmin(1.0, fmax(0.0, Km * S[d]));
-            const double kk = wp * (Kpos * kabs) + wm * (kneg / h);
-            kd.p[d][id] = fmax(-kmin, fmin(kclamp, kk));
-        }
-    });
+    __shared__ QLds L;
+    const QCell X = qcell(g);
+    const size_t id = X.id;
+    const int i = X.i, j = X.j, k = X.k;
+    const double Kp = 300.0, Km = 300.0, beta = 0.1, eps_x = 1e-4, Kpos = 3.0, eps_k = 1e-7, h = g.h;
+    const double kmin = 1e-4 / dt * h * h, kclamp = 0.05 / dt * h * h;
+    double am[4];
+    qstage(L, QTap{advc, kEven, g}, X.i0, X.j0, X.k0);
+    qderiv<false>(L, F, am);
+    if (!X.valid) return;
+    const double a = 2.0 * (am[3] / F.ml - advc[id]);
+    const Tap2 tc{C, kEven, g};
+    const double c0 = C[id];
+    double S[3];
+    for (int d = 0; d < 3; ++d) {
+        double c[5];
+        for (int o = -2; o <= 2; ++o)
+            c[o + 2] = tc(i + (d == 0 ? o : 0), j + (d == 1 ? o : 0), k + (d == 2 ? o : 0));
+        S[d] = (c[2] - c[1]) * (c[3] - c[2]);
+        const double s1 = (c[1] - c[0]) * (c[2] - c[1]), s3 = (c[3] - c[2]) * (c[4] - c[3]);
+        if (s1 < S[d]) S[d] = s1;
+        if (s3 < S[d]) S[d] = s3;
+    }
+    if (c0 > 0.95 || c0 < 0.05) S[0] = S[1] = S[2] = -1.0;
+    const double cx = Cd.p[0][id], cy = Cd.p[1][id], cz = Cd.p[2][id];
+    const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
+    const double g2 = cx * cx + cy * cy + cz * cz;
+    const double proj = (u * cx + v * cy + w * cz) / (eps_x + g2);
+    const double us = cx * proj, vs = cy * proj, ws = cz * proj;
+    const double kneg = -beta * (u * u + v * v + w * w) / (eps_x + g2 * (fabs(us) + fabs(vs) + fabs(ws)) / 3.0);
+    const double G = fabs(cx) + fabs(cy) + fabs(cz);
+    const double kabs = (1.0 / 16.0) * h * fabs(a) / (eps_k + G / 3.0);
+    for (int d = 0; d < 3; ++d) {
+        const double wp = -fmax(-1.0, fmin(0.0, Kp * S[d]));
+        const double wm = fmin(1.0, fmax(0.0, Km * S[d]));
+        const double kk = wp * (Kpos * kabs) + wm * (kneg / h);
+        kd.p[d][id] = fmax(-kmin, fmin(kclamp, kk));
+    }
 }
 
 C3 c3(double *const p[3]) { return C3{{p[0], p[1], p[2]}}; }
@@ -1184,6 +1244,9 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     const Phys P{p.rho_l, p.rho_g, p.mu_l, p.mu_g, p.g, p.sigma_t, p.dt};
     const hipStream_t s = S->s;
     const dim3 grid = cells_grid(g), blk(256);
+    // the quadratic kernels: one workgroup per 8^3 block
+    const dim3 qgrid((unsigned)(((g.nx + QB - 1) / QB) * ((g.ny + QB - 1) / QB) * ((g.nz + QB - 1) / QB)));
+    const QW qw = quad_weights(g.h);
     double *q[3] = {u, v, w};
     float ms_mg = 0.0f;
     int rc;
@@ -1191,9 +1254,10 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     const bool quad = p.order == 2;
     STEP_TRY(hipEventRecord(S->ev[0], s), "hipEventRecord");
     if (quad) {
-        hipLaunchKernelGGL(props2_kernel, grid, blk, 0, s, g, P, (const double *)C, S->rho, S->mu, f3(S->Cd),
-                           f3(S->nrm));
-        hipLaunchKernelGGL(surface2_kernel, grid, blk, 0, s, g, p.sigma_t, c3(S->nrm), c3(S->Cd), f3(S->st));
+        hipLaunchKernelGGL(props2_kernel, qgrid, dim3(QT), 0, s, g, P, qw, (const double *)C, S->rho, S->mu,
+                           f3(S->Cd), f3(S->nrm));
+        hipLaunchKernelGGL(surface2_kernel, qgrid, dim3(QT), 0, s, g, qw, p.sigma_t, c3(S->nrm), c3(S->Cd),
+                           f3(S->st));
     } else {
         hipLaunchKernelGGL(props_kernel, grid, blk, 0, s, g, P, (const double *)C, S->rho, S->mu, f3(S->Cd),
                            f3(S->nrm));
@@ -1212,10 +1276,11 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     hipLaunchKernelGGL(copy3_kernel, grid, blk, 0, s, g.n, c3(q), f3(cur));
     for (int it = 0; it < p.n_vel_iter; ++it) {
         if (quad) {
-            hipLaunchKernelGGL(advection2_kernel, grid, blk, 0, s, g, c3(cur), f3(S->adv));
-            hipLaunchKernelGGL(pg_velocity2_kernel, grid, blk, 0, s, g, c3(cur), c3(S->adv), (const double *)S->rho,
+            hipLaunchKernelGGL(advection2_kernel, qgrid, dim3(QT), 0, s, g, qw, c3(cur), f3(S->adv));
+            hipLaunchKernelGGL(pg_velocity2_kernel, qgrid, dim3(QT), 0, s, g, qw, c3(cur), c3(S->adv),
+                               (const double *)S->rho,
                                (const double *)S->mu, f3(S->kq));
-            hipLaunchKernelGGL(momentum2_kernel, grid, blk, 0, s, g, P, c3(q), (const double *)p_hs,
+            hipLaunchKernelGGL(momentum2_kernel, qgrid, dim3(QT), 0, s, g, P, qw, c3(q), (const double *)p_hs,
                                (const double *)p_nh, (const double *)S->rho, c3(cur), c3(S->kq), c3(S->st),
                                c3(S->adv), f3(S->qt), f3(nxt));
             double **t = cur;
@@ -1262,8 +1327,8 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     // Stage 4: volume fraction with the new velocity
     hipLaunchKernelGGL(advection_c_kernel, grid, blk, 0, s, g, c3(q), c3(S->Cd), S->tmp);
     if (quad)
-        hipLaunchKernelGGL(pg_volume_fraction2_kernel, grid, blk, 0, s, g, p.dt, (const double *)C, c3(S->Cd), c3(q),
-                           (const double *)S->tmp, f3(S->kq));
+        hipLaunchKernelGGL(pg_volume_fraction2_kernel, qgrid, dim3(QT), 0, s, g, qw, p.dt, (const double *)C,
+                           c3(S->Cd), c3(q), (const double *)S->tmp, f3(S->kq));
     else
         hipLaunchKernelGGL(pg_volume_fraction_kernel, grid, blk, 0, s, g, p.dt, (const double *)C, c3(S->Cd), c3(q),
                            (const double *)S->tmp, f3(S->kq));

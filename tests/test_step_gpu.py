@@ -161,6 +161,7 @@ QUAD_CASES = [
     ("quadratic_water_air", (32, 16, 32), dict(order=2)),
     ("quadratic_predictor_only", (32, 16, 32), dict(n_corr=0, order=2)),
     ("quadratic_64", (64, 64, 64), dict(rho_g=500.0, order=2)),
+    ("quadratic_ragged", (24, 20, 28), dict(order=2)),
 ]
 
 
