@@ -215,6 +215,89 @@ struct C3 {
 
 // ------------------------------------------------------------------ kernels
 
+// ---- one workgroup per 8^3 block ----
+// For kernels that filter several fields per cell (the advection and the PG
+// diffusivity of the three components) each field is staged once in LDS on
+// the block plus a one-cell halo (10^3 cells, the field's boundary rule
+// applied as tap() applies it), and each thread gathers its cell's 27 values
+// from there into an Nb: the values load() gives, with one global load per
+// staged cell instead of 27 per cell.  Two staging buffers alternate, one
+// barrier per field: a thread stages field f only after the barrier of field
+// f - 1, which every thread reaches after gathering f - 2.  (For the kernels
+// that filter one or two fields, and the plane-marching momentum kernel, the
+// per-cell gathers through L1/L2 measured faster.)
+constexpr int SB = 8;                // block edge
+constexpr int SBT = SB * SB * SB;    // threads: one cell each
+constexpr int SL = SB + 2;           // staged edge
+constexpr int SLN = SL * SL * SL;    // staged cells
+
+// This thread's cell of the workgroup's block (the block at (i0, j0, k0)); a
+// ragged block's threads beyond the grid work on their cell clamped into it
+// and write nothing.
+struct BCell {
+    int i0, j0, k0, i, j, k;
+    bool valid;
+    size_t id;
+};
+__device__ inline BCell bcell(const Grid &g)
+{
+    BCell c;
+    const int bxn = (g.nx + SB - 1) / SB, byn = (g.ny + SB - 1) / SB;
+    const int lb = blockIdx.x, t = threadIdx.x;
+    c.i0 = (lb % bxn) * SB;
+    c.j0 = ((lb / bxn) % byn) * SB;
+    c.k0 = (lb / bxn / byn) * SB;
+    const int i = c.i0 + t % SB, j = c.j0 + (t / SB) % SB, k = c.k0 + t / (SB * SB);
+    c.valid = i < g.nx && j < g.ny && k < g.nz;
+    c.i = min(i, g.nx - 1);
+    c.j = min(j, g.ny - 1);
+    c.k = min(k, g.nz - 1);
+    c.id = at(g, c.i, c.j, c.k);
+    return c;
+}
+
+unsigned blocks_of(const Grid &g)
+{
+    return (unsigned)(((g.nx + SB - 1) / SB) * ((g.ny + SB - 1) / SB) * ((g.nz + SB - 1) / SB));
+}
+
+// Neighbourhoods from LDS: load_nb(nb, u, odd) stages field u (rule odd) into
+// the next buffer, waits for the workgroup and gathers this thread's 27 values.
+struct LNb {
+    double (*buf)[SLN];
+    const Grid &g;
+    const BCell &X;
+    int next;
+    template <typename V>
+    __device__ void stage_gather(Nb &n, const V &val)
+    {
+        double *b = buf[next];
+        next ^= 1;
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int r = 0; r < (SLN + SBT - 1) / SBT; ++r) {
+            const int idx = t + r * SBT;
+            if (idx < SLN) {
+                const int x = idx % SL, y = (idx / SL) % SL, z = idx / (SL * SL);
+                b[idx] = val(X.i0 + x - 1, X.j0 + y - 1, X.k0 + z - 1);
+            }
+        }
+        __syncthreads();
+        const int tx = t % SB, ty = (t / SB) % SB, tz = t / (SB * SB);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) n.v[c * 9 + bb * 3 + a] = b[(tx + a) + SL * ((ty + bb) + SL * (tz + c))];
+    }
+    __device__ void operator()(Nb &n, const double *u, unsigned odd)
+    {
+        const Grid &gg = g;
+        stage_gather(n, [&](int i, int j, int k) { return tap(u, odd, gg, i, j, k); });
+    }
+};
+
 // rho, mu (Eq. rho), grad C in derivative units, unit normals.
 __global__ __launch_bounds__(256) void props_kernel(Grid g, Phys P, const double *C, double *rho, double *mu, F3 Cd,
                                                     F3 nrm)
@@ -281,48 +364,52 @@ __global__ __launch_bounds__(256) void rhs_hydrostatic_kernel(Grid g, double gra
 }
 
 // Advection of each velocity component by the iterate: adv_c = q . grad q_c.
-__global__ __launch_bounds__(256) void advection_kernel(Grid g, C3 q, F3 adv)
+__global__ __launch_bounds__(SBT) void advection_kernel(Grid g, C3 q, F3 adv)
 {
-    cell_of(g, [&](size_t id, int i, int j, int k) {
-        const Filt F(g.h);
-        const double q0[3] = {q.p[0][id], q.p[1][id], q.p[2][id]};
-        for (int c = 0; c < 3; ++c) {
-            Nb n;
-            load(n, q.p[c], rule_vel(c), g, i, j, k);
-            double a = 0.0;
-            for (int d = 0; d < 3; ++d) a += q0[d] * (F.d(n, d) / F.ml);
-            adv.p[c][id] = a;
-        }
-    });
+    __shared__ double sb[2][SLN];
+    const BCell X = bcell(g);
+    LNb load_nb{sb, g, X, 0};
+    const Filt F(g.h);
+    const size_t id = X.id;
+    const double q0[3] = {q.p[0][id], q.p[1][id], q.p[2][id]};
+    for (int c = 0; c < 3; ++c) {
+        Nb n;
+        load_nb(n, q.p[c], rule_vel(c));
+        double a = 0.0;
+        for (int d = 0; d < 3; ++d) a += q0[d] * (F.d(n, d) / F.ml);
+        if (X.valid) adv.p[c][id] = a;
+    }
 }
 
 // Isotropic Petrov-Galerkin diffusivity of each component (Eq. k_Psi-n with
 // Eqs. efficient-kabs-special-case, k-square with h_Psi = h, max-k and the
 // residual a_Psi of Eq. a_psi, alpha_a = 2): k_c = rho min(k_max, k_abs, k_sq) + mu.
-__global__ __launch_bounds__(256) void pg_velocity_kernel(Grid g, C3 q, C3 adv, const double *rho,
+__global__ __launch_bounds__(SBT) void pg_velocity_kernel(Grid g, C3 q, C3 adv, const double *rho,
                                                           const double *mu, F3 kq)
 {
-    cell_of(g, [&](size_t id, int i, int j, int k) {
-        const Filt F(g.h);
-        const double eps_k = 1e-7, a_kabs = 1.0 / 16.0, a_ksq = 4.0, h = g.h;
-        const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
-        for (int c = 0; c < 3; ++c) {
-            Nb n;
-            load(n, q.p[c], rule_vel(c), g, i, j, k);
-            const double px = F.d(n, 0) / F.ml, py = F.d(n, 1) / F.ml, pz = F.d(n, 2) / F.ml;
-            Nb an;
-            load(an, adv.p[c], kEven, g, i, j, k);
-            const double a = 2.0 * F.mass_resid(an);
-            const double G = fabs(px) + fabs(py) + fabs(pz);
-            const double kabs = a_kabs * h * fabs(a) / (eps_k + G / 3.0);
-            const double g2 = px * px + py * py + pz * pz;
-            const double advabs = fabs(u * px) + fabs(v * py) + fabs(w * pz);
-            const double ksq = a_ksq * a * a * h / (eps_k + advabs / 3.0 * g2);
-            const double kmax = h * (fabs(u) + fabs(v) + fabs(w));
-            const double m = fmin(kmax, fmin(kabs, ksq));
-            kq.p[c][id] = rho[id] * m + mu[id];
-        }
-    });
+    __shared__ double sb[2][SLN];
+    const BCell X = bcell(g);
+    LNb load_nb{sb, g, X, 0};
+    const Filt F(g.h);
+    const size_t id = X.id;
+    const double eps_k = 1e-7, a_kabs = 1.0 / 16.0, a_ksq = 4.0, h = g.h;
+    const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
+    for (int c = 0; c < 3; ++c) {
+        Nb n;
+        load_nb(n, q.p[c], rule_vel(c));
+        const double px = F.d(n, 0) / F.ml, py = F.d(n, 1) / F.ml, pz = F.d(n, 2) / F.ml;
+        Nb an;
+        load_nb(an, adv.p[c], kEven);
+        const double a = 2.0 * F.mass_resid(an);
+        const double G = fabs(px) + fabs(py) + fabs(pz);
+        const double kabs = a_kabs * h * fabs(a) / (eps_k + G / 3.0);
+        const double g2 = px * px + py * py + pz * pz;
+        const double advabs = fabs(u * px) + fabs(v * py) + fabs(w * pz);
+        const double ksq = a_ksq * a * a * h / (eps_k + advabs / 3.0 * g2);
+        const double kmax = h * (fabs(u) + fabs(v) + fabs(w));
+        const double m = fmin(kmax, fmin(kabs, ksq));
+        if (X.valid) kq.p[c][id] = rho[id] * m + mu[id];
+    }
 }
 
 // One predictor iteration (Eqs. Petrov, velocity-1): the momentum residual
@@ -630,8 +717,8 @@ struct Tap2 {
 };
 
 
-constexpr int QB = 8;                 // output block edge
-constexpr int QT = QB * QB * QB;      // threads: one output cell each
+constexpr int QB = SB;                // output block edge
+constexpr int QT = SBT;               // threads: one output cell each
 constexpr int QS = QB + 4;            // staged edge
 constexpr int QSN = QS * QS * QS;     // staged cells
 constexpr int QRN = QB * QS * QS;     // x-pass outputs per filter (8 x 12 x 12)
@@ -825,37 +912,12 @@ __device__ inline double qlap(QLds &L, const QW &F)
     return out;
 }
 
-// This thread's cell of the workgroup's 8^3 block (the block at (i0, j0, k0));
-// a ragged block's threads beyond the grid read their cell clamped into it
-// and write nothing.
-struct QCell {
-    int i0, j0, k0, i, j, k;
-    bool valid;
-    size_t id;
-};
-__device__ inline QCell qcell(const Grid &g)
-{
-    QCell c;
-    const int bxn = (g.nx + QB - 1) / QB, byn = (g.ny + QB - 1) / QB;
-    const int lb = blockIdx.x, t = threadIdx.x;
-    c.i0 = (lb % bxn) * QB;
-    c.j0 = ((lb / bxn) % byn) * QB;
-    c.k0 = (lb / bxn / byn) * QB;
-    const int i = c.i0 + t % QB, j = c.j0 + (t / QB) % QB, k = c.k0 + t / (QB * QB);
-    c.valid = i < g.nx && j < g.ny && k < g.nz;
-    c.i = min(i, g.nx - 1);
-    c.j = min(j, g.ny - 1);
-    c.k = min(k, g.nz - 1);
-    c.id = at(g, c.i, c.j, c.k);
-    return c;
-}
-
 // rho, mu, grad C in derivative units and the unit normals, quadratic filters.
 __global__ __launch_bounds__(QT) void props2_kernel(Grid g, Phys P, const QW F, const double *C, double *rho,
                                                     double *mu, F3 Cd, F3 nrm)
 {
     __shared__ QLds L;
-    const QCell X = qcell(g);
+    const BCell X = bcell(g);
     const size_t id = X.id;
     double d[4];
     qstage(L, QTap{C, kEven, g}, X.i0, X.j0, X.k0);
@@ -878,7 +940,7 @@ __global__ __launch_bounds__(QT) void props2_kernel(Grid g, Phys P, const QW F, 
 __global__ __launch_bounds__(QT) void surface2_kernel(Grid g, const QW F, double sigma, C3 nrm, C3 Cd, F3 st)
 {
     __shared__ QLds L;
-    const QCell X = qcell(g);
+    const BCell X = bcell(g);
     double kap = 0.0;
     for (int e = 0; e < 3; ++e) {
         double d[4];
@@ -895,7 +957,7 @@ __global__ __launch_bounds__(QT) void surface2_kernel(Grid g, const QW F, double
 __global__ __launch_bounds__(QT) void advection2_kernel(Grid g, const QW F, C3 q, F3 adv)
 {
     __shared__ QLds L;
-    const QCell X = qcell(g);
+    const BCell X = bcell(g);
     const size_t id = X.id;
     const double q0[3] = {q.p[0][id], q.p[1][id], q.p[2][id]};
     for (int c = 0; c < 3; ++c) {
@@ -912,7 +974,7 @@ __global__ __launch_bounds__(QT) void pg_velocity2_kernel(Grid g, const QW F, C3
                                                           const double *mu, F3 kq)
 {
     __shared__ QLds L;
-    const QCell X = qcell(g);
+    const BCell X = bcell(g);
     const size_t id = X.id;
     const double eps_k = 1e-7, a_kabs = 1.0 / 16.0, a_ksq = 4.0, h = g.h;
     const double u = q.p[0][id], v = q.p[1][id], w = q.p[2][id];
@@ -943,7 +1005,7 @@ __global__ __launch_bounds__(QT) void momentum2_kernel(Grid g, Phys P, const QW 
                                                        C3 adv, F3 qt, F3 qnext)
 {
     __shared__ QLds L;
-    const QCell X = qcell(g);
+    const BCell X = bcell(g);
     const size_t id = X.id;
     const int i0 = X.i0, j0 = X.j0, k0 = X.k0;
     const double r0 = rho[id];
@@ -991,7 +1053,7 @@ __global__ __launch_bounds__(QT) void pg_volume_fraction2_kernel(Grid g, const Q
                                                                  C3 Cd, C3 q, const double *advc, F3 kd)
 {
     __shared__ QLds L;
-    const QCell X = qcell(g);
+    const BCell X = bcell(g);
     const size_t id = X.id;
     const int i = X.i, j = X.j, k = X.k;
     const double Kp = 300.0, Km = 300.0, beta = 0.1, eps_x = 1e-4, Kpos = 3.0, eps_k = 1e-7, h = g.h;
@@ -1244,8 +1306,8 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     const Phys P{p.rho_l, p.rho_g, p.mu_l, p.mu_g, p.g, p.sigma_t, p.dt};
     const hipStream_t s = S->s;
     const dim3 grid = cells_grid(g), blk(256);
-    // the quadratic kernels: one workgroup per 8^3 block
-    const dim3 qgrid((unsigned)(((g.nx + QB - 1) / QB) * ((g.ny + QB - 1) / QB) * ((g.nz + QB - 1) / QB)));
+    // the block-staged kernels: one workgroup per 8^3 block
+    const dim3 bgrid(blocks_of(g)), bblk(SBT);
     const QW qw = quad_weights(g.h);
     double *q[3] = {u, v, w};
     float ms_mg = 0.0f;
@@ -1254,9 +1316,9 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     const bool quad = p.order == 2;
     STEP_TRY(hipEventRecord(S->ev[0], s), "hipEventRecord");
     if (quad) {
-        hipLaunchKernelGGL(props2_kernel, qgrid, dim3(QT), 0, s, g, P, qw, (const double *)C, S->rho, S->mu,
+        hipLaunchKernelGGL(props2_kernel, bgrid, bblk, 0, s, g, P, qw, (const double *)C, S->rho, S->mu,
                            f3(S->Cd), f3(S->nrm));
-        hipLaunchKernelGGL(surface2_kernel, qgrid, dim3(QT), 0, s, g, qw, p.sigma_t, c3(S->nrm), c3(S->Cd),
+        hipLaunchKernelGGL(surface2_kernel, bgrid, bblk, 0, s, g, qw, p.sigma_t, c3(S->nrm), c3(S->Cd),
                            f3(S->st));
     } else {
         hipLaunchKernelGGL(props_kernel, grid, blk, 0, s, g, P, (const double *)C, S->rho, S->mu, f3(S->Cd),
@@ -1276,11 +1338,11 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     hipLaunchKernelGGL(copy3_kernel, grid, blk, 0, s, g.n, c3(q), f3(cur));
     for (int it = 0; it < p.n_vel_iter; ++it) {
         if (quad) {
-            hipLaunchKernelGGL(advection2_kernel, qgrid, dim3(QT), 0, s, g, qw, c3(cur), f3(S->adv));
-            hipLaunchKernelGGL(pg_velocity2_kernel, qgrid, dim3(QT), 0, s, g, qw, c3(cur), c3(S->adv),
+            hipLaunchKernelGGL(advection2_kernel, bgrid, bblk, 0, s, g, qw, c3(cur), f3(S->adv));
+            hipLaunchKernelGGL(pg_velocity2_kernel, bgrid, bblk, 0, s, g, qw, c3(cur), c3(S->adv),
                                (const double *)S->rho,
                                (const double *)S->mu, f3(S->kq));
-            hipLaunchKernelGGL(momentum2_kernel, qgrid, dim3(QT), 0, s, g, P, qw, c3(q), (const double *)p_hs,
+            hipLaunchKernelGGL(momentum2_kernel, bgrid, bblk, 0, s, g, P, qw, c3(q), (const double *)p_hs,
                                (const double *)p_nh, (const double *)S->rho, c3(cur), c3(S->kq), c3(S->st),
                                c3(S->adv), f3(S->qt), f3(nxt));
             double **t = cur;
@@ -1288,8 +1350,8 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
             nxt = t;
             continue;
         }
-        hipLaunchKernelGGL(advection_kernel, grid, blk, 0, s, g, c3(cur), f3(S->adv));
-        hipLaunchKernelGGL(pg_velocity_kernel, grid, blk, 0, s, g, c3(cur), c3(S->adv), (const double *)S->rho,
+        hipLaunchKernelGGL(advection_kernel, bgrid, bblk, 0, s, g, c3(cur), f3(S->adv));
+        hipLaunchKernelGGL(pg_velocity_kernel, bgrid, bblk, 0, s, g, c3(cur), c3(S->adv), (const double *)S->rho,
                            (const double *)S->mu, f3(S->kq));
         {
             MomIn in;
@@ -1327,7 +1389,7 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     // Stage 4: volume fraction with the new velocity
     hipLaunchKernelGGL(advection_c_kernel, grid, blk, 0, s, g, c3(q), c3(S->Cd), S->tmp);
     if (quad)
-        hipLaunchKernelGGL(pg_volume_fraction2_kernel, qgrid, dim3(QT), 0, s, g, qw, p.dt, (const double *)C,
+        hipLaunchKernelGGL(pg_volume_fraction2_kernel, bgrid, bblk, 0, s, g, qw, p.dt, (const double *)C,
                            c3(S->Cd), c3(q), (const double *)S->tmp, f3(S->kq));
     else
         hipLaunchKernelGGL(pg_volume_fraction_kernel, grid, blk, 0, s, g, p.dt, (const double *)C, c3(S->Cd), c3(q),
