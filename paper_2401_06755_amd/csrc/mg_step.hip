@@ -760,19 +760,28 @@ __device__ inline int qfold(int i, int n, unsigned odd, unsigned lo_bit, unsigne
 }
 
 // A field at unfolded (i, j, k) with the two-cell halo of rule odd.
+// Each staging functor splits into fetch (the global loads and the sign or
+// halo case of an unfolded (i, j, k)) and value (the staged value from the
+// fetched raw data), so the loads of the next field can be in flight while
+// the current field's passes run.
 struct QTap {
     const double *u;
     unsigned odd;
     Grid g;
-    __device__ double operator()(int i, int j, int k) const
+    struct Raw {
+        double v;
+        bool neg;
+    };
+    __device__ Raw fetch(int i, int j, int k) const
     {
         double s = 1.0;
         const int fi = qfold(i, g.nx, odd, 1u, 2u, s);
         const int fj = qfold(j, g.ny, odd, 4u, 8u, s);
         const int fk = qfold(k, g.nz, odd, 16u, 32u, s);
-        const double v = u[at(g, fi, fj, fk)];
-        return s < 0.0 ? -v : v;
+        return {u[at(g, fi, fj, fk)], s < 0.0};
     }
+    __device__ double value(const Raw &r) const { return r.neg ? -r.v : r.v; }
+    __device__ double operator()(int i, int j, int k) const { return value(fetch(i, j, k)); }
 };
 
 // p_hs at unfolded (i, j, k): +mirror on the sides, -mirror on top, and below
@@ -782,27 +791,70 @@ struct QPhs {
     const double *p, *rho;
     Grid g;
     double gh;
-    __device__ double operator()(int i, int j, int k) const
+    struct Raw {
+        double p, r;
+        int m;  // below the bottom: the mirror distance m (>= 0); -1 inside; -2 above the top
+    };
+    __device__ Raw fetch(int i, int j, int k) const
     {
         double s = 1.0;
         const int fi = qfold(i, g.nx, 0u, 1u, 2u, s);
         const int fj = qfold(j, g.ny, 0u, 4u, 8u, s);
         const int fk = qfold(k, g.nz, 0u, 16u, 32u, s);
         const size_t idx = at(g, fi, fj, fk);
-        if (k < 0) {
-            const int m = -1 - k;
-            return p[idx] + (double)(2 * m + 1) * gh * rho[idx];
-        }
-        const double v = p[idx];
-        return k >= g.nz ? -v : v;
+        Raw o;
+        o.p = p[idx];
+        o.r = k < 0 ? rho[idx] : 0.0;
+        o.m = k < 0 ? -1 - k : (k >= g.nz ? -2 : -1);
+        return o;
     }
+    __device__ double value(const Raw &o) const
+    {
+        if (o.m >= 0) return o.p + (double)(2 * o.m + 1) * gh * o.r;
+        return o.m == -2 ? -o.p : o.p;
+    }
+    __device__ double operator()(int i, int j, int k) const { return value(fetch(i, j, k)); }
 };
 
 template <typename A, typename B>
 struct QMul {
     A a;
     B b;
-    __device__ double operator()(int i, int j, int k) const { return a(i, j, k) * b(i, j, k); }
+    struct Raw {
+        typename A::Raw a;
+        typename B::Raw b;
+    };
+    __device__ Raw fetch(int i, int j, int k) const { return {a.fetch(i, j, k), b.fetch(i, j, k)}; }
+    __device__ double value(const Raw &r) const { return a.value(r.a) * b.value(r.b); }
+    __device__ double operator()(int i, int j, int k) const { return value(fetch(i, j, k)); }
+};
+
+// The next field's staging in registers: fetch issues its loads, commit
+// writes the staged values to LDS (after the current field's passes; the x
+// pass, the only reader of the staged field, is then done on every thread).
+template <typename V>
+struct QNext {
+    static constexpr int NR = (QSN + QT - 1) / QT;
+    typename V::Raw r[NR];
+    __device__ void fetch(const V &v, int i0, int j0, int k0)
+    {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const int idx = min(t + q * QT, QSN - 1);
+            const int x = idx % QS, y = (idx / QS) % QS, z = idx / (QS * QS);
+            r[q] = v.fetch(i0 + x - 2, j0 + y - 2, k0 + z - 2);
+        }
+    }
+    __device__ void commit(QLds &L, const V &v) const
+    {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const int idx = t + q * QT;
+            if (idx < QSN) L.s[idx] = v.value(r[q]);
+        }
+    }
 };
 
 // Stage field v on the block at (i0, j0, k0) plus its two-cell halo.
@@ -1010,30 +1062,72 @@ __global__ __launch_bounds__(QT) void momentum2_kernel(Grid g, Phys P, const QW 
     const int i0 = X.i0, j0 = X.j0, k0 = X.k0;
     const double r0 = rho[id];
     double ghs[4], gnh[4], rm[4];
-    qstage(L, QPhs{p_hs, rho, g, P.g * g.h}, i0, j0, k0);
-    qderiv<true>(L, F, ghs);
-    qstage(L, QTap{p_nh, kOddTop, g}, i0, j0, k0);
-    qderiv<true>(L, F, gnh);
-    qstage(L, QTap{rho, kEven, g}, i0, j0, k0);
-    qderiv<false>(L, F, rm);
+    // each field's loads are issued before the previous field's passes
+    const QPhs fphs{p_hs, rho, g, P.g * g.h};
+    const QTap fnh{p_nh, kOddTop, g}, frho{rho, kEven, g};
+    {
+        QNext<QPhs> n0;
+        n0.fetch(fphs, i0, j0, k0);
+        n0.commit(L, fphs);
+    }
+    {
+        QNext<QTap> n1;
+        n1.fetch(fnh, i0, j0, k0);
+        qderiv<true>(L, F, ghs);
+        n1.commit(L, fnh);
+    }
+    {
+        QNext<QTap> n2;
+        n2.fetch(frho, i0, j0, k0);
+        qderiv<true>(L, F, gnh);
+        n2.commit(L, frho);
+    }
+    using TM = QMul<QTap, QTap>;
+    {
+        const TM m0{QTap{kq.p[0], kEven, g}, QTap{qh.p[0], rule_vel(0), g}};
+        QNext<TM> n3;
+        n3.fetch(m0, i0, j0, k0);
+        qderiv<false>(L, F, rm);
+        n3.commit(L, m0);
+    }
     const double buoy = -P.g * rm[3];  // f(-g rho; w_m)
 #pragma unroll 1
     for (int c = 0; c < 3; ++c) {
-        const QTap tq{qh.p[c], rule_vel(c), g}, tk{kq.p[c], kEven, g};
+        const QTap tq{qh.p[c], rule_vel(c), g}, tk{kq.p[c], kEven, g}, ts{st.p[c], rule_grad(c), g};
         const double q0 = qh.p[c][id], kc = kq.p[c][id];
-        // Eq. k-T: 1/2 [f(k q; w) + k f(q; w) - q f(k; w)]
-        qstage(L, QMul<QTap, QTap>{tk, tq}, i0, j0, k0);
-        const double lkq = qlap(L, F);
-        qstage(L, tq, i0, j0, k0);
-        const double lq = qlap(L, F);
-        qstage(L, tk, i0, j0, k0);
-        const double lk = qlap(L, F);
+        // Eq. k-T: 1/2 [f(k q; w) + k f(q; w) - q f(k; w)]; f(k q) is staged
+        double lkq, lq, lk;
+        {
+            QNext<QTap> n;
+            n.fetch(tq, i0, j0, k0);
+            lkq = qlap(L, F);
+            n.commit(L, tq);
+        }
+        {
+            QNext<QTap> n;
+            n.fetch(tk, i0, j0, k0);
+            lq = qlap(L, F);
+            n.commit(L, tk);
+        }
+        {
+            QNext<QTap> n;
+            n.fetch(ts, i0, j0, k0);
+            lk = qlap(L, F);
+            n.commit(L, ts);
+        }
         double s = 0.5 * (lkq + kc * lq - q0 * lk);
         s += ghs[c];
         s += gnh[c];
         double t4[4];
-        qstage(L, QTap{st.p[c], rule_grad(c), g}, i0, j0, k0);
-        qderiv<false>(L, F, t4);
+        {
+            // the next component's product field
+            const int cn = c < 2 ? c + 1 : c;
+            const TM mn{QTap{kq.p[cn], kEven, g}, QTap{qh.p[cn], rule_vel(cn), g}};
+            QNext<TM> n;
+            if (c < 2) n.fetch(mn, i0, j0, k0);
+            qderiv<false>(L, F, t4);
+            if (c < 2) n.commit(L, mn);
+        }
         s += t4[3];
         if (c == 2) s -= buoy;
         s += r0 * F.ml * adv.p[c][id];

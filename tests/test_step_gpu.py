@@ -74,6 +74,8 @@ CASES = [
     ("predictor_only", (32, 16, 32), dict(n_corr=0)),
     ("water_air_default", (32, 16, 32), dict()),
     ("ratio2_three_predictor_iters", (48, 16, 32), dict(rho_g=500.0, n_vel_iter=3, n_corr=1, mg_cycles=10)),
+    # partial 8^3 blocks along every axis
+    ("ratio2_ragged", (24, 20, 28), dict(rho_g=500.0)),
 ]
 
 
