@@ -10,6 +10,7 @@
 // of later cycles exit at once when the rule has fired, so the host only
 // synchronises once per batch of cycles.
 #include "../../include/nn4mg.h"
+#include "mg_async.h"
 #include "mg_internal.h"
 
 #include <chrono>
@@ -1526,6 +1527,31 @@ int solve_after_header(nn4mg_hier *H)
 }
 
 int solve_finish(nn4mg_hier *H, double *x, nn4mg_info *info) { return finish_solve(H, x, info, H->solve_t0); }
+
+size_t solve_header_bytes() { return sizeof(StateHeader); }
+
+int solve_fixed_enqueue(nn4mg_hier *H, const double *b, double *x, int cycles, void *host_hdr)
+{
+    if (!H || !b || !x || !host_hdr || cycles < 1) return fail(NN4MG_EINVAL, "bad fixed-count solve arguments");
+    if (H->singular || H->cfg.outer == NN4MG_OUTER_FCG || H->group || H->view_of || H->L < 1)
+        return fail(NN4MG_EINVAL, "fixed-count solve without host round trip: stationary, non-singular hierarchies only");
+    int rc;
+    if ((rc = solve_begin(H, b, x, 0.0, cycles, 1))) return rc;
+    if ((rc = solve_enqueue_next(H, b, x))) return rc;  // all `cycles`, as planned for a fixed count
+    HIP_TRY(launch_finish_fixed(x, H->lv[0].t, H->lv[0].n, H->st, direct_fine(H) ? 1 : 0, H->stream));
+    HIP_TRY(hipMemcpyAsync(host_hdr, H->st, sizeof(StateHeader), hipMemcpyDeviceToHost, H->stream));
+    return NN4MG_OK;
+}
+
+int solve_fixed_result(const void *host_hdr, double *relres)
+{
+    StateHeader hd;
+    std::memcpy(&hd, host_hdr, sizeof(hd));
+    if (relres) *relres = hd.last;
+    if (hd.status == -5)
+        return fail(NN4MG_EBREAKDOWN, "breakdown: non-finite residual or residual grown past 1e3 times the first");
+    return NN4MG_OK;  // status -4 is the end of the fixed count
+}
 
 int hier_set_stream(nn4mg_hier *H, hipStream_t s)
 {

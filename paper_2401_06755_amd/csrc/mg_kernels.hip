@@ -1,5 +1,6 @@
 // Grid-transfer, coefficient, reduction and coarsest-level kernels of the
 // multigrid solve (gfx950).  The stencil kernel lives in mg_stencil.hip.
+#include "mg_async.h"
 #include "mg_internal.h"
 
 #include <type_traits>
@@ -500,6 +501,32 @@ hipError_t launch_add(double *x, const void *e, int e_f32, size_t n, const int *
         hipLaunchKernelGGL(add_kernel<float>, dim3(stream_blocks(n)), dim3(256), 0, s, x, (const float *)e, n, done);
     else
         hipLaunchKernelGGL(add_kernel<double>, dim3(stream_blocks(n)), dim3(256), 0, s, x, (const double *)e, n, done);
+    return hipGetLastError();
+}
+
+
+namespace {
+
+// The device side of a fixed-count solve's finish (see launch_finish_fixed).
+__global__ __launch_bounds__(256) void finish_fixed_kernel(double *x, const double *t, size_t n, const SolveState *st,
+                                                           int direct)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (st->nb == 0.0) {
+        x[i] = 0.0;
+        return;
+    }
+    const int nres = st->nres;
+    if (direct && nres > 0 && ((nres - 1) & 1)) x[i] = t[i];
+}
+
+}  // namespace
+
+hipError_t launch_finish_fixed(double *x, const double *t, size_t n, const SolveState *st, int direct, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(finish_fixed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, t, n, st, direct);
     return hipGetLastError();
 }
 

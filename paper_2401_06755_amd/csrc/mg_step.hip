@@ -34,6 +34,7 @@
 // curvature div n of Eq. surface-tension-k, the pressure of Eq. ph_disc has the
 // physical Laplace jump across a drop and gradient -s_t, so s_t enters the
 // predictor as +f(s_t; w_m).
+#include "mg_async.h"
 #include "mg_internal.h"
 
 #include <cmath>
@@ -1203,6 +1204,12 @@ struct nn4mg_stepper {
     double *red = nullptr;     // per-block partials of sum C, then the volume (last entry)
     int nred = 0;
     hipEvent_t ev[4]{};        // step start / end, solve start / end
+    // the step's solves are enqueued without waiting: per solve a start/end
+    // event pair and a pinned slot for its state header, read after the step
+    static constexpr int kSolves = 8;  // 1 + n_corr <= 8
+    hipEvent_t sev[2 * kSolves]{};
+    unsigned char *hdr = nullptr;
+    bool pending[kSolves]{};
 };
 
 namespace {
@@ -1228,23 +1235,53 @@ dim3 mom_grid(const Grid &g)
 }
 
 // Fixed-cycle solve of A x = b on the pressure hierarchy; the work pair
-// (b, px) is the same for every solve, so a captured cycle stays valid.
+// (b, px) is the same for every solve, so a captured cycle stays valid.  The
+// solve is enqueued with nothing waited for on the host (its status, residual
+// and time are read by collect_solves after the step); hierarchies that need
+// the host inside the solve (singular ones) take the synchronous solve.
 int pressure_solve(nn4mg_stepper *S, int slot, int cycles, nn4mg_step_info *info, float *ms_mg)
 {
+    STEP_TRY(hipEventRecord(S->sev[2 * slot], S->s), "hipEventRecord");
+    int rc = solve_fixed_enqueue(S->P, S->b, S->px, cycles, S->hdr + (size_t)slot * solve_header_bytes());
+    if (rc == NN4MG_OK) {
+        STEP_TRY(hipEventRecord(S->sev[2 * slot + 1], S->s), "hipEventRecord");
+        S->pending[slot] = true;
+        if (info) info->solves = slot + 1;
+        return NN4MG_OK;
+    }
+    if (rc != NN4MG_EINVAL) return rc;
     nn4mg_info si;
-    STEP_TRY(hipEventRecord(S->ev[2], S->s), "hipEventRecord");
-    int rc = nn4mg_solve(S->P, S->b, S->px, 0.0, cycles, 1, &si);
+    rc = nn4mg_solve(S->P, S->b, S->px, 0.0, cycles, 1, &si);
     if (rc != NN4MG_OK && rc != NN4MG_ENOTCONV) return rc;
-    STEP_TRY(hipEventRecord(S->ev[3], S->s), "hipEventRecord");
-    STEP_TRY(hipEventSynchronize(S->ev[3]), "hipEventSynchronize");
+    STEP_TRY(hipEventRecord(S->sev[2 * slot + 1], S->s), "hipEventRecord");
+    STEP_TRY(hipEventSynchronize(S->sev[2 * slot + 1]), "hipEventSynchronize");
     float ms = 0.0f;
-    STEP_TRY(hipEventElapsedTime(&ms, S->ev[2], S->ev[3]), "hipEventElapsedTime");
+    STEP_TRY(hipEventElapsedTime(&ms, S->sev[2 * slot], S->sev[2 * slot + 1]), "hipEventElapsedTime");
     *ms_mg += ms;
     if (info) {
         info->relres[slot] = si.relres;
         info->solves = slot + 1;
     }
     return NN4MG_OK;
+}
+
+// After the step's stream has drained: the status, final residual and device
+// time of every solve enqueued without waiting.
+int collect_solves(nn4mg_stepper *S, nn4mg_step_info *info, float *ms_mg)
+{
+    int status = NN4MG_OK;
+    for (int slot = 0; slot < nn4mg_stepper::kSolves; ++slot) {
+        if (!S->pending[slot]) continue;
+        S->pending[slot] = false;
+        double relres = 0.0;
+        const int rc = solve_fixed_result(S->hdr + (size_t)slot * solve_header_bytes(), &relres);
+        if (rc != NN4MG_OK && status == NN4MG_OK) status = rc;
+        float ms = 0.0f;
+        STEP_TRY(hipEventElapsedTime(&ms, S->sev[2 * slot], S->sev[2 * slot + 1]), "hipEventElapsedTime");
+        *ms_mg += ms;
+        if (info) info->relres[slot] = relres;
+    }
+    return status;
 }
 
 // sum C h^3 over the grid into S->red[S->nred] (fixed-order block partials)
@@ -1303,6 +1340,9 @@ int nn4mg_step_destroy(nn4mg_step_t S)
     if (S->red) (void)hipFree(S->red);
     for (auto &e : S->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : S->sev)
+        if (e) (void)hipEventDestroy(e);
+    if (S->hdr) (void)hipHostFree(S->hdr);
     delete S;
     return NN4MG_OK;
 }
@@ -1372,6 +1412,19 @@ int nn4mg_step_create(int nx, int ny, int nz, double h, const nn4mg_step_params 
             nn4mg_step_destroy(S);
             return hip_fail(e, "hipEventCreate");
         }
+    for (auto &ev : S->sev)
+        if ((e = hipEventCreate(&ev)) != hipSuccess) {
+            ev = nullptr;
+            nn4mg_step_destroy(S);
+            return hip_fail(e, "hipEventCreate");
+        }
+    if ((e = hipHostMalloc((void **)&S->hdr, nn4mg_stepper::kSolves * solve_header_bytes(), hipHostMallocDefault)) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        S->hdr = nullptr;
+        nn4mg_step_destroy(S);
+        return set_error(NN4MG_ENOMEM, "step solve headers: hipHostMalloc failed");
+    }
     // launch shapes of the pressure hierarchy, tuned once for this grid on the
     // stepper's own (zeroed) solve pair; every solve of the stepper uses them
     if ((e = launch_fill(S->b, n, 0.0, (hipStream_t)hip_stream)) != hipSuccess ||
@@ -1408,6 +1461,7 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     int rc;
 
     const bool quad = p.order == 2;
+    for (bool &pend : S->pending) pend = false;  // nothing left over from a step that failed midway
     STEP_TRY(hipEventRecord(S->ev[0], s), "hipEventRecord");
     if (quad) {
         hipLaunchKernelGGL(props2_kernel, bgrid, bblk, 0, s, g, P, qw, (const double *)C, S->rho, S->mu,
@@ -1498,6 +1552,7 @@ int nn4mg_step(nn4mg_step_t S, double *C, double *u, double *v, double *w, doubl
     if ((rc = enqueue_volume(S, C))) return rc;
     STEP_TRY(hipMemcpyAsync(&vol, S->red + S->nred, sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
     STEP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if ((rc = collect_solves(S, info, &ms_mg))) return rc;
     if (info) {
         float ms = 0.0f;
         STEP_TRY(hipEventElapsedTime(&ms, S->ev[0], S->ev[1]), "hipEventElapsedTime");
