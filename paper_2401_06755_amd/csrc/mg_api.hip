@@ -1739,13 +1739,16 @@ int solve_stationary(nn4mg_hier *H, const double *b, double *x, double rtol, int
 {
     int rc;
     if ((rc = nn4mg::solve_begin(H, b, x, rtol, max_cycles, fixed))) return rc;
+    StateHeader hd;
     while (true) {
         if ((rc = nn4mg::solve_enqueue_next(H, b, x))) return rc;
-        StateHeader hd;
         if ((rc = read_header(H, &hd))) return rc;
         if (nn4mg::solve_after_header(H)) break;
     }
-    return finish_solve(H, x, info, H->solve_t0);
+    // the header just read is the final one (nothing was enqueued since): finish without reading it again
+    if ((rc = finish_enqueue(H, x, hd))) return rc;
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    return finish_complete(H, info, H->solve_t0);
 }
 
 }  // namespace
