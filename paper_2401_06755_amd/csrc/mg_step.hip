@@ -424,7 +424,7 @@ __global__ __launch_bounds__(SBT) void pg_velocity_kernel(Grid g, C3 q, C3 adv, 
 // from LDS in the order load() builds them (the same arithmetic as the
 // per-cell form).  The neighbourhood re-reads that would go through L1/L2
 // (324 loads per cell) become LDS reads.
-constexpr int MT_X = 16, MT_Y = 8, MT_Z = 16;
+constexpr int MT_X = 16, MT_Y = 8, MT_Z = 8;
 constexpr int MP_X = MT_X + 2, MP_N = (MT_X + 2) * (MT_Y + 2);
 constexpr int M_NF = 12;  // p_hs, p_nh, rho, q0..2, kq0..2, st0..2
 
